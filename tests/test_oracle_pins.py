@@ -1,0 +1,412 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself:
+published test vectors, closed forms, library routines, theorems about the
+merge, special cases and invariants stated by the paper (Zhao et al., "On the
+Merge of k-NN Graph").  No GPU."""
+import numpy as np
+import pytest
+from scipy.spatial import distance as spd
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+F32_EPS = 2.0 ** -24
+
+
+# ---------------------------------------------------------------- SplitMix64
+
+def test_splitmix64_published_vector():
+    # SplitMix64 seeded with 0 (Steele, Lea, Flood 2014; the reference C
+    # generator): the first three outputs.
+    gamma = 0x9E3779B97F4A7C15
+    M = 2 ** 64 - 1
+    outs = [oracle.splitmix64((i * gamma) & M) for i in range(3)]
+    assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_hash_chain_definition():
+    # H(seed,tag,a,b,c) chains the generator over the tuple (seed ^ tag first)
+    sm = oracle.splitmix64
+    seed, tag, a, b, c = 12345, 0xB1, 7, 99, 1234567
+    h = sm(sm(sm(sm(seed ^ tag) ^ a) ^ b) ^ c)
+    assert oracle.hash5(seed, tag, a, b, c) == h
+    # the order of the tuple matters (a transposed argument changes it)
+    assert oracle.hash5(seed, tag, b, a, c) != h
+
+
+def test_draws_distinct_in_range_and_uniform():
+    N = 50
+    counts = np.zeros(N)
+    for row in range(2000):
+        d = oracle.draws(7, oracle.TAG_APPEND, row, N, -1, 10)
+        assert len(set(d.tolist())) == 10
+        assert d.min() >= 0 and d.max() < N
+        counts[d] += 1
+    # 20,000 draws over 50 values: each about 400 (chi-square sanity)
+    chi2 = np.sum((counts - 400.0) ** 2 / 400.0)
+    assert chi2 < 120  # 49 dof: p < 1e-6 beyond this
+
+
+def test_draws_skip_self_and_exhaustive():
+    for row in range(40):
+        d = oracle.draws(3, oracle.TAG_INIT, row, 40, row, 39)
+        assert sorted(d.tolist()) == [v for v in range(40) if v != row]
+        d = oracle.draws(3, oracle.TAG_INIT, row, 40, row, 12)
+        assert row not in d.tolist() and len(set(d.tolist())) == 12
+
+
+# ---------------------------------------------------------------- distances
+
+def test_closed_forms():
+    assert oracle.dist32("l2", [0, 0, 0], [3, 4, 0]) == 25.0
+    assert oracle.dist32("l1", [0, 0, 0], [3, 4, 0]) == 7.0
+    assert oracle.dist32("l2", [1, 2, 3], [1, 2, 3]) == 0.0
+    assert oracle.dist32("l1", [1, -2], [-1, 2]) == 6.0
+    assert oracle.dist32("l2", [1, -2], [-1, 2]) == 20.0
+    assert oracle.dist32("cos", [1, 0], [0, 2]) == 1.0
+    # parallel rows: 0 up to the rounding of the two norms (a few ulp of 1)
+    assert abs(oracle.dist32("cos", [1, 1], [2, 2])) < 4 * F32_EPS
+    assert oracle.dist32("cos", [1, 0], [-3, 0]) == 2.0
+    assert abs(oracle.dist32("cos", [1, 0], [1, 1]) - (1 - 1 / np.sqrt(2))) < 1e-7
+    assert oracle.norm32([3, 4]) == 5.0
+    assert oracle.dist64("l2", [0, 0], [3, 4]) == 25.0
+    assert oracle.dist64("cos", [1, 0], [0, 5]) == 1.0
+
+
+@pytest.mark.parametrize("metric,ref", [("l2", spd.sqeuclidean), ("l1", spd.cityblock),
+                                        ("cos", spd.cosine)])
+def test_fp64_matches_scipy(metric, ref):
+    g = synth.rng(11)
+    for d in (1, 3, 32, 129):
+        for _ in range(20):
+            a = g.standard_normal(d).astype(np.float32)
+            b = g.standard_normal(d).astype(np.float32)
+            want = ref(a.astype(np.float64), b.astype(np.float64))
+            got = oracle.dist64(metric, a, b)
+            assert abs(got - want) <= 1e-12 * max(1.0, abs(want))
+
+
+@pytest.mark.parametrize("metric", ["l2", "l1", "cos"])
+def test_fp32_within_error_bound_and_symmetric(metric):
+    g = synth.rng(12)
+    for d in (2, 32, 128, 960):
+        for _ in range(30):
+            a = g.standard_normal(d).astype(np.float32)
+            b = (a + 0.3 * g.standard_normal(d)).astype(np.float32)
+            d32 = oracle.dist32(metric, a, b)
+            d64 = oracle.dist64(metric, a, b)
+            assert d32 == oracle.dist32(metric, b, a)
+            if metric == "cos":
+                # absolute bound: the l2 sum of two unit-scaled rows plus norms
+                bound = (2 * d + 16) * F32_EPS * (1.0 + d64)
+                assert abs(d32 - d64) <= bound
+            else:
+                # sequential accumulation of nonnegative terms
+                assert abs(d32 - d64) <= (d + 2) * F32_EPS * d64 + 1e-30
+
+
+def test_integer_rows_are_exact():
+    # byte-valued rows: every partial sum is an integer below 2^24
+    g = synth.rng(13)
+    for _ in range(50):
+        a = g.integers(0, 256, 128).astype(np.float32)
+        b = g.integers(0, 256, 128).astype(np.float32)
+        assert oracle.dist32("l2", a, b) == oracle.dist64("l2", a, b)
+        assert oracle.dist32("l1", a, b) == oracle.dist64("l1", a, b)
+
+
+def test_cosine_small_distances_stay_accurate():
+    # the difference form keeps relative accuracy near 0 where 1 - a.b/(|a||b|)
+    # in FP32 would cancel
+    g = synth.rng(14)
+    for _ in range(20):
+        a = g.standard_normal(64)
+        b = a + 1e-3 * g.standard_normal(64)
+        a, b = a.astype(np.float32), b.astype(np.float32)
+        d64 = oracle.dist64("cos", a, b)
+        assert abs(oracle.dist32("cos", a, b) - d64) <= 1e-3 * d64
+
+
+# ---------------------------------------------------------------- graphs
+
+def _sorted_exact_by_fullsort(X, k, metric):
+    # textbook: sort all other rows by (FP64 distance, id)
+    ref = {"l2": "sqeuclidean", "l1": "cityblock", "cos": "cosine"}[metric]
+    D = spd.cdist(X.astype(np.float64), X.astype(np.float64), ref)
+    np.fill_diagonal(D, np.inf)
+    n = X.shape[0]
+    ids = np.empty((n, k), np.int64)
+    for i in range(n):
+        order = np.lexsort((np.arange(n), D[i]))
+        ids[i] = order[:k]
+    return ids
+
+
+@pytest.mark.parametrize("metric", ["l2", "l1"])
+def test_exact_graph_equals_full_sort_on_integer_data(metric):
+    # integer rows: FP32 distances are exact, so (dist, id) order is unique
+    X = synth.rng(21).integers(0, 6, size=(150, 5)).astype(np.float32)
+    ids, dist = oracle.exact_graph(X, 8, metric)
+    assert np.array_equal(ids, _sorted_exact_by_fullsort(X, 8, metric))
+
+
+def test_exact_graph_cosine_matches_full_sort_distances():
+    X = synth.rng(22).standard_normal((120, 6)).astype(np.float32)
+    ids, dist = oracle.exact_graph(X, 7, "cos")
+    ref = _sorted_exact_by_fullsort(X, 7, "cos")
+    D = spd.cdist(X.astype(np.float64), X.astype(np.float64), "cosine")
+    got = np.take_along_axis(D, ids.astype(np.int64), 1)
+    want = np.take_along_axis(D, ref, 1)
+    assert np.allclose(got, want, rtol=0, atol=1e-6)
+
+
+def _check_graph(ids, dist, X, metric, k):
+    """A k-NN graph: sorted by (dist, id), self-free, duplicate-free, ids in
+    range, and every stored distance is the canonical FP32 value."""
+    n = X.shape[0]
+    assert ids.shape == (n, k) and dist.shape == (n, k)
+    for i in range(n):
+        row, dr = ids[i], dist[i]
+        valid = row >= 0
+        assert np.all(valid[:np.sum(valid)])  # padding only at the end
+        r, dv = row[valid], dr[valid]
+        assert np.all((r >= 0) & (r < n)) and i not in r
+        assert len(set(r.tolist())) == len(r)
+        keys = list(zip(dv.tolist(), r.tolist()))
+        assert keys == sorted(keys)
+        for j in range(len(r)):
+            assert dv[j] == np.float32(oracle.dist32(metric, X[i], X[r[j]]))
+
+
+def test_bruteforce_merge_of_exact_graphs_is_exact():
+    # top-k(A u B) = top-k(top-k(A) u B): merging exact subgraphs by brute
+    # force reproduces the exact graph of S1 u S2 (Section 1)
+    g = synth.rng(31)
+    S1 = g.standard_normal((130, 8)).astype(np.float32)
+    S2 = g.standard_normal((90, 8)).astype(np.float32)
+    for metric in ("l2", "l1", "cos"):
+        G1 = oracle.exact_graph(S1, 9, metric)
+        G2 = oracle.exact_graph(S2, 9, metric)
+        ids, dist = oracle.merge_bruteforce(S1, G1, S2, G2, 9, metric)
+        E = oracle.exact_graph(np.concatenate([S1, S2]), 9, metric)
+        assert np.array_equal(ids, E[0]) and np.array_equal(dist, E[1])
+
+
+def test_bruteforce_merge_recomputes_missing_distances():
+    g = synth.rng(32)
+    S1 = g.standard_normal((60, 4)).astype(np.float32)
+    S2 = g.standard_normal((70, 4)).astype(np.float32)
+    G1 = oracle.exact_graph(S1, 6)
+    G2 = oracle.exact_graph(S2, 6)
+    # shuffle the row order of the input lists: without distances the oracle
+    # computes and sorts them itself
+    perm = synth.rng(33).permutation(6)
+    a = oracle.merge_bruteforce(S1, (G1[0][:, perm], None), S2, (G2[0][:, perm], None), 6)
+    b = oracle.merge_bruteforce(S1, G1, S2, G2, 6)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_invalid_inputs_rejected():
+    g = synth.rng(34)
+    S1 = g.standard_normal((20, 3)).astype(np.float32)
+    S2 = g.standard_normal((20, 3)).astype(np.float32)
+    G1 = oracle.exact_graph(S1, 4)
+    G2 = oracle.exact_graph(S2, 4)
+    bad = G1[0].copy()
+    bad[3, 1] = bad[3, 0]  # duplicate id in a row
+    with pytest.raises(oracle.OracleError):
+        oracle.smerge(S1, (bad, G1[1]), S2, G2, 4)
+    bad = G1[0].copy()
+    bad[5, 0] = 5  # self
+    with pytest.raises(oracle.OracleError):
+        oracle.smerge(S1, (bad, None), S2, G2, 4)
+    unsorted = G1[1].copy()
+    unsorted[2] = unsorted[2][::-1]
+    with pytest.raises(oracle.OracleError):
+        oracle.smerge(S1, (G1[0], unsorted), S2, G2, 4)
+    Z = S1.copy()
+    Z[0] = 0.0
+    with pytest.raises(oracle.OracleError):
+        oracle.smerge(Z, G1, S2, G2, 4, metric="cos")
+    with pytest.raises(oracle.OracleError):
+        oracle.smerge(S1, G1, S2, G2, 40)  # k > n - 1
+
+
+# ---------------------------------------------------------------- S-Merge / J-Merge
+
+@pytest.fixture(scope="module")
+def small_pair():
+    S1, S2 = synth.gaussian_sets(400, 300, 6, workload=41)
+    return S1, S2
+
+
+@pytest.mark.parametrize("metric", ["l2", "l1", "cos"])
+def test_smerge_output_is_a_knn_graph(small_pair, metric):
+    S1, S2 = small_pair
+    G1 = oracle.exact_graph(S1, 10, metric)
+    G2 = oracle.exact_graph(S2, 10, metric)
+    ids, dist, st = oracle.smerge(S1, G1, S2, G2, 10, metric, sample=8, seed=5)
+    X = np.concatenate([S1, S2])
+    _check_graph(ids, dist, X, metric, 10)
+    assert 1 <= st["rounds"] <= 30
+
+
+def test_smerge_same_set_members_come_from_input(small_pair):
+    # the join only compares pairs from different sets (Algorithm 1, the if
+    # of the inner loop) and the rear part returns unchanged, so the S1 ids
+    # of a final S1 row are a subset of that row of G1 (likewise for S2)
+    S1, S2 = small_pair
+    n1 = S1.shape[0]
+    G1 = oracle.exact_graph(S1, 10)
+    G2 = oracle.exact_graph(S2, 10)
+    ids, dist, _ = oracle.smerge(S1, G1, S2, G2, 10, sample=6, seed=9)
+    for i in range(ids.shape[0]):
+        row = ids[i]
+        if i < n1:
+            assert set(row[row < n1].tolist()) <= set(G1[0][i].tolist())
+        else:
+            assert set((row[row >= n1] - n1).tolist()) <= set(G2[0][i - n1].tolist())
+
+
+def test_smerge_lists_only_improve(small_pair):
+    # the output row is the top k of a superset of the input row, so each
+    # position can only get closer (Merge and Sort, last step of Algorithm 1)
+    S1, S2 = small_pair
+    G1 = oracle.exact_graph(S1, 10)
+    G2 = oracle.exact_graph(S2, 10)
+    ids, dist, _ = oracle.smerge(S1, G1, S2, G2, 10, sample=6, seed=2)
+    din = np.concatenate([G1[1], G2[1]])
+    assert np.all(dist <= din)
+
+
+def test_phi_non_increasing(small_pair):
+    # Eq. (2): phi(U^0) >= phi(U^1) >= ... >= phi(exact)
+    S1, S2 = small_pair
+    for metric in ("l2", "l1"):
+        G1 = oracle.exact_graph(S1, 10, metric)
+        G2 = oracle.exact_graph(S2, 10, metric)
+        _, _, st = oracle.smerge(S1, G1, S2, G2, 10, metric, sample=5, seed=3)
+        phi = st["phi"]
+        assert all(phi[t + 1] <= phi[t] for t in range(len(phi) - 1))
+        assert all(phi[t + 1] < phi[t] for t in range(len(phi) - 1) if st["c"][t] > 0)
+        E = oracle.exact_graph(np.concatenate([S1, S2]), 10, metric)
+        assert phi[-1] >= oracle.phi(E[1]) * (1 - 1e-6)
+
+
+def test_termination_rule(small_pair):
+    S1, S2 = small_pair
+    G1 = oracle.exact_graph(S1, 10)
+    G2 = oracle.exact_graph(S2, 10)
+    _, _, st = oracle.smerge(S1, G1, S2, G2, 10, sample=5, seed=4, max_rounds=3)
+    assert st["rounds"] == 3
+    _, _, st = oracle.smerge(S1, G1, S2, G2, 10, sample=5, seed=4)
+    assert st["rounds"] < 30 and st["c"][-1] == 0 and all(c > 0 for c in st["c"][:-1])
+    n = S1.shape[0] + S2.shape[0]
+    _, _, st = oracle.smerge(S1, G1, S2, G2, 10, sample=5, seed=4, delta=0.01)
+    assert st["c"][-1] <= 0.01 * n * 10
+    assert all(c > 0.01 * n * 10 for c in st["c"][:-1])
+
+
+def test_separated_sets_return_the_inputs():
+    # S1 and S2 far apart: no cross pair can enter a list, so the result is
+    # G1 and G2 unchanged (ids of S2 offset by n1)
+    g = synth.rng(51)
+    S1 = g.standard_normal((200, 4)).astype(np.float32)
+    S2 = (g.standard_normal((150, 4)) + 1000.0).astype(np.float32)
+    n1 = S1.shape[0]
+    for metric in ("l2", "l1"):
+        G1 = oracle.exact_graph(S1, 8, metric)
+        G2 = oracle.exact_graph(S2, 8, metric)
+        ids, dist, _ = oracle.smerge(S1, G1, S2, G2, 8, metric, sample=8, seed=1)
+        assert np.array_equal(ids[:n1], G1[0]) and np.array_equal(ids[n1:], G2[0] + n1)
+        assert np.array_equal(dist[:n1], G1[1]) and np.array_equal(dist[n1:], G2[1])
+
+
+def test_exact_graph_recall_is_one():
+    X = synth.rng(61).integers(0, 4, size=(200, 3)).astype(np.float32)  # many ties
+    ids, _ = oracle.exact_graph(X, 10)
+    r_thr, _ = oracle.recall_at(ids, X, np.arange(200), 10)
+    assert r_thr == 1.0
+
+
+def test_recall_counts_misses():
+    X = synth.rng(62).standard_normal((100, 3)).astype(np.float32)
+    ids, _ = oracle.exact_graph(X, 10)
+    bad = ids.copy()
+    bad[:, 9] = ids[:, 0]  # duplicate replaces the 10th neighbour: 1 miss
+    bad[:, 9] = np.array([(i + 50) % 100 for i in range(100)])
+    r, _ = oracle.recall_at(bad, X, np.arange(100), 10)
+    assert r < 1.0 and r >= 0.89
+
+
+def test_full_sampling_smerge_reaches_high_recall():
+    # low-dimensional sets with full sampling: hill climbing from good
+    # subgraphs recovers almost the whole exact graph (Section 3.4)
+    recalls = []
+    for seed in range(10):
+        S1, S2 = synth.gaussian_sets(150, 150, 3, workload=70 + seed)
+        G1 = oracle.exact_graph(S1, 8)
+        G2 = oracle.exact_graph(S2, 8)
+        ids, _, _ = oracle.smerge(S1, G1, S2, G2, 8, sample=24, seed=seed)
+        X = np.concatenate([S1, S2])
+        recalls.append(oracle.recall_at(ids, X, np.arange(300), 8)[0])
+    assert np.mean(recalls) >= 0.99
+
+
+def test_jmerge_structure_and_base_subset():
+    S1, S2 = synth.gaussian_sets(300, 200, 5, workload=81)
+    nb = S1.shape[0]
+    G = oracle.exact_graph(S1, 10)
+    ids, dist, st = oracle.jmerge(S1, G, S2, 10, sample=8, seed=7)
+    X = np.concatenate([S1, S2])
+    _check_graph(ids, dist, X, "l2", 10)
+    # base-base pairs are never joined (Algorithm 2): base ids of a base row
+    # come from its input list, and base rows only improve
+    for i in range(nb):
+        row = ids[i]
+        assert set(row[row < nb].tolist()) <= set(G[0][i].tolist())
+    assert np.all(dist[:nb] <= G[1])
+    phi = st["phi"]
+    assert all(phi[t + 1] <= phi[t] for t in range(len(phi) - 1))
+
+
+def test_jmerge_initialisation_without_rounds():
+    # max_rounds = 0: raw rows hold k distinct random non-self samples with
+    # canonical distances, sorted; base rows are the top k of their input
+    # list and k - k1 appended raw samples
+    S1, S2 = synth.gaussian_sets(50, 40, 3, workload=82)
+    G = oracle.exact_graph(S1, 6)
+    ids, dist, st = oracle.jmerge(S1, G, S2, 6, sample=4, seed=8, max_rounds=0)
+    X = np.concatenate([S1, S2])
+    _check_graph(ids, dist, X, "l2", 6)
+    assert st["rounds"] == 0
+    assert st["evals"] == 50 * 3 + 40 * 6
+
+
+def test_nn_descent_from_empty_base():
+    # J-Merge with an empty base set is NN-Descent on the raw set
+    X = synth.rng(83).standard_normal((400, 3)).astype(np.float32)
+    ids, dist, st = oracle.jmerge(None, None, X, 8, sample=8, seed=1)
+    _check_graph(ids, dist, X, "l2", 8)
+    assert oracle.recall_at(ids, X, np.arange(400), 8)[0] > 0.97
+
+
+def test_smerge_is_deterministic_and_seeded(small_pair):
+    S1, S2 = small_pair
+    G1 = oracle.exact_graph(S1, 10)
+    G2 = oracle.exact_graph(S2, 10)
+    a = oracle.smerge(S1, G1, S2, G2, 10, sample=4, seed=11)
+    b = oracle.smerge(S1, G1, S2, G2, 10, sample=4, seed=11)
+    c = oracle.smerge(S1, G1, S2, G2, 10, sample=4, seed=12)
+    assert np.array_equal(a[0], b[0]) and a[2] == b[2]
+    assert a[2]["c"] != c[2]["c"]
+
+
+def test_odd_k_and_keep_ratio():
+    S1, S2 = synth.gaussian_sets(120, 100, 4, workload=84)
+    for k, r in ((7, 0.5), (9, 0.2), (6, 1.0), (5, 0.0)):
+        G1 = oracle.exact_graph(S1, k)
+        G2 = oracle.exact_graph(S2, k)
+        ids, dist, _ = oracle.smerge(S1, G1, S2, G2, k, keep_ratio=r, sample=5, seed=1)
+        _check_graph(ids, dist, np.concatenate([S1, S2]), "l2", k)
