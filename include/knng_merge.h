@@ -1,0 +1,220 @@
+/*
+ * knng_merge.h -- C ABI of libknngmerge.so, k-NN graph merge on one MI355X.
+ *
+ * Implements the two merge problems of Zhao, Wang, Lin and Ngo, "On the Merge
+ * of k-NN Graph":
+ *   knng_merge   symmetric merge, S-Merge (Section 3.1, Algorithm 1): two
+ *                built graphs G1 of S1 and G2 of S2 become the graph of
+ *                S1 u S2;
+ *   knng_expand  joint merge, J-Merge (Section 3.2, Algorithm 2): a built
+ *                graph G of S absorbs a raw set that has no graph yet;
+ *   knng_merge_bruteforce   the exhaustive cross comparison that Section 1
+ *                describes as the naive way to merge (deterministic);
+ *   knng_exact_graph        the exact k-NN graph by brute force (Section 1's
+ *                definition of G[i]), used to build inputs.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers inside knng_set / knng_graph are DEVICE pointers (HIP device
+ *     memory of the current device).  A host pointer is rejected with
+ *     KNNG_EINVAL.  Row-major layouts: set rows are n x d fp32; graph rows are
+ *     n x k int32 ids and n x k fp32 distances.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     The merges read a 4-byte counter back to the host once per round and
+ *     therefore synchronise the stream; results are valid on return.
+ *   - The caller owns every buffer.  Inputs are never written.  Device
+ *     scratch memory is the caller's `workspace` of at least the bytes that
+ *     the matching *_workspace_size call returns; nothing is allocated on
+ *     the device by these calls.  Outputs must not alias inputs.
+ *   - Distances: l2 is the SQUARED Euclidean distance, l1 the sum of
+ *     absolute differences, cosine is 1 - cos.  Smaller is closer.  Stored
+ *     distances are canonical FP32 values (ascending-coordinate
+ *     accumulation with fused multiply-add; see the design notes).
+ *   - Output rows are sorted by (distance, id) ascending, hold no self and
+ *     no duplicate ids; ids are global (rows of the first set first, then
+ *     rows of the second).  When fewer than k neighbours exist a row is
+ *     padded with id -1 and distance +inf.
+ *   - Errors: no exception or abort crosses the ABI.  The return code says
+ *     what failed and knng_last_error() (thread-local, valid until the next
+ *     call on the same thread) says why.  On error the output content is
+ *     unspecified and inputs are untouched.
+ */
+#ifndef KNNG_MERGE_H
+#define KNNG_MERGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KNNG_VERSION 10000 /* major*10000 + minor*100 + patch */
+
+typedef enum {
+    KNNG_OK = 0,
+    KNNG_EINVAL = 1,  /* bad argument or invalid input data */
+    KNNG_ENOMEM = 2,  /* workspace smaller than required */
+    KNNG_EDEVICE = 3, /* a HIP call failed; see knng_last_error() */
+} knng_status;
+
+typedef enum {
+    KNNG_L2 = 0,     /* squared Euclidean */
+    KNNG_COSINE = 1, /* 1 - cos; zero rows are rejected */
+    KNNG_L1 = 2,     /* sum of |a_t - b_t| */
+} knng_metric;
+
+typedef enum {
+    /* every joined pair evaluated in canonical FP32 */
+    KNNG_FP32 = 0,
+    /* block distances in BF16 on MFMA with FP32 accumulation, screened with a
+     * bound that never drops a pair the FP32 path would insert; pairs that
+     * pass are rescored in canonical FP32 before insertion (l2 and cosine;
+     * l1 has no MFMA form and runs the FP32 path) */
+    KNNG_BF16_RESCORE = 1,
+} knng_precision;
+
+/* opts.flags */
+#define KNNG_FLAG_PROFILE 1u /* time each phase with HIP events (stats.ms_*) */
+
+/*
+ * Parameters of the merges.
+ *   keep_ratio  r = k1/k, the share of each input list kept by Divide
+ *               (Section 5.2 ablation; Sections 3.1-3.2 use 1/2).
+ *               k1 = floor(r*k); the other k-k1 slots receive random samples.
+ *   sample      s: NEW entries sampled per list per round, and the size of
+ *               each sampled reverse list (NN-Descent sampling, which
+ *               Section 3.1 invokes by citation).  1..32.
+ *   delta       the repeat loop of Algorithms 1-2 stops when the number of
+ *               entries inserted in a round is <= delta*n*k (0 = until no
+ *               update, as the paper states).
+ *   max_rounds  cap on rounds (the paper has none).
+ *   seed        seed of the counter-based random stream (SplitMix64).
+ *   precision   knng_precision.
+ *   flags       KNNG_FLAG_*.
+ * Constraints: 3*sample + k <= 160, 1 <= k <= 64.
+ */
+typedef struct {
+    float keep_ratio;
+    int32_t sample;
+    float delta;
+    int32_t max_rounds;
+    uint64_t seed;
+    int32_t precision;
+    uint32_t flags;
+} knng_opts;
+
+/* a point set: n rows of d fp32 values, row-major, on the device */
+typedef struct {
+    int64_t n;
+    int32_t d;
+    const float *x;
+} knng_set;
+
+/*
+ * A k-NN graph: n rows of k entries.  As an INPUT, ids are LOCAL to the
+ * graph's own set (0..n-1), rows must be duplicate-free and self-free, and
+ * `dist` may be NULL (distances are then computed canonically and each row is
+ * sorted) or must hold each row sorted by (distance, id).  Given distances
+ * are trusted as they are.  As an OUTPUT, ids are global and both arrays are
+ * written.
+ */
+typedef struct {
+    int64_t n;
+    int32_t k;
+    int32_t *ids;
+    float *dist;
+} knng_graph;
+
+#define KNNG_STATS_ROUNDS 64
+
+/* Counters of one merge (all counts are exact, taken on the device). */
+typedef struct {
+    int32_t rounds;              /* rounds of the repeat loop run */
+    int32_t max_group;           /* largest neighbourhood seen (|new|+|old|) */
+    int64_t evals;               /* C of the scanning rate: distance evaluations
+                                    of Append/Initialize and of the local joins */
+    int64_t rescored;            /* BF16 path: pairs re-evaluated in FP32 */
+    int64_t updates[KNNG_STATS_ROUNDS];  /* c: entries inserted and kept, per round */
+    int64_t pairs[KNNG_STATS_ROUNDS];    /* joined pairs per round */
+    int64_t gathered[KNNG_STATS_ROUNDS]; /* neighbourhood members staged per round */
+    /* device time per phase in ms (KNNG_FLAG_PROFILE only) */
+    double ms_prep, ms_init, ms_sample, ms_reverse, ms_join, ms_final;
+    int32_t join_launches;
+    int32_t reserved;
+} knng_stats;
+
+/* fills *o with keep_ratio 0.5, sample 10, delta 0, max_rounds 30, seed 0,
+ * precision FP32, flags 0 */
+void knng_opts_default(knng_opts *o);
+
+/*
+ * S-Merge (Algorithm 1): Divide G1 and G2 (first k1 entries kept, the rear
+ * set aside), Append k-k1 distinct random samples of the other set to every
+ * list, iterate the cross-set local join (only pairs from different sets are
+ * compared), then Merge and Sort each list with its set-aside rear part.
+ *   S1, G1: n1 rows; G1->k = kin1 >= k1.   S2, G2: n2 rows; kin2 >= k1.
+ *   k: output list size, 1..min(64, n1+n2-1).
+ *   out: n1+n2 rows, k columns; S1 rows first, S2 ids offset by n1.
+ *   stats: may be NULL.
+ * Returns KNNG_EINVAL for bad sizes/options, ids out of range, duplicate or
+ * self ids, unsorted given rows, non-finite values or (cosine) zero rows.
+ */
+knng_status knng_merge(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
+                       const knng_graph *G2, int32_t k, knng_metric metric,
+                       const knng_opts *opts, knng_graph *out, void *workspace,
+                       size_t workspace_bytes, void *stream, knng_stats *stats);
+
+size_t knng_merge_workspace_size(int64_t n1, int64_t n2, int32_t d, int32_t k, int32_t kin1,
+                                 int32_t kin2, knng_metric metric, const knng_opts *opts);
+
+/*
+ * J-Merge (Algorithm 2): Divide G (base set S, n_b rows), Append k-k1 random
+ * raw samples to every base list, Initialize every raw row with k random
+ * samples of S u raw (self excluded), iterate the local join over pairs that
+ * are not both from S (cross pairs and raw-raw pairs), then Merge and Sort
+ * the base rows with their set-aside rear parts.
+ *   S may have n = 0 (G ignored): the call is then an NN-Descent build of
+ *   the raw set.  out: n_b + n_raw rows, base rows first.
+ */
+knng_status knng_expand(const knng_set *S, const knng_graph *G, const knng_set *raw, int32_t k,
+                        knng_metric metric, const knng_opts *opts, knng_graph *out,
+                        void *workspace, size_t workspace_bytes, void *stream,
+                        knng_stats *stats);
+
+size_t knng_expand_workspace_size(int64_t n_base, int64_t n_raw, int32_t d, int32_t k,
+                                  int32_t kin, knng_metric metric, const knng_opts *opts);
+
+/*
+ * Brute-force cross merge (Section 1): row i of S1 becomes the top k of
+ * G1[i] and every (m(x_i, y_j), n1+j); S2 rows likewise against S1.
+ * Deterministic: equal to the exact result in canonical FP32 with ties broken
+ * by the smaller id.  Arguments as in knng_merge (no options).
+ */
+knng_status knng_merge_bruteforce(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
+                                  const knng_graph *G2, int32_t k, knng_metric metric,
+                                  knng_graph *out, void *workspace, size_t workspace_bytes,
+                                  void *stream);
+
+size_t knng_bruteforce_workspace_size(int64_t n1, int64_t n2, int32_t d, int32_t k,
+                                      int32_t kin1, int32_t kin2, knng_metric metric);
+
+/*
+ * Exact k-NN graph of S (Section 1): each row's k smallest (distance, id)
+ * over all other rows.  out: S->n rows, k columns, ids local to S.
+ */
+knng_status knng_exact_graph(const knng_set *S, int32_t k, knng_metric metric, knng_graph *out,
+                             void *workspace, size_t workspace_bytes, void *stream);
+
+size_t knng_exact_graph_workspace_size(int64_t n, int32_t d, int32_t k, knng_metric metric);
+
+/* thread-local text of the last error ("" after success) */
+const char *knng_last_error(void);
+
+/* KNNG_VERSION of the loaded library */
+int knng_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNNG_MERGE_H */

@@ -1,0 +1,644 @@
+// knng_api.hip -- the C ABI of libknngmerge (declared in include/knng_merge.h):
+// argument checking, workspace carving and the host side of the merges.
+//
+// Host orchestration of Algorithms 1 and 2 (Zhao et al., "On the Merge of
+// k-NN Graph", Sections 3.1-3.2): Divide/Append (or Initialize), then the
+// repeat loop -- per round: sampling, Reverse(G), local join -- until the
+// number of surviving insertions c drops to delta*n*k, then Merge and Sort.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/knng_merge.h"
+#include "knng_common.h"
+#include "knng_internal.h"
+
+using namespace knng;
+
+namespace {
+
+thread_local std::string g_err;
+
+knng_status fail(knng_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+knng_status ok()
+{
+    g_err.clear();
+    return KNNG_OK;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(KNNG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+int pad4(int d) { return (d + 3) / 4 * 4; }
+int pad32(int d) { return (d + 31) / 32 * 32; }
+
+// bump allocator over the caller's workspace; with base == nullptr it only
+// measures
+struct Carve {
+    uint8_t *base;
+    size_t off = 0;
+    explicit Carve(void *b) : base((uint8_t *)b) {}
+    template <class T> T *take(size_t count)
+    {
+        off = (off + 255) / 256 * 256;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Layout {
+    uint64_t *ctr;
+    float *x, *norm, *sq;
+    uint16_t *xb;
+    uint64_t *gin, *L, *worst, *rnew, *rold;
+    int32_t *new_f, *old_f, *cnt_f;
+    int dp, db, gstride;
+};
+
+bool uses_bf16(knng_metric m, const knng_opts *o)
+{
+    return o && o->precision == KNNG_BF16_RESCORE && m != KNNG_L1;
+}
+
+// one layout for S-Merge and J-Merge: n rows, input lists on `n_list` rows
+void carve_merge(Carve &c, Layout &w, int64_t n, int64_t n_list, int d, int k, int gstride, int s,
+                 knng_metric m, bool bf16)
+{
+    w.dp = pad4(d);
+    w.db = pad32(d);
+    w.gstride = gstride;
+    w.ctr = c.take<uint64_t>(C_WORDS);
+    w.x = c.take<float>((size_t)n * w.dp);
+    w.norm = m == KNNG_COSINE ? c.take<float>(n) : nullptr;
+    w.xb = bf16 ? c.take<uint16_t>((size_t)n * w.db) : nullptr;
+    w.sq = bf16 ? c.take<float>(n) : nullptr;
+    w.gin = c.take<uint64_t>((size_t)(n_list > 0 ? n_list : 1) * (gstride > 0 ? gstride : 1));
+    w.L = c.take<uint64_t>((size_t)n * k);
+    w.worst = c.take<uint64_t>(n);
+    w.new_f = c.take<int32_t>((size_t)n * s);
+    w.old_f = c.take<int32_t>((size_t)n * k);
+    w.cnt_f = c.take<int32_t>((size_t)n * 2);
+    w.rnew = c.take<uint64_t>((size_t)n * s);
+    w.rold = c.take<uint64_t>((size_t)n * s);
+}
+
+bool is_device_ptr(const void *p)
+{
+    if (!p)
+        return false;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+knng_status check_set(const knng_set *S, const char *name, bool allow_empty = false)
+{
+    if (!S)
+        return fail(KNNG_EINVAL, "%s is NULL", name);
+    if (S->n < (allow_empty ? 0 : 1) || S->n >= (1ll << 30) - 64)
+        return fail(KNNG_EINVAL, "%s->n = %lld out of range", name, (long long)S->n);
+    if (S->d < 1 || S->d > 65536)
+        return fail(KNNG_EINVAL, "%s->d = %d out of range", name, S->d);
+    if (S->n > 0 && !is_device_ptr(S->x))
+        return fail(KNNG_EINVAL, "%s->x is not device memory", name);
+    return KNNG_OK;
+}
+
+knng_status check_graph_in(const knng_graph *G, int64_t n, const char *name, int kmin)
+{
+    if (!G)
+        return fail(KNNG_EINVAL, "%s is NULL", name);
+    if (G->n != n)
+        return fail(KNNG_EINVAL, "%s->n = %lld, expected %lld", name, (long long)G->n,
+                    (long long)n);
+    if (G->k < kmin || G->k > MAX_K || G->k > n - 1)
+        return fail(KNNG_EINVAL, "%s->k = %d out of range [%d, min(64, n-1)]", name, G->k, kmin);
+    if (G->k > 0 && !is_device_ptr(G->ids))
+        return fail(KNNG_EINVAL, "%s->ids is not device memory", name);
+    if (G->dist && !is_device_ptr(G->dist))
+        return fail(KNNG_EINVAL, "%s->dist is not device memory", name);
+    return KNNG_OK;
+}
+
+knng_status check_out(const knng_graph *out, int64_t n, int k)
+{
+    if (!out)
+        return fail(KNNG_EINVAL, "out is NULL");
+    if (out->n != n || out->k != k)
+        return fail(KNNG_EINVAL, "out is %lld x %d, expected %lld x %d", (long long)out->n,
+                    out->k, (long long)n, k);
+    if (!is_device_ptr(out->ids) || !is_device_ptr(out->dist))
+        return fail(KNNG_EINVAL, "out->ids / out->dist must be device memory");
+    return KNNG_OK;
+}
+
+knng_status check_opts(const knng_opts *o, int k)
+{
+    if (!o)
+        return fail(KNNG_EINVAL, "opts is NULL");
+    if (!(o->keep_ratio >= 0.0f && o->keep_ratio <= 1.0f))
+        return fail(KNNG_EINVAL, "keep_ratio %g not in [0, 1]", (double)o->keep_ratio);
+    if (o->sample < 1 || o->sample > MAX_S)
+        return fail(KNNG_EINVAL, "sample %d not in [1, %d]", o->sample, MAX_S);
+    if (!(o->delta >= 0.0f))
+        return fail(KNNG_EINVAL, "delta must be >= 0");
+    if (o->max_rounds < 0)
+        return fail(KNNG_EINVAL, "max_rounds must be >= 0");
+    if (o->precision != KNNG_FP32 && o->precision != KNNG_BF16_RESCORE)
+        return fail(KNNG_EINVAL, "unknown precision %d", o->precision);
+    if (3 * o->sample + k > MAX_G)
+        return fail(KNNG_EINVAL, "3*sample + k = %d exceeds %d", 3 * o->sample + k, MAX_G);
+    return KNNG_OK;
+}
+
+knng_status check_metric(knng_metric m)
+{
+    if (m != KNNG_L2 && m != KNNG_COSINE && m != KNNG_L1)
+        return fail(KNNG_EINVAL, "unknown metric %d", (int)m);
+    return KNNG_OK;
+}
+
+const char *err_text(uint64_t bits)
+{
+    if (bits & ERR_NONFINITE)
+        return "input rows hold a non-finite value";
+    if (bits & ERR_ZERO_NORM)
+        return "cosine metric: an input row has zero norm";
+    if (bits & ERR_ID_RANGE)
+        return "input graph id out of range";
+    if (bits & ERR_SELF)
+        return "input graph row lists itself";
+    if (bits & ERR_DUP)
+        return "input graph row holds a duplicate id";
+    if (bits & ERR_UNSORTED)
+        return "input graph row not sorted by (distance, id)";
+    if (bits & ERR_BAD_DIST)
+        return "input graph distance negative or not finite";
+    if (bits & ERR_SPIN)
+        return "internal: list insert exceeded its retry budget";
+    if (bits & ERR_GROUP)
+        return "internal: neighbourhood exceeded the kernel bound";
+    return "unknown device error";
+}
+
+// reads the counter block; returns the error bits
+knng_status read_ctr(const uint64_t *dctr, uint64_t *h, hipStream_t st)
+{
+    HIP_TRY(hipMemcpyAsync(h, dctr, sizeof(uint64_t) * C_WORDS, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return KNNG_OK;
+}
+
+// phase timing with HIP events (KNNG_FLAG_PROFILE)
+struct Prof {
+    bool on;
+    hipStream_t st;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+    hipEvent_t cur = nullptr;
+    int cur_phase = -1;
+    void begin(int phase)
+    {
+        if (!on)
+            return;
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return;
+        (void)hipEventRecord(e, st);
+        cur = e;
+        cur_phase = phase;
+    }
+    void end()
+    {
+        if (!on || !cur)
+            return;
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return;
+        (void)hipEventRecord(e, st);
+        ev.push_back({cur_phase, {cur, e}});
+        cur = nullptr;
+    }
+    void collect(knng_stats *s)
+    {
+        if (!on)
+            return;
+        (void)hipStreamSynchronize(st);
+        for (auto &p : ev) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, p.second.first, p.second.second);
+            if (s) {
+                double *slot[] = {&s->ms_prep, &s->ms_init, &s->ms_sample, &s->ms_reverse,
+                                  &s->ms_join, &s->ms_final};
+                *slot[p.first] += ms;
+                if (p.first == 4)
+                    s->join_launches++;
+            }
+            (void)hipEventDestroy(p.second.first);
+            (void)hipEventDestroy(p.second.second);
+        }
+        ev.clear();
+    }
+    ~Prof()
+    {
+        for (auto &p : ev) {
+            (void)hipEventDestroy(p.second.first);
+            (void)hipEventDestroy(p.second.second);
+        }
+        if (cur)
+            (void)hipEventDestroy(cur);
+    }
+};
+enum { PH_PREP = 0, PH_INIT, PH_SAMPLE, PH_REVERSE, PH_JOIN, PH_FINAL };
+
+// layout + input preparation shared by both merges.  Rows [0, n1) come from
+// set A (input lists of A on rows [0, n1)), rows [n1, n) from set B (input
+// lists only when listsB).
+knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
+                    const knng_graph *GB, knng_metric metric, bool bf16, const Layout &w,
+                    int64_t n1, int64_t n, hipStream_t st, Rows &R)
+{
+    const int d = B->d;
+    HIP_TRY(launch_zero_counters(w.ctr, C_WORDS, st));
+    HIP_TRY(launch_pack(A->n ? A->x : nullptr, n1, B->x, n - n1, d, w.dp, w.x, bf16 ? w.db : 0,
+                        w.xb, w.ctr, st));
+    R.x = w.x;
+    R.norm = w.norm;
+    R.xb = w.xb;
+    R.sq = w.sq;
+    R.n = n;
+    R.d = d;
+    R.dp = w.dp;
+    R.db = w.db;
+    if (w.norm || w.sq)
+        HIP_TRY(launch_norms(w.x, n, w.dp, w.norm, w.sq, w.xb, w.db, metric == KNNG_COSINE,
+                             w.ctr, st));
+    uint64_t h[C_WORDS];
+    knng_status s = read_ctr(w.ctr, h, st);
+    if (s != KNNG_OK)
+        return s;
+    if (h[C_ERR])
+        return fail(KNNG_EINVAL, "%s", err_text(h[C_ERR]));
+    if (GA && n1 > 0)
+        HIP_TRY(launch_prep_input(R, metric, 0, n1, 0, n1, GA->ids, GA->dist, GA->k, w.gstride,
+                                  w.gin, w.ctr, st));
+    if (GB)
+        HIP_TRY(launch_prep_input(R, metric, n1, n - n1, n1, n - n1, GB->ids, GB->dist, GB->k,
+                                  w.gstride, w.gin, w.ctr, st));
+    s = read_ctr(w.ctr, h, st);
+    if (s != KNNG_OK)
+        return s;
+    if (h[C_ERR])
+        return fail(KNNG_EINVAL, "%s", err_text(h[C_ERR]));
+    return KNNG_OK;
+}
+
+// the repeat loop and Merge and Sort, shared by S-Merge and J-Merge
+knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool bf16,
+                      const knng_opts *o, int64_t n, int64_t n1, int k, int k1, int joint,
+                      int64_t rows_with_rear, knng_graph *out, hipStream_t st, knng_stats *stats,
+                      Prof &prof)
+{
+    InitArgs ia;
+    ia.L = w.L;
+    ia.gin = w.gin;
+    ia.kin = w.gstride;
+    ia.k = k;
+    ia.k1 = k1;
+    ia.n = n;
+    ia.n1 = n1;
+    ia.joint = joint;
+    ia.seed = o->seed;
+    ia.ctr = w.ctr;
+    prof.begin(PH_INIT);
+    HIP_TRY(launch_init(R, (int)metric, ia, st));
+    prof.end();
+
+    RoundArgs a;
+    a.L = w.L;
+    a.worst = w.worst;
+    a.new_f = w.new_f;
+    a.old_f = w.old_f;
+    a.cnt_f = w.cnt_f;
+    a.rnew = w.rnew;
+    a.rold = w.rold;
+    a.ctr = w.ctr;
+    a.n = n;
+    a.n1 = n1;
+    a.k = k;
+    a.s = o->sample;
+    a.joint = joint;
+    a.seed = o->seed;
+    const double thr = (double)o->delta * (double)n * (double)k;
+    uint64_t h[C_WORDS];
+    int rounds = 0;
+    for (int t = 0;; t++) {
+        const bool last = t == o->max_rounds;
+        a.round = t;
+        prof.begin(PH_SAMPLE);
+        if (!last)
+            HIP_TRY(launch_sample(a, st));  // also counts the FRESH entries of round t-1
+        else
+            HIP_TRY(launch_count_fresh(a, st));
+        prof.end();
+        if (t > 0) {
+            knng_status s = read_ctr(w.ctr, h, st);
+            if (s != KNNG_OK)
+                return s;
+            if (h[C_ERR])
+                return fail(KNNG_EDEVICE, "%s", err_text(h[C_ERR]));
+            if (stats && t - 1 < KNNG_STATS_ROUNDS) {
+                stats->updates[t - 1] = (int64_t)h[C_FRESH];
+                stats->pairs[t - 1] = (int64_t)h[C_PAIRS];
+                stats->gathered[t - 1] = (int64_t)h[C_GATHER];
+            }
+            rounds = t;
+            if ((double)h[C_FRESH] <= thr)
+                break;
+        }
+        if (last)
+            break;
+        HIP_TRY(launch_zero_counters(w.ctr, C_ROUND_WORDS, st));
+        prof.begin(PH_REVERSE);
+        HIP_TRY(launch_reverse(a, st));
+        prof.end();
+        prof.begin(PH_JOIN);
+        HIP_TRY(launch_join(R, (int)metric, bf16 ? 1 : 0, a, st));
+        prof.end();
+    }
+    prof.begin(PH_FINAL);
+    HIP_TRY(launch_final(w.L, k, w.gin, w.gstride, k1, rows_with_rear, n, out->ids, out->dist,
+                         st));
+    prof.end();
+    knng_status s = read_ctr(w.ctr, h, st);
+    if (s != KNNG_OK)
+        return s;
+    if (h[C_ERR])
+        return fail(KNNG_EDEVICE, "%s", err_text(h[C_ERR]));
+    if (stats) {
+        stats->rounds = rounds;
+        stats->evals = (int64_t)h[C_EVALS];
+        stats->rescored = (int64_t)h[C_RESCORE];
+        stats->max_group = (int32_t)h[C_MAXG];
+    }
+    prof.collect(stats);
+    return ok();
+}
+
+int keep_count(const knng_opts *o, int k) { return (int)floorf(o->keep_ratio * (float)k); }
+
+} // namespace
+
+extern "C" {
+
+void knng_opts_default(knng_opts *o)
+{
+    if (!o)
+        return;
+    o->keep_ratio = 0.5f;
+    o->sample = 10;
+    o->delta = 0.0f;
+    o->max_rounds = 30;
+    o->seed = 0;
+    o->precision = KNNG_FP32;
+    o->flags = 0;
+}
+
+const char *knng_last_error(void) { return g_err.c_str(); }
+
+int knng_version(void) { return KNNG_VERSION; }
+
+size_t knng_merge_workspace_size(int64_t n1, int64_t n2, int32_t d, int32_t k, int32_t kin1,
+                                 int32_t kin2, knng_metric metric, const knng_opts *opts)
+{
+    if (n1 < 1 || n2 < 1 || d < 1 || k < 1 || !opts)
+        return 0;
+    Carve c(nullptr);
+    Layout w;
+    carve_merge(c, w, n1 + n2, n1 + n2, d, k, kin1 > kin2 ? kin1 : kin2, opts->sample, metric,
+                uses_bf16(metric, opts));
+    return c.off + 256;
+}
+
+size_t knng_expand_workspace_size(int64_t n_base, int64_t n_raw, int32_t d, int32_t k,
+                                  int32_t kin, knng_metric metric, const knng_opts *opts)
+{
+    if (n_base < 0 || n_raw < 1 || d < 1 || k < 1 || !opts)
+        return 0;
+    Carve c(nullptr);
+    Layout w;
+    carve_merge(c, w, n_base + n_raw, n_base, d, k, n_base > 0 ? kin : 0, opts->sample, metric,
+                uses_bf16(metric, opts));
+    return c.off + 256;
+}
+
+knng_status knng_merge(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
+                       const knng_graph *G2, int32_t k, knng_metric metric,
+                       const knng_opts *opts, knng_graph *out, void *workspace,
+                       size_t workspace_bytes, void *stream, knng_stats *stats)
+{
+    knng_status s;
+    if ((s = check_metric(metric)) || (s = check_set(S1, "S1")) || (s = check_set(S2, "S2")) ||
+        (s = check_opts(opts, k)))
+        return s;
+    if (S1->d != S2->d)
+        return fail(KNNG_EINVAL, "S1->d = %d differs from S2->d = %d", S1->d, S2->d);
+    const int64_t n1 = S1->n, n2 = S2->n, n = n1 + n2;
+    if (k < 1 || k > MAX_K || k > n - 1)
+        return fail(KNNG_EINVAL, "k = %d out of range [1, min(64, n1+n2-1)]", k);
+    const int k1 = keep_count(opts, k);
+    if ((s = check_graph_in(G1, n1, "G1", k1)) || (s = check_graph_in(G2, n2, "G2", k1)) ||
+        (s = check_out(out, n, k)))
+        return s;
+    const bool bf16 = uses_bf16(metric, opts);
+    const int gstride = G1->k > G2->k ? G1->k : G2->k;
+    const size_t need = knng_merge_workspace_size(n1, n2, S1->d, k, G1->k, G2->k, metric, opts);
+    if (!workspace || workspace_bytes < need)
+        return fail(KNNG_ENOMEM, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    if (!is_device_ptr(workspace))
+        return fail(KNNG_EINVAL, "workspace is not device memory");
+    hipStream_t st = (hipStream_t)stream;
+    if (stats)
+        memset(stats, 0, sizeof *stats);
+    Carve c(workspace);
+    Layout w;
+    carve_merge(c, w, n, n, S1->d, k, gstride, opts->sample, metric, bf16);
+    Prof prof{(opts->flags & KNNG_FLAG_PROFILE) != 0, st};
+    Rows R;
+    prof.begin(PH_PREP);
+    s = prepare(S1, G1, S2, G2, metric, bf16, w, n1, n, st, R);
+    prof.end();
+    if (s != KNNG_OK)
+        return s;
+    return run_merge(R, w, metric, bf16, opts, n, n1, k, k1, 0, n, out, st, stats, prof);
+}
+
+knng_status knng_expand(const knng_set *S, const knng_graph *G, const knng_set *raw, int32_t k,
+                        knng_metric metric, const knng_opts *opts, knng_graph *out,
+                        void *workspace, size_t workspace_bytes, void *stream,
+                        knng_stats *stats)
+{
+    knng_status s;
+    if ((s = check_metric(metric)) || (s = check_set(S, "S", true)) ||
+        (s = check_set(raw, "raw")) || (s = check_opts(opts, k)))
+        return s;
+    if (S->n > 0 && S->d != raw->d)
+        return fail(KNNG_EINVAL, "S->d = %d differs from raw->d = %d", S->d, raw->d);
+    const int64_t nb = S->n, nr = raw->n, n = nb + nr;
+    if (k < 1 || k > MAX_K || k > n - 1)
+        return fail(KNNG_EINVAL, "k = %d out of range [1, min(64, n-1)]", k);
+    const int k1 = keep_count(opts, k);
+    if (nb > 0 && (s = check_graph_in(G, nb, "G", k1)))
+        return s;
+    if ((s = check_out(out, n, k)))
+        return s;
+    const bool bf16 = uses_bf16(metric, opts);
+    const int kin = nb > 0 ? G->k : 0;
+    const size_t need = knng_expand_workspace_size(nb, nr, raw->d, k, kin, metric, opts);
+    if (!workspace || workspace_bytes < need)
+        return fail(KNNG_ENOMEM, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    if (!is_device_ptr(workspace))
+        return fail(KNNG_EINVAL, "workspace is not device memory");
+    hipStream_t st = (hipStream_t)stream;
+    if (stats)
+        memset(stats, 0, sizeof *stats);
+    Carve c(workspace);
+    Layout w;
+    carve_merge(c, w, n, nb, raw->d, k, kin, opts->sample, metric, bf16);
+    Prof prof{(opts->flags & KNNG_FLAG_PROFILE) != 0, st};
+    Rows R;
+    prof.begin(PH_PREP);
+    s = prepare(S, nb > 0 ? G : nullptr, raw, nullptr, metric, bf16, w, nb, n, st, R);
+    prof.end();
+    if (s != KNNG_OK)
+        return s;
+    return run_merge(R, w, metric, bf16, opts, n, nb, k, nb > 0 ? k1 : 0, 1, nb, out, st, stats,
+                     prof);
+}
+
+size_t knng_bruteforce_workspace_size(int64_t n1, int64_t n2, int32_t d, int32_t k,
+                                      int32_t kin1, int32_t kin2, knng_metric metric)
+{
+    if (n1 < 1 || n2 < 1 || d < 1 || k < 1)
+        return 0;
+    Carve c(nullptr);
+    const int64_t n = n1 + n2;
+    c.take<uint64_t>(C_WORDS);
+    c.take<float>((size_t)n * pad4(d));
+    if (metric == KNNG_COSINE)
+        c.take<float>(n);
+    c.take<uint64_t>((size_t)n * (kin1 > kin2 ? kin1 : kin2));
+    return c.off + 256;
+}
+
+knng_status knng_merge_bruteforce(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
+                                  const knng_graph *G2, int32_t k, knng_metric metric,
+                                  knng_graph *out, void *workspace, size_t workspace_bytes,
+                                  void *stream)
+{
+    knng_status s;
+    if ((s = check_metric(metric)) || (s = check_set(S1, "S1")) || (s = check_set(S2, "S2")))
+        return s;
+    if (S1->d != S2->d)
+        return fail(KNNG_EINVAL, "S1->d = %d differs from S2->d = %d", S1->d, S2->d);
+    const int64_t n1 = S1->n, n2 = S2->n, n = n1 + n2;
+    if (k < 1 || k > MAX_K || k > n - 1)
+        return fail(KNNG_EINVAL, "k = %d out of range [1, min(64, n1+n2-1)]", k);
+    if ((s = check_graph_in(G1, n1, "G1", 0)) || (s = check_graph_in(G2, n2, "G2", 0)) ||
+        (s = check_out(out, n, k)))
+        return s;
+    const size_t need = knng_bruteforce_workspace_size(n1, n2, S1->d, k, G1->k, G2->k, metric);
+    if (!workspace || workspace_bytes < need)
+        return fail(KNNG_ENOMEM, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    if (!is_device_ptr(workspace))
+        return fail(KNNG_EINVAL, "workspace is not device memory");
+    hipStream_t st = (hipStream_t)stream;
+    Carve c(workspace);
+    Layout w{};
+    w.dp = pad4(S1->d);
+    w.db = 0;
+    w.gstride = G1->k > G2->k ? G1->k : G2->k;
+    w.ctr = c.take<uint64_t>(C_WORDS);
+    w.x = c.take<float>((size_t)n * w.dp);
+    w.norm = metric == KNNG_COSINE ? c.take<float>(n) : nullptr;
+    w.gin = c.take<uint64_t>((size_t)n * w.gstride);
+    Rows R;
+    s = prepare(S1, G1, S2, G2, metric, false, w, n1, n, st, R);
+    if (s != KNNG_OK)
+        return s;
+    HIP_TRY(launch_brute(R, metric, 0, n1, n1, n, w.gin, w.gstride, k, 0, 0, 0, out->ids,
+                         out->dist, st));
+    HIP_TRY(launch_brute(R, metric, n1, n, 0, n1, w.gin + n1 * w.gstride, w.gstride, k, 0, 0, 0,
+                         out->ids, out->dist, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return ok();
+}
+
+size_t knng_exact_graph_workspace_size(int64_t n, int32_t d, int32_t k, knng_metric metric)
+{
+    if (n < 2 || d < 1 || k < 1)
+        return 0;
+    Carve c(nullptr);
+    c.take<uint64_t>(C_WORDS);
+    c.take<float>((size_t)n * pad4(d));
+    if (metric == KNNG_COSINE)
+        c.take<float>(n);
+    return c.off + 256;
+}
+
+knng_status knng_exact_graph(const knng_set *S, int32_t k, knng_metric metric, knng_graph *out,
+                             void *workspace, size_t workspace_bytes, void *stream)
+{
+    knng_status s;
+    if ((s = check_metric(metric)) || (s = check_set(S, "S")))
+        return s;
+    const int64_t n = S->n;
+    if (k < 1 || k > MAX_K || k > n - 1)
+        return fail(KNNG_EINVAL, "k = %d out of range [1, min(64, n-1)]", k);
+    if ((s = check_out(out, n, k)))
+        return s;
+    const size_t need = knng_exact_graph_workspace_size(n, S->d, k, metric);
+    if (!workspace || workspace_bytes < need)
+        return fail(KNNG_ENOMEM, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    if (!is_device_ptr(workspace))
+        return fail(KNNG_EINVAL, "workspace is not device memory");
+    hipStream_t st = (hipStream_t)stream;
+    Carve c(workspace);
+    Layout w{};
+    w.dp = pad4(S->d);
+    w.ctr = c.take<uint64_t>(C_WORDS);
+    w.x = c.take<float>((size_t)n * w.dp);
+    w.norm = metric == KNNG_COSINE ? c.take<float>(n) : nullptr;
+    knng_set empty{0, S->d, nullptr};
+    Rows R;
+    s = prepare(&empty, nullptr, S, nullptr, metric, false, w, 0, n, st, R);
+    if (s != KNNG_OK)
+        return s;
+    HIP_TRY(launch_brute(R, metric, 0, n, 0, n, nullptr, 0, k, 1, 0, 0, out->ids, out->dist,
+                         st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return ok();
+}
+
+} // extern "C"

@@ -1,0 +1,215 @@
+// knng_common.h -- device helpers shared by the HIP kernels of libknngmerge.
+//
+// Packed list entries, the counter-based random stream, canonical FP32
+// distances and the lock-free bounded-set insert.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace knng {
+
+enum { M_L2 = 0, M_COS = 1, M_L1 = 2 };
+
+constexpr int WAVE = 64;
+constexpr int MAX_K = 64;      // list capacity
+constexpr int MAX_S = 32;      // sample size
+constexpr int MAX_G = 160;     // neighbourhood size bound: 2s + k + s
+
+// error bits collected in the device error word
+enum : uint32_t {
+    ERR_NONFINITE = 1u << 0,
+    ERR_ZERO_NORM = 1u << 1,
+    ERR_ID_RANGE = 1u << 2,
+    ERR_SELF = 1u << 3,
+    ERR_DUP = 1u << 4,
+    ERR_UNSORTED = 1u << 5,
+    ERR_BAD_DIST = 1u << 6,
+    ERR_SPIN = 1u << 7,  // an insert exceeded its retry budget
+    ERR_GROUP = 1u << 8, // neighbourhood larger than the kernel bound
+};
+
+// counters block (uint64 words)
+enum : int {
+    // per-round words (cleared before each round's reverse/join)
+    C_FRESH = 0,    // entries inserted during the last round and still present
+    C_PAIRS = 1,    // joined pairs this round
+    C_GATHER = 2,   // neighbourhood members staged this round
+    C_ROUND_WORDS = 3,
+    // whole-call words
+    C_EVALS = 3,    // distance evaluations (scanning-rate numerator)
+    C_RESCORE = 4,  // pairs rescored in FP32 (BF16 path)
+    C_MAXG = 5,     // largest neighbourhood (max)
+    C_ERR = 6,      // error bits
+    C_WORDS = 8,
+};
+
+// ---------------------------------------------------------------- keys
+// A list entry is one 64-bit word ordered as an unsigned integer:
+//   bits 63..32  IEEE bits of the distance (always >= +0, so the unsigned
+//                order of the bits is the numeric order)
+//   bits 31..2   id (< 2^30)
+//   bit 1        FRESH: inserted during the current round
+//   bit 0        NEW:   not yet taken as a NEW sample
+// Unsigned order of the word = (distance, id) order; the flags never decide
+// between different entries.  Empty slots hold ~0 - slot: above every real
+// entry and distinct from each other.
+constexpr uint32_t F_NEW = 1u;
+constexpr uint32_t F_FRESH = 2u;
+
+__device__ __forceinline__ uint64_t make_key(float d, uint32_t id, uint32_t flags)
+{
+    return ((uint64_t)__float_as_uint(d) << 32) | ((uint64_t)id << 2) | flags;
+}
+__device__ __forceinline__ uint32_t key_id(uint64_t k) { return ((uint32_t)k) >> 2; }
+__device__ __forceinline__ float key_dist(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ __forceinline__ uint64_t key_strip(uint64_t k) { return k & ~3ull; }
+__device__ __forceinline__ uint64_t empty_key(int slot) { return ~0ull - (uint64_t)slot; }
+__device__ __forceinline__ bool key_empty(uint64_t k) { return (uint32_t)(k >> 32) == 0xFFFFFFFFu; }
+
+// ---------------------------------------------------------------- random stream
+// SplitMix64 (Steele, Lea, Flood 2014): state x -> mix(x + golden gamma).
+__device__ __forceinline__ uint64_t sm64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// hash of a tuple: the generator chained over (seed ^ tag, a, b, c)
+__device__ __forceinline__ uint64_t hash5(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b,
+                                          uint64_t c)
+{
+    uint64_t h = sm64(seed ^ tag);
+    h = sm64(h ^ a);
+    h = sm64(h ^ b);
+    return sm64(h ^ c);
+}
+
+constexpr uint32_t TAG_APPEND = 0xA1u, TAG_INIT = 0xA2u, TAG_FWD = 0xB1u, TAG_RNEW = 0xB2u,
+                   TAG_ROLD = 0xB3u;
+
+// uniform draw below N from the high 32 bits (multiply-shift)
+__device__ __forceinline__ uint32_t draw_below(uint64_t h, uint32_t N)
+{
+    return (uint32_t)(((h >> 32) * (uint64_t)N) >> 32);
+}
+
+// ---------------------------------------------------------------- canonical FP32
+// Rows are padded with zeros to a multiple of 4 floats; a zero pair adds
+// exactly nothing to any accumulator below, so padded lengths give the same
+// bits as the true length.
+template <int METRIC>
+__device__ __forceinline__ float canon_step(float acc, float a, float b)
+{
+    if constexpr (METRIC == M_L1) {
+        return acc + fabsf(a - b);
+    } else {
+        float diff = a - b;
+        return __builtin_fmaf(diff, diff, acc);
+    }
+}
+
+// cosine distance from the l2 accumulator and the two canonical norms
+__device__ __forceinline__ float cos_finish(float D, float na, float nb)
+{
+    float e = na - nb;
+    float num = __builtin_fmaf(-e, e, D);
+    float den = (2.0f * na) * nb;
+    float r = num / den;  // correctly rounded (see build flags)
+    return r > 0.0f ? r : 0.0f;
+}
+
+template <int METRIC>
+__device__ __forceinline__ float canon_finish(float acc, float na, float nb)
+{
+    if constexpr (METRIC == M_COS)
+        return cos_finish(acc, na, nb);
+    else
+        return acc;
+}
+
+// full canonical distance of two padded rows read from global memory
+template <int METRIC>
+__device__ __forceinline__ float canon_dist(const float *__restrict__ a, const float *__restrict__ b,
+                                            int dp, float na, float nb)
+{
+    float acc = 0.0f;
+    const float4 *a4 = reinterpret_cast<const float4 *>(a);
+    const float4 *b4 = reinterpret_cast<const float4 *>(b);
+    for (int t = 0; t < dp / 4; t++) {
+        float4 x = a4[t], y = b4[t];
+        acc = canon_step<METRIC>(acc, x.x, y.x);
+        acc = canon_step<METRIC>(acc, x.y, y.y);
+        acc = canon_step<METRIC>(acc, x.z, y.z);
+        acc = canon_step<METRIC>(acc, x.w, y.w);
+    }
+    return canon_finish<METRIC>(acc, na, nb);
+}
+
+// ---------------------------------------------------------------- atomics
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool cas64(uint64_t *p, uint64_t expect, uint64_t desired)
+{
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int SPIN_BUDGET = 1 << 16;
+
+// Insert `key` into the unordered bounded set slots[0..cap): when the key is
+// below the current maximum and (if `dedupe`) no slot holds the same
+// (distance, id), the maximum slot is replaced.  Linearises at the CAS:
+// slot values only ever decrease, so the maximum read before a successful
+// CAS is still the maximum, and the final content of the set after any
+// interleaving of inserts is the `cap` smallest distinct keys offered
+// (together with what it held).  Returns true when the key went in.
+__device__ inline bool bounded_insert(uint64_t *slots, int cap, uint64_t key, bool dedupe,
+                                      uint64_t *err_word)
+{
+    uint64_t kid = key_strip(key);
+    for (int spin = 0; spin < SPIN_BUDGET; spin++) {
+        uint64_t mx = 0;
+        int mj = 0;
+        for (int j = 0; j < cap; j++) {
+            uint64_t v = ld_agent(slots + j);
+            if (dedupe && key_strip(v) == kid)
+                return false;
+            if (j == 0 || v > mx) {
+                mx = v;
+                mj = j;
+            }
+        }
+        if (key >= mx)
+            return false;
+        if (cas64(slots + mj, mx, key))
+            return true;
+    }
+    atomicOr((unsigned long long *)err_word, (unsigned long long)ERR_SPIN);
+    return false;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+// wave-wide sums / max through shuffles
+__device__ __forceinline__ int wave_sum(int v)
+{
+    for (int o = WAVE / 2; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        uint64_t w = __shfl_xor(v, o, WAVE);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+} // namespace knng

@@ -1,0 +1,85 @@
+// knng_internal.h -- host-side launchers of the kernels (one per .hip file
+// family) and the layout shared between the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace knng {
+
+// Device view of the rows of a merge: the two input sets concatenated into one
+// padded fp32 array (rows of the first set first), plus per-row canonical norms.
+struct Rows {
+    const float *x;  // n x dp fp32, zero-padded
+    const float *norm;  // n canonical norms (cosine) or nullptr
+    const uint16_t *xb;  // n x db bf16 copy (BF16 path) or nullptr
+    const float *sq;  // n squared norms of the bf16 rows (BF16 l2) or nullptr
+    int64_t n;
+    int d, dp, db;
+};
+
+// Parameters of one iteration of the merge loop.
+struct RoundArgs {
+    uint64_t *L;        // n x k list words
+    uint64_t *worst;    // n: maximum word of each list at the round start
+    int32_t *new_f;     // n x s
+    int32_t *old_f;     // n x k
+    int32_t *cnt_f;     // n x 2: (#new_f, #old_f)
+    uint64_t *rnew;     // n x s reverse NEW reservoirs
+    uint64_t *rold;     // n x s reverse OLD reservoirs
+    uint64_t *ctr;      // counter words
+    int64_t n;
+    int64_t n1;         // first row of the second set
+    int k, s;
+    int joint;          // 0: S-Merge predicate, 1: J-Merge predicate
+    uint64_t seed;
+    int round;
+};
+
+// ---- knng_prep.hip
+hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2, int d, int dp,
+                       float *x, int db, uint16_t *xb, uint64_t *ctr, hipStream_t st);
+hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float *sq_bf16,
+                        const uint16_t *xb, int db, int check_zero, uint64_t *ctr,
+                        hipStream_t st);
+// Input graph rows [row0, row0+nrows) of the concatenated set: local ids +
+// offset -> sorted keys (kin per row) in `gin`.
+hipError_t launch_prep_input(const Rows &R, int metric, int64_t row0, int64_t nrows,
+                             int64_t id_offset, int64_t n_local, const int32_t *ids,
+                             const float *dist, int kin, int gstride, uint64_t *gin,
+                             uint64_t *ctr, hipStream_t st);
+// Divide + Append (rows with an input list) and Initialize (raw rows).
+struct InitArgs {
+    uint64_t *L;
+    const uint64_t *gin;
+    int kin, k, k1;
+    int64_t n, n1;      // n1: rows of the first set (S1 or base)
+    int joint;          // J-Merge: rows >= n1 are raw
+    uint64_t seed;
+    uint64_t *ctr;
+};
+hipError_t launch_init(const Rows &R, int metric, const InitArgs &a, hipStream_t st);
+// Merge and Sort: list + set-aside rear part -> output rows.
+hipError_t launch_final(const uint64_t *L, int k, const uint64_t *gin, int kin, int k1,
+                        int64_t rows_with_rear, int64_t n, int32_t *out_ids, float *out_dist,
+                        hipStream_t st);
+hipError_t launch_zero_counters(uint64_t *ctr, int words, hipStream_t st);
+
+// ---- knng_round.hip
+hipError_t launch_sample(const RoundArgs &a, hipStream_t st);
+hipError_t launch_reverse(const RoundArgs &a, hipStream_t st);
+hipError_t launch_count_fresh(const RoundArgs &a, hipStream_t st);
+
+// ---- knng_join.hip
+hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, hipStream_t st);
+
+// ---- knng_brute.hip
+// Rows [a_lo,a_hi) against rows [b_lo,b_hi) of R; optional sorted initial
+// keys per A row (kin each, indexed from a_lo); writes out rows a (global
+// index a - out_base).  exclude_self skips a == b.
+hipError_t launch_brute(const Rows &R, int metric, int64_t a_lo, int64_t a_hi, int64_t b_lo,
+                        int64_t b_hi, const uint64_t *init, int kin, int k, int exclude_self,
+                        int64_t out_base, int64_t id_base, int32_t *out_ids, float *out_dist,
+                        hipStream_t st);
+
+} // namespace knng

@@ -1,0 +1,402 @@
+// knng_prep.hip -- input layout, Divide/Append/Initialize and Merge-and-Sort.
+//
+// Steps of Algorithms 1 and 2 (Zhao et al., "On the Merge of k-NN Graph",
+// Sections 3.1-3.2) that run once per call: building the device layout,
+// reading the input graphs, the Divide/Append (or Initialize) steps before the
+// repeat loop, and the final Merge and Sort with the set-aside rear lists.
+#include "knng_common.h"
+#include "knng_internal.h"
+
+namespace knng {
+
+namespace {
+
+// round-to-nearest-even fp32 -> bf16 bits (inputs are finite)
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// concatenate the two sets into one zero-padded fp32 array (+ bf16 copy)
+__global__ void k_pack(const float *__restrict__ x1, int64_t n1, const float *__restrict__ x2,
+                       int64_t n2, int d, int dp, float *__restrict__ x, int db,
+                       uint16_t *__restrict__ xb, uint64_t *ctr)
+{
+    int64_t n = n1 + n2;
+    int wmax = dp > db ? dp : db;
+    int64_t total = n * (int64_t)wmax;
+    uint32_t bad = 0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = e / wmax;
+        int c = (int)(e - r * wmax);
+        float v = 0.0f;
+        if (c < d) {
+            v = r < n1 ? x1[r * d + c] : x2[(r - n1) * d + c];
+            if (!isfinite(v)) {
+                bad = 1;
+                v = 0.0f;
+            }
+        }
+        if (c < dp)
+            x[r * dp + c] = v;
+        if (xb && c < db)
+            xb[r * db + c] = f32_to_bf16(v);
+    }
+    if (bad)
+        atomicOr((unsigned long long *)(ctr + C_ERR), (unsigned long long)ERR_NONFINITE);
+}
+
+// canonical norms (ascending fused accumulation, correctly rounded sqrt) and,
+// for the BF16 path, the squared norms of the bf16-rounded rows
+__global__ void k_norms(const float *__restrict__ x, int64_t n, int dp, float *__restrict__ norm,
+                        float *__restrict__ sq, const uint16_t *__restrict__ xb, int db,
+                        int check_zero, uint64_t *ctr)
+{
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n)
+        return;
+    if (norm) {
+        const float4 *p = reinterpret_cast<const float4 *>(x + r * dp);
+        float acc = 0.0f;
+        for (int t = 0; t < dp / 4; t++) {
+            float4 v = p[t];
+            acc = __builtin_fmaf(v.x, v.x, acc);
+            acc = __builtin_fmaf(v.y, v.y, acc);
+            acc = __builtin_fmaf(v.z, v.z, acc);
+            acc = __builtin_fmaf(v.w, v.w, acc);
+        }
+        float nr = __builtin_sqrtf(acc);  // correctly rounded (see build flags)
+        norm[r] = nr;
+        if (check_zero && !(nr > 0.0f))
+            atomicOr((unsigned long long *)(ctr + C_ERR), (unsigned long long)ERR_ZERO_NORM);
+    }
+    if (sq) {
+        // exact enough: a sum of squares of bf16 values accumulated in fp32
+        float acc = 0.0f;
+        for (int t = 0; t < db; t++) {
+            float v = bf16_to_f32(xb[r * db + t]);
+            acc = __builtin_fmaf(v, v, acc);
+        }
+        sq[r] = acc;
+    }
+}
+
+// one wave per input row: local ids -> global keys, validated, sorted
+template <int METRIC>
+__global__ __launch_bounds__(256) void k_prep_input(Rows R, int64_t row0, int64_t nrows,
+                                                    int64_t id_offset, int64_t n_local,
+                                                    const int32_t *__restrict__ ids,
+                                                    const float *__restrict__ dist, int kin,
+                                                    int gstride, uint64_t *__restrict__ gin,
+                                                    uint64_t *ctr)
+{
+    const int lane = lane_id();
+    const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    if (wid >= nrows)
+        return;
+    const int64_t r = row0 + wid;
+    uint32_t err = 0;
+    bool act = lane < kin;
+    int64_t g = -1;
+    uint64_t key = ~0ull;
+    if (act) {
+        int32_t loc = ids[wid * kin + lane];
+        if (loc < 0 || loc >= n_local) {
+            err |= ERR_ID_RANGE;
+        } else {
+            g = loc + id_offset;
+            if (g == r)
+                err |= ERR_SELF;
+        }
+        float dv = 0.0f;
+        if (g >= 0) {
+            if (dist) {
+                dv = dist[wid * kin + lane];
+                if (!(dv >= 0.0f) || isinf(dv))
+                    err |= ERR_BAD_DIST;
+            } else {
+                const float *a = R.x + r * R.dp, *b = R.x + g * R.dp;
+                float na = R.norm ? R.norm[r] : 0.0f, nb = R.norm ? R.norm[g] : 0.0f;
+                dv = canon_dist<METRIC>(a, b, R.dp, na, nb);
+            }
+        }
+        key = make_key(dv > 0.0f ? dv : 0.0f, (uint32_t)(g < 0 ? 0 : g), 0);
+    }
+    // duplicates and order
+    int rank = 0;
+    for (int j = 0; j < kin; j++) {
+        uint64_t o = __shfl(key, j, WAVE);
+        int64_t og = __shfl(g, j, WAVE);
+        if (act && j != lane && og == g && g >= 0)
+            err |= ERR_DUP;
+        if (act && o < key)
+            rank++;
+    }
+    if (dist) {
+        uint64_t prev = __shfl_up(key, 1, WAVE);
+        if (act && lane > 0 && !(prev < key))
+            err |= ERR_UNSORTED;
+        rank = lane;
+    }
+    if (act && err == 0)
+        gin[r * gstride + rank] = key;
+    if (lane >= kin && lane < gstride)
+        gin[r * gstride + lane] = ~0ull;  // padding of a shorter row
+    if (err)
+        atomicOr((unsigned long long *)(ctr + C_ERR), (unsigned long long)err);
+}
+
+// one wave per row: Divide + Append (rows with a list) or Initialize (raw)
+template <int METRIC>
+__global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
+{
+    __shared__ int32_t picked_all[4][MAX_K];
+    const int lane = lane_id();
+    const int w = threadIdx.x / WAVE;
+    int32_t *picked = picked_all[w];
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    if (i >= a.n)
+        return;
+    const bool has_list = !a.joint || i < a.n1;
+    int first, m;
+    uint32_t N;
+    int64_t skip, cand_off;
+    if (has_list) {
+        // Append: k - k1 samples of the other set (S-Merge) / of the raw set
+        int64_t n_other = a.joint ? a.n - a.n1 : (i < a.n1 ? a.n - a.n1 : a.n1);
+        N = (uint32_t)n_other;
+        cand_off = a.joint ? a.n1 : (i < a.n1 ? a.n1 : 0);
+        skip = -1;
+        first = a.k1;
+        m = (int64_t)(a.k - a.k1) < n_other ? a.k - a.k1 : (int)n_other;
+    } else {
+        // Initialize: k samples of S u raw, self excluded
+        N = (uint32_t)a.n;
+        cand_off = 0;
+        skip = i;
+        first = 0;
+        m = (int64_t)a.k < a.n - 1 ? a.k : (int)(a.n - 1);
+    }
+    const uint32_t tag = has_list ? TAG_APPEND : TAG_INIT;
+    const uint32_t avail = N - (skip >= 0 ? 1u : 0u);
+    // m distinct draws in draw order (the first m distinct values of the stream)
+    int got = 0;
+    if ((uint32_t)m >= avail) {
+        if (lane < m)
+            picked[lane] = (int32_t)((skip >= 0 && lane >= skip) ? lane + 1 : lane);
+        got = m;
+    } else {
+        const int64_t budget = 64 * (int64_t)m + 4096;
+        const uint64_t below = (1ull << lane) - 1ull;
+        for (int64_t base = 0; got < m && base < budget; base += WAVE) {
+            int64_t t = base + lane;
+            bool valid = t < budget;
+            uint64_t h = hash5(a.seed, tag, (uint64_t)i, (uint64_t)t, 0);
+            uint32_t v;
+            if (skip >= 0) {
+                v = draw_below(h, N - 1);
+                if ((int64_t)v >= skip)
+                    v++;
+            } else {
+                v = draw_below(h, N);
+            }
+            bool dup = false;
+            for (int j = 0; j < WAVE; j++) {
+                uint32_t o = __shfl(v, j, WAVE);
+                if (j < lane && o == v)
+                    dup = true;
+            }
+            for (int q = 0; q < got; q++)
+                if ((uint32_t)picked[q] == v)
+                    dup = true;
+            bool acc = valid && !dup;
+            uint64_t mask = __ballot(acc);
+            int pos = got + __popcll(mask & below);
+            if (acc && pos < m)
+                picked[pos] = (int32_t)v;
+            int add = __popcll(mask);
+            got = got + add < m ? got + add : m;
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (got < m && lane == 0) {
+            // draw budget exhausted: smallest values not yet taken
+            for (uint32_t v = 0; v < N && got < m; v++) {
+                if ((int64_t)v == skip)
+                    continue;
+                bool dup = false;
+                for (int q = 0; q < got; q++)
+                    if ((uint32_t)picked[q] == v)
+                        dup = true;
+                if (!dup)
+                    picked[got++] = (int32_t)v;
+            }
+        }
+        got = __shfl(got, 0, WAVE);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < a.k) {
+        uint64_t key;
+        if (lane < first) {
+            key = key_strip(a.gin[i * a.kin + lane]);  // kept entries start OLD
+        } else if (lane < first + m) {
+            int64_t g = picked[lane - first] + cand_off;
+            float na = R.norm ? R.norm[i] : 0.0f, nb = R.norm ? R.norm[g] : 0.0f;
+            float dv = canon_dist<METRIC>(R.x + i * R.dp, R.x + g * R.dp, R.dp, na, nb);
+            key = make_key(dv, (uint32_t)g, F_NEW);
+        } else {
+            key = empty_key(lane);
+        }
+        a.L[i * a.k + lane] = key;
+    }
+    if (lane == 0 && m > 0)
+        atomicAdd((unsigned long long *)(a.ctr + C_EVALS), (unsigned long long)m);
+}
+
+// one wave per row: top k of the list and the rear part, deduplicated
+__global__ __launch_bounds__(256) void k_final(const uint64_t *__restrict__ L, int k,
+                                               const uint64_t *__restrict__ gin, int kin, int k1,
+                                               int64_t rows_with_rear, int64_t n,
+                                               int32_t *__restrict__ out_ids,
+                                               float *__restrict__ out_dist)
+{
+    __shared__ uint64_t cand_all[4][2 * WAVE];
+    __shared__ uint64_t kept_all[4][2 * WAVE];
+    const int lane = lane_id();
+    const int w = threadIdx.x / WAVE;
+    uint64_t *cand = cand_all[w];
+    uint64_t *kept = kept_all[w];
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    if (i >= n)
+        return;
+    const int nrear = i < rows_with_rear ? kin - k1 : 0;
+    uint64_t c0 = lane < k ? key_strip(L[i * k + lane]) : ~0ull;
+    uint64_t c1 = lane < nrear ? key_strip(gin[i * kin + k1 + lane]) : ~0ull;
+    if (key_empty(c0))
+        c0 = ~0ull;
+    if (key_empty(c1))
+        c1 = ~0ull;  // padding of rows shorter than the row stride
+    cand[lane] = c0;
+    cand[WAVE + lane] = c1;
+    __builtin_amdgcn_wave_barrier();
+    // keep the first occurrence of each entry
+    bool v0 = c0 != ~0ull, v1 = c1 != ~0ull;
+    for (int j = 0; j < 2 * WAVE; j++) {
+        uint64_t o = cand[j];
+        if (o == c0 && j < lane)
+            v0 = false;
+        if (o == c1 && j < WAVE + lane)
+            v1 = false;
+    }
+    kept[lane] = v0 ? c0 : ~0ull;
+    kept[WAVE + lane] = v1 ? c1 : ~0ull;
+    __builtin_amdgcn_wave_barrier();
+    int r0 = 0, r1 = 0;
+    for (int j = 0; j < 2 * WAVE; j++) {
+        uint64_t o = kept[j];
+        r0 += o < c0;
+        r1 += o < c1;
+    }
+    int nvalid = wave_sum((int)v0 + (int)v1);
+    if (v0 && r0 < k) {
+        out_ids[i * k + r0] = (int32_t)key_id(c0);
+        out_dist[i * k + r0] = key_dist(c0);
+    }
+    if (v1 && r1 < k) {
+        out_ids[i * k + r1] = (int32_t)key_id(c1);
+        out_dist[i * k + r1] = key_dist(c1);
+    }
+    if (lane >= nvalid && lane < k) {
+        out_ids[i * k + lane] = -1;
+        out_dist[i * k + lane] = __uint_as_float(0x7F800000u);
+    }
+}
+
+__global__ void k_zero(uint64_t *p, int words)
+{
+    int t = threadIdx.x;
+    if (t < words)
+        p[t] = 0;
+}
+
+inline unsigned grid_for(int64_t items, int per_block)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+} // namespace
+
+hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2, int d, int dp,
+                       float *x, int db, uint16_t *xb, uint64_t *ctr, hipStream_t st)
+{
+    int64_t total = (n1 + n2) * (int64_t)(dp > db ? dp : db);
+    unsigned grid = grid_for(total, 256);
+    if (grid > 65536u)
+        grid = 65536u;
+    hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, x1, n1, x2, n2, d, dp, x, db, xb,
+                       ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float *sq_bf16,
+                        const uint16_t *xb, int db, int check_zero, uint64_t *ctr,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_norms, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, dp, norm,
+                       sq_bf16, xb, db, check_zero, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_input(const Rows &R, int metric, int64_t row0, int64_t nrows,
+                             int64_t id_offset, int64_t n_local, const int32_t *ids,
+                             const float *dist, int kin, int gstride, uint64_t *gin,
+                             uint64_t *ctr, hipStream_t st)
+{
+    if (nrows <= 0 || gstride <= 0)
+        return hipSuccess;
+    dim3 grid(grid_for(nrows, 4)), block(256);
+    if (metric == M_L2)
+        hipLaunchKernelGGL(k_prep_input<M_L2>, grid, block, 0, st, R, row0, nrows, id_offset,
+                           n_local, ids, dist, kin, gstride, gin, ctr);
+    else if (metric == M_COS)
+        hipLaunchKernelGGL(k_prep_input<M_COS>, grid, block, 0, st, R, row0, nrows, id_offset,
+                           n_local, ids, dist, kin, gstride, gin, ctr);
+    else
+        hipLaunchKernelGGL(k_prep_input<M_L1>, grid, block, 0, st, R, row0, nrows, id_offset,
+                           n_local, ids, dist, kin, gstride, gin, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const Rows &R, int metric, const InitArgs &a, hipStream_t st)
+{
+    dim3 grid(grid_for(a.n, 4)), block(256);
+    if (metric == M_L2)
+        hipLaunchKernelGGL(k_init<M_L2>, grid, block, 0, st, R, a);
+    else if (metric == M_COS)
+        hipLaunchKernelGGL(k_init<M_COS>, grid, block, 0, st, R, a);
+    else
+        hipLaunchKernelGGL(k_init<M_L1>, grid, block, 0, st, R, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_final(const uint64_t *L, int k, const uint64_t *gin, int kin, int k1,
+                        int64_t rows_with_rear, int64_t n, int32_t *out_ids, float *out_dist,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_final, dim3(grid_for(n, 4)), dim3(256), 0, st, L, k, gin, kin, k1,
+                       rows_with_rear, n, out_ids, out_dist);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(uint64_t *ctr, int words, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, ctr, words);
+    return hipGetLastError();
+}
+
+} // namespace knng

@@ -1,0 +1,148 @@
+// knng_round.hip -- per-round sampling and Reverse(G) of the repeat loop of
+// Algorithms 1 and 2 (Zhao et al., Sections 3.1-3.2).  The paper runs the
+// NN-Descent iteration by citation; its sampling is realised as:
+//   forward: each row takes up to s NEW entries with the smallest hash
+//            priority as its NEW sample and marks them OLD; entries that were
+//            OLD before form its OLD sample;
+//   reverse: every sampled edge u -> v offers u to v's reverse NEW (or OLD)
+//            list, which keeps the s offers of smallest hash priority.
+// Both selections are order-independent, so the result does not depend on
+// thread scheduling.
+#include "knng_common.h"
+#include "knng_internal.h"
+
+namespace knng {
+
+namespace {
+
+// one wave per row (k <= 64 lanes)
+__global__ __launch_bounds__(256) void k_sample(RoundArgs a)
+{
+    const int lane = lane_id();
+    const int64_t u = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    if (u >= a.n)
+        return;
+    const bool act = lane < a.k;
+    uint64_t v = act ? a.L[u * a.k + lane] : ~0ull;
+    const bool empty = !act || key_empty(v);
+    const bool fresh = !empty && (v & F_FRESH);
+    const bool isnew = !empty && (v & F_NEW);
+    const bool isold = !empty && !(v & F_NEW);
+    const uint32_t id = key_id(v);
+    uint64_t pk = ~0ull;
+    if (isnew) {
+        uint64_t h = hash5(a.seed, TAG_FWD, (uint64_t)a.round, (uint64_t)u, (uint64_t)id);
+        pk = ((h >> 32) << 32) | id;
+    }
+    int rank = 0, nnew = 0;
+    for (int j = 0; j < a.k; j++) {
+        uint64_t o = __shfl(pk, j, WAVE);
+        rank += o < pk;
+        nnew += o != ~0ull;
+    }
+    const bool sampled = isnew && rank < a.s;
+    if (sampled)
+        a.new_f[u * a.s + rank] = (int32_t)id;
+    uint64_t nv = v & ~(uint64_t)F_FRESH;
+    if (sampled)
+        nv &= ~(uint64_t)F_NEW;
+    if (act && !empty && nv != v)
+        a.L[u * a.k + lane] = nv;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint64_t om = __ballot(isold);
+    if (isold)
+        a.old_f[u * a.k + __popcll(om & below)] = (int32_t)id;
+    uint64_t wv = act ? (empty ? v : key_strip(nv)) : 0ull;
+    wv = wave_max_u64(wv);
+    int nfresh = wave_sum((int)fresh);
+    if (lane == 0) {
+        a.worst[u] = wv;
+        a.cnt_f[2 * u] = nnew < a.s ? nnew : a.s;
+        a.cnt_f[2 * u + 1] = __popcll(om);
+        if (nfresh)
+            atomicAdd((unsigned long long *)(a.ctr + C_FRESH), (unsigned long long)nfresh);
+    }
+    if (lane < a.s) {
+        a.rnew[u * a.s + lane] = empty_key(lane);
+        a.rold[u * a.s + lane] = empty_key(lane);
+    }
+}
+
+// one thread per sampled edge u -> v
+__global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
+{
+    const int per = a.s + a.k;
+    const int64_t total = a.n * per;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t u = e / per;
+        int j = (int)(e - u * per);
+        int32_t v;
+        uint32_t tag;
+        uint64_t *res;
+        if (j < a.s) {
+            if (j >= a.cnt_f[2 * u])
+                continue;
+            v = a.new_f[u * a.s + j];
+            tag = TAG_RNEW;
+            res = a.rnew;
+        } else {
+            j -= a.s;
+            if (j >= a.cnt_f[2 * u + 1])
+                continue;
+            v = a.old_f[u * a.k + j];
+            tag = TAG_ROLD;
+            res = a.rold;
+        }
+        uint64_t h = hash5(a.seed, tag, (uint64_t)a.round, (uint64_t)v, (uint64_t)u);
+        uint64_t key = ((h >> 32) << 32) | (uint64_t)u;
+        bounded_insert(res + (int64_t)v * a.s, a.s, key, false, a.ctr + C_ERR);
+    }
+}
+
+// count the FRESH entries left by the last round (statistics only)
+__global__ __launch_bounds__(256) void k_count_fresh(RoundArgs a)
+{
+    const int64_t total = a.n * a.k;
+    int c = 0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t v = a.L[e];
+        c += !key_empty(v) && (v & F_FRESH);
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0 && c)
+        atomicAdd((unsigned long long *)(a.ctr + C_FRESH), (unsigned long long)c);
+}
+
+inline unsigned grid_for(int64_t items, int per_block, unsigned cap)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1)
+        g = 1;
+    return (unsigned)(g > cap ? cap : g);
+}
+
+} // namespace
+
+hipError_t launch_sample(const RoundArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sample, dim3(grid_for(a.n, 4, 0x7FFFFFFFu)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse(const RoundArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reverse, dim3(grid_for(a.n * (a.s + a.k), 256, 1u << 20)), dim3(256),
+                       0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_fresh(const RoundArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_count_fresh, dim3(grid_for(a.n * a.k, 256, 16384)), dim3(256), 0, st,
+                       a);
+    return hipGetLastError();
+}
+
+} // namespace knng

@@ -1,0 +1,253 @@
+"""Python binding of libknngmerge.so (include/knng_merge.h).
+
+Argument marshalling only: every step of every call runs in the HIP kernels of
+the library.  PyTorch provides device memory (inputs, outputs, workspace) and
+the stream.  There is no fallback: if the library is not built, load() raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libknngmerge.so")
+
+L2, COSINE, L1 = 0, 1, 2
+METRICS = {"l2": L2, "cos": COSINE, "cosine": COSINE, "l1": L1}
+FP32, BF16_RESCORE = 0, 1
+PRECISIONS = {"fp32": FP32, "bf16": BF16_RESCORE, "bf16_rescore": BF16_RESCORE}
+FLAG_PROFILE = 1
+STATS_ROUNDS = 64
+
+STATUS = {0: "KNNG_OK", 1: "KNNG_EINVAL", 2: "KNNG_ENOMEM", 3: "KNNG_EDEVICE"}
+
+ENTRY_POINTS = ["knng_opts_default", "knng_merge", "knng_merge_workspace_size", "knng_expand",
+                "knng_expand_workspace_size", "knng_merge_bruteforce",
+                "knng_bruteforce_workspace_size", "knng_exact_graph",
+                "knng_exact_graph_workspace_size", "knng_last_error", "knng_version"]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("keep_ratio", ctypes.c_float), ("sample", ctypes.c_int32),
+                ("delta", ctypes.c_float), ("max_rounds", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class Set(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("x", ctypes.c_void_p)]
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("ids", ctypes.c_void_p),
+                ("dist", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("max_group", ctypes.c_int32),
+                ("evals", ctypes.c_int64), ("rescored", ctypes.c_int64),
+                ("updates", ctypes.c_int64 * STATS_ROUNDS),
+                ("pairs", ctypes.c_int64 * STATS_ROUNDS),
+                ("gathered", ctypes.c_int64 * STATS_ROUNDS),
+                ("ms_prep", ctypes.c_double), ("ms_init", ctypes.c_double),
+                ("ms_sample", ctypes.c_double), ("ms_reverse", ctypes.c_double),
+                ("ms_join", ctypes.c_double), ("ms_final", ctypes.c_double),
+                ("join_launches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def to_dict(self):
+        r = min(self.rounds, STATS_ROUNDS)
+        return {"rounds": self.rounds, "max_group": self.max_group, "evals": self.evals,
+                "rescored": self.rescored, "c": list(self.updates[:r]),
+                "pairs": list(self.pairs[:r]), "gathered": list(self.gathered[:r]),
+                "ms": {"prep": self.ms_prep, "init": self.ms_init, "sample": self.ms_sample,
+                       "reverse": self.ms_reverse, "join": self.ms_join,
+                       "final": self.ms_final},
+                "join_launches": self.join_launches}
+
+
+class KnngError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load the built library (raises if it is missing: no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_1908_00814_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    pS, pG, pO, pSt = (ctypes.POINTER(Set), ctypes.POINTER(Graph), ctypes.POINTER(Opts),
+                       ctypes.POINTER(Stats))
+    lib.knng_opts_default.restype = None
+    lib.knng_opts_default.argtypes = [pO]
+    lib.knng_merge.restype = ctypes.c_int
+    lib.knng_merge.argtypes = [pS, pG, pS, pG, I32, ctypes.c_int, pO, pG, P, SZ, P, pSt]
+    lib.knng_merge_workspace_size.restype = SZ
+    lib.knng_merge_workspace_size.argtypes = [I64, I64, I32, I32, I32, I32, ctypes.c_int, pO]
+    lib.knng_expand.restype = ctypes.c_int
+    lib.knng_expand.argtypes = [pS, pG, pS, I32, ctypes.c_int, pO, pG, P, SZ, P, pSt]
+    lib.knng_expand_workspace_size.restype = SZ
+    lib.knng_expand_workspace_size.argtypes = [I64, I64, I32, I32, I32, ctypes.c_int, pO]
+    lib.knng_merge_bruteforce.restype = ctypes.c_int
+    lib.knng_merge_bruteforce.argtypes = [pS, pG, pS, pG, I32, ctypes.c_int, pG, P, SZ, P]
+    lib.knng_bruteforce_workspace_size.restype = SZ
+    lib.knng_bruteforce_workspace_size.argtypes = [I64, I64, I32, I32, I32, I32, ctypes.c_int]
+    lib.knng_exact_graph.restype = ctypes.c_int
+    lib.knng_exact_graph.argtypes = [pS, I32, ctypes.c_int, pG, P, SZ, P]
+    lib.knng_exact_graph_workspace_size.restype = SZ
+    lib.knng_exact_graph_workspace_size.argtypes = [I64, I32, I32, ctypes.c_int]
+    lib.knng_last_error.restype = ctypes.c_char_p
+    lib.knng_last_error.argtypes = []
+    lib.knng_version.restype = ctypes.c_int
+    lib.knng_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise KnngError(rc, load().knng_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _set(x):
+    assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.dim() == 2
+    return Set(x.shape[0], x.shape[1], x.data_ptr())
+
+
+def _graph(ids, dist):
+    assert ids.is_cuda and ids.dtype == torch.int32 and ids.is_contiguous()
+    if dist is not None:
+        assert dist.is_cuda and dist.dtype == torch.float32 and dist.is_contiguous()
+    return Graph(ids.shape[0], ids.shape[1], ids.data_ptr(),
+                 None if dist is None else dist.data_ptr())
+
+
+def _metric(m):
+    return METRICS[m] if isinstance(m, str) else int(m)
+
+
+def opts(keep_ratio=0.5, sample=10, delta=0.0, max_rounds=30, seed=0, precision="fp32",
+         profile=False):
+    o = Opts()
+    load().knng_opts_default(ctypes.byref(o))
+    o.keep_ratio = keep_ratio
+    o.sample = sample
+    o.delta = delta
+    o.max_rounds = max_rounds
+    o.seed = seed & (2 ** 64 - 1)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.flags = FLAG_PROFILE if profile else 0
+    return o
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _out(n, k, device):
+    ids = torch.empty((n, k), dtype=torch.int32, device=device)
+    dist = torch.empty((n, k), dtype=torch.float32, device=device)
+    return ids, dist
+
+
+def merge_workspace_size(n1, n2, d, k, kin1, kin2, metric="l2", **kw):
+    o = opts(**kw)
+    return load().knng_merge_workspace_size(n1, n2, d, k, kin1, kin2, _metric(metric),
+                                            ctypes.byref(o))
+
+
+def merge(S1, G1, S2, G2, k, metric="l2", stream=None, workspace=None, out=None, **kw):
+    """S-Merge (knng_merge).  G1/G2 = (ids int32, dist fp32 or None), local ids.
+    Returns (ids, dist, stats dict)."""
+    lib = load()
+    o = opts(**kw)
+    s1, s2 = _set(S1), _set(S2)
+    g1, g2 = _graph(*G1), _graph(*G2)
+    n = S1.shape[0] + S2.shape[0]
+    need = lib.knng_merge_workspace_size(S1.shape[0], S2.shape[0], S1.shape[1], k, g1.k, g2.k,
+                                         _metric(metric), ctypes.byref(o))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=S1.device)
+    ids, dist = out if out is not None else _out(n, k, S1.device)
+    go = _graph(ids, dist)
+    st = Stats()
+    _check(lib.knng_merge(ctypes.byref(s1), ctypes.byref(g1), ctypes.byref(s2), ctypes.byref(g2),
+                          k, _metric(metric), ctypes.byref(o), ctypes.byref(go),
+                          _ptr(workspace), workspace.numel(), _stream(stream),
+                          ctypes.byref(st)))
+    return ids, dist, st.to_dict()
+
+
+def expand(S, G, raw, k, metric="l2", stream=None, workspace=None, out=None, **kw):
+    """J-Merge (knng_expand).  S may be None/empty (NN-Descent of raw).
+    Returns (ids, dist, stats dict)."""
+    lib = load()
+    o = opts(**kw)
+    d = raw.shape[1]
+    if S is None or S.shape[0] == 0:
+        s = Set(0, d, None)
+        g = Graph(0, 0, None, None)
+        nb, kin = 0, 0
+    else:
+        s = _set(S)
+        g = _graph(*G)
+        nb, kin = S.shape[0], g.k
+    r = _set(raw)
+    n = nb + raw.shape[0]
+    need = lib.knng_expand_workspace_size(nb, raw.shape[0], d, k, kin, _metric(metric),
+                                          ctypes.byref(o))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=raw.device)
+    ids, dist = out if out is not None else _out(n, k, raw.device)
+    go = _graph(ids, dist)
+    st = Stats()
+    _check(lib.knng_expand(ctypes.byref(s), ctypes.byref(g), ctypes.byref(r), k,
+                           _metric(metric), ctypes.byref(o), ctypes.byref(go), _ptr(workspace),
+                           workspace.numel(), _stream(stream), ctypes.byref(st)))
+    return ids, dist, st.to_dict()
+
+
+def merge_bruteforce(S1, G1, S2, G2, k, metric="l2", stream=None):
+    """Brute-force cross merge (knng_merge_bruteforce).  Returns (ids, dist)."""
+    lib = load()
+    s1, s2 = _set(S1), _set(S2)
+    g1, g2 = _graph(*G1), _graph(*G2)
+    n = S1.shape[0] + S2.shape[0]
+    need = lib.knng_bruteforce_workspace_size(S1.shape[0], S2.shape[0], S1.shape[1], k, g1.k,
+                                              g2.k, _metric(metric))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=S1.device)
+    ids, dist = _out(n, k, S1.device)
+    go = _graph(ids, dist)
+    _check(lib.knng_merge_bruteforce(ctypes.byref(s1), ctypes.byref(g1), ctypes.byref(s2),
+                                     ctypes.byref(g2), k, _metric(metric), ctypes.byref(go),
+                                     _ptr(ws), ws.numel(), _stream(stream)))
+    return ids, dist
+
+
+def exact_graph(S, k, metric="l2", stream=None):
+    """Exact k-NN graph (knng_exact_graph).  Returns (ids, dist), local ids."""
+    lib = load()
+    s = _set(S)
+    need = lib.knng_exact_graph_workspace_size(S.shape[0], S.shape[1], k, _metric(metric))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=S.device)
+    ids, dist = _out(S.shape[0], k, S.device)
+    go = _graph(ids, dist)
+    _check(lib.knng_exact_graph(ctypes.byref(s), k, _metric(metric), ctypes.byref(go), _ptr(ws),
+                                ws.numel(), _stream(stream)))
+    return ids, dist
+
+
+def version():
+    return load().knng_version()

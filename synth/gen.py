@@ -89,20 +89,27 @@ def request_sizes(count, lo=1, hi=20_000, workload=5):
     return np.clip(np.floor(np.exp(u)).astype(np.int64), lo, hi)
 
 
-def degrade_lists(ids_ext, k, target_recall, workload=2, stream=6):
+def degrade_positions(n, m, k, target_recall, workload=2, stream=6):
     """Index-level perturbation of exact neighbour lists into approximate
-    ones.  `ids_ext` holds, per row, at least 2k exact neighbours in
-    ascending order.  The entry at rank r (0-based, r < k) is dropped with
-    probability 2 (1 - target) (r + 0.5) / k, so drops grow with rank and
-    average 1 - target; the row keeps the first k entries that survive, so
-    recall@k is close to `target_recall`.  Returns int32 ids (n, k)."""
-    ids_ext = np.asarray(ids_ext)
-    n, m = ids_ext.shape
+    ones.  Rows hold m >= 2k exact neighbours in ascending order; the entry at
+    rank r (0-based, r < k) is dropped with probability
+    2 (1 - target) (r + 0.5) / k, so drops grow with rank and average
+    1 - target; a row keeps the first k entries that survive, so recall@k is
+    close to `target_recall`.  Returns the kept column positions (n, k), in
+    ascending rank order."""
     assert m >= 2 * k
     g = rng(1000 * workload + stream)
     p = 2.0 * (1.0 - target_recall) * (np.arange(m) + 0.5) / k
     p[k:] = 0.0
     keep = g.random((n, m)) >= p[None, :]
     # stable order: survivors first (in rank order), then the dropped ones
-    order = np.argsort(~keep, axis=1, kind="stable")
-    return np.take_along_axis(ids_ext, order, axis=1)[:, :k].astype(np.int32)
+    order = np.argsort(~keep, axis=1, kind="stable")[:, :k]
+    return np.sort(order, axis=1)
+
+
+def degrade_lists(ids_ext, k, target_recall, workload=2, stream=6):
+    """degrade_positions applied to exact lists `ids_ext` (n, >= 2k)."""
+    ids_ext = np.asarray(ids_ext)
+    pos = degrade_positions(ids_ext.shape[0], ids_ext.shape[1], k, target_recall, workload,
+                            stream)
+    return np.take_along_axis(ids_ext, pos, axis=1).astype(np.int32)

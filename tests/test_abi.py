@@ -1,0 +1,59 @@
+"""The C-ABI library builds, loads and exports every entry point its header
+declares; host-only queries answer without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "knng_merge.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:knng_status|size_t|void|int|const char \*)\s*\*?\s*(knng_\w+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1908_00814_amd import knng
+    if not os.path.exists(knng.LIB_PATH):
+        from paper_1908_00814_amd import build
+        build.build()
+    return knng.load()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("knng_merge", "knng_expand", "knng_merge_bruteforce", "knng_exact_graph",
+                 "knng_last_error", "knng_version", "knng_opts_default"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert isinstance(getattr(lib, name), ctypes._CFuncPtr)
+
+
+def test_binding_covers_the_header():
+    from paper_1908_00814_amd import knng
+    assert sorted(knng.ENTRY_POINTS) == declared_functions()
+
+
+def test_host_queries(lib):
+    from paper_1908_00814_amd import knng
+    assert knng.version() == 10000
+    o = knng.opts()
+    assert abs(o.keep_ratio - 0.5) < 1e-7 and o.sample == 10 and o.max_rounds == 30
+    ws = knng.merge_workspace_size(500_000, 500_000, 128, 20, 20, 20)
+    # lists, rows and per-round buffers of 1M points: a little over 1 GB
+    assert 1.0e9 < ws < 2.0e9
+    assert knng.merge_workspace_size(500_000, 500_000, 128, 20, 20, 20, precision="bf16") > ws
+    # struct layouts agree with the header's field order
+    assert ctypes.sizeof(knng.Opts) == 32
+    assert ctypes.sizeof(knng.Set) == 24 and ctypes.sizeof(knng.Graph) == 32
