@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark: symmetric merge (S-Merge, Algorithm 1 of Zhao et al., "On the
+Merge of k-NN Graph") of two byte-valued cluster sets of 500,000 x 128 with
+approximate k=20 input graphs, merged to k=20 under squared l2, on one MI355X.
+
+A step is one whole merge call (layout, Divide/Append, all rounds of the
+repeat loop, Merge and Sort) with inputs already resident in HBM.  The value
+is points merged per second.  After the timed steps the script
+  - checks recall@10 of the merged graph on 1,000 sampled rows (exact FP64
+    ground truth; the metric is quoted at recall@10 >= 0.95),
+  - re-runs one merge with per-phase HIP-event timing to price the local-join
+    kernel against the HBM roofline,
+  - times the CPU oracle on a bounded sample of the same workload.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("points merged/s at recall@10≥0.95 (FP32 vs BF16-MFMA); "
+          "p50/p99 insert latency")
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def exact_kth_rows(X, rows, kk, device):
+    """FP64 distances of sampled rows to all rows and their exact kk-th
+    nearest distance (self excluded).  Integer rows: the GEMM form is exact."""
+    import torch
+    Xd = torch.from_numpy(X).to(device=device, dtype=torch.float64)
+    sq = (Xd * Xd).sum(1)
+    out_kth = []
+    D_rows = []
+    for lo in range(0, len(rows), 250):
+        r = torch.from_numpy(rows[lo:lo + 250]).to(device)
+        D = sq[r, None] + sq[None, :] - 2.0 * (Xd[r] @ Xd.T)
+        D[torch.arange(len(r), device=device), r] = float("inf")
+        out_kth.append(torch.topk(D, kk, dim=1, largest=False, sorted=True)[0][:, kk - 1])
+        D_rows.append(D)
+    return torch.cat(out_kth), torch.cat(D_rows)
+
+
+def recall_at10(ids, X, rows, device):
+    import torch
+    kth, D = exact_kth_rows(X, rows, 10, device)
+    got = torch.from_numpy(ids[rows, :10].astype(np.int64)).to(device)
+    dv = torch.gather(D, 1, got.clamp(min=0))
+    hits = ((dv <= kth[:, None]) & (got >= 0)).sum().item()
+    return hits / (len(rows) * 10)
+
+
+def join_roofline(st, n, d, k, s):
+    """Algorithmic bytes of the local-join launches of one merge and the
+    achieved rate over their summed duration."""
+    dp = (d + 3) // 4 * 4
+    rounds = st["rounds"]
+    members = sum(st["gathered"])
+    per_u_lists = 8 + 4 * s + 8 * s + 4 * k + 8 * s  # counts, samples, reservoirs
+    traffic = (members * (4 * dp + 8)                    # member vectors + worst
+               + rounds * n * per_u_lists                 # neighbourhood id lists
+               + st["insert_attempts"] * (8 * k + 16))   # list scan + CAS per insert
+    launches = max(st["join_launches"], 1)
+    secs = st["ms"]["join"] / 1e3
+    achieved = traffic / secs if secs > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "traffic": None,
+            "kernel": "k_join_f32<M_L2>", "launches": launches,
+            "algorithmic_bytes_per_launch": traffic / launches,
+            "avg_launch_ms": st["ms"]["join"] / launches}
+
+
+def cpu_baseline(n_per, k, s, delta, seed):
+    import oracle
+    import synth
+    from synth.graphs import approximate_graph
+    S1, S2 = synth.byte_cluster_sets(n_per, n_per, workload=2)
+    G1 = approximate_graph(S1, k, 0.9, device="cpu", stream=6)
+    G2 = approximate_graph(S2, k, 0.9, device="cpu", stream=7)
+    t0 = time.perf_counter()
+    oracle.smerge(S1, G1, S2, G2, k, "l2", sample=s, delta=delta, seed=seed)
+    dt = time.perf_counter() - t0
+    return {"value": 2 * n_per / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": (f"S-Merge of 2 x {n_per:,} points drawn from the same byte-valued "
+                       f"cluster law (d=128, k=20, s={s}, delta={delta}), approximate "
+                       f"input graphs built the same way; single-threaded C oracle, "
+                       f"{dt:.1f} s"),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-per", type=int, default=500_000)
+    ap.add_argument("--k", type=int, default=20)
+    ap.add_argument("--sample", type=int, default=20)
+    ap.add_argument("--delta", type=float, default=0.001)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--seed", type=int, default=2004)
+    ap.add_argument("--cpu-n", type=int, default=25_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              f"path is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from synth.graphs import approximate_graph
+    from paper_1908_00814_amd import knng
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    knng.load()
+    n1 = n2 = args.n_per
+    n, d, k = n1 + n2, 128, args.k
+    t = time.perf_counter()
+    S1, S2 = synth.byte_cluster_sets(n1, n2, workload=2)
+    log(f"[bench] points generated in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    G1 = approximate_graph(S1, k, 0.9, device=dev, stream=6)
+    G2 = approximate_graph(S2, k, 0.9, device=dev, stream=7)
+    log(f"[bench] input graphs (recall@20 ~0.9) built in {time.perf_counter() - t:.1f}s")
+    dS1, dS2 = torch.from_numpy(S1).to(dev), torch.from_numpy(S2).to(dev)
+    dG1 = (torch.from_numpy(G1[0]).to(dev), torch.from_numpy(G1[1]).to(dev))
+    dG2 = (torch.from_numpy(G2[0]).to(dev), torch.from_numpy(G2[1]).to(dev))
+    kw = dict(sample=args.sample, delta=args.delta, seed=args.seed, precision=args.precision)
+    ws_bytes = knng.merge_workspace_size(n1, n2, d, k, k, k, "l2", **kw)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    out = (torch.empty((n, k), dtype=torch.int32, device=dev),
+           torch.empty((n, k), dtype=torch.float32, device=dev))
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return knng.merge(dS1, dG1, dS2, dG2, k, "l2", stream=stream, workspace=ws, out=out,
+                          **kw)[2]
+
+    for i in range(args.warmup):
+        st = step()
+        log(f"[bench] warmup {i}: {st['rounds']} rounds")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed * 1e3 / max(args.steps, 1)
+    value = n * args.steps / elapsed
+    log(f"[bench] {args.steps} steps: {ms_step:.1f} ms/step, {value / 1e6:.2f} M points/s, "
+        f"{st['rounds']} rounds")
+
+    ids = out[0].cpu().numpy()
+    rows = synth.rng(2000 + 8).choice(n, 1000, replace=False)
+    X = np.concatenate([S1, S2])
+    rec = recall_at10(ids, X, rows, dev)
+    log(f"[bench] recall@10 on 1,000 sampled rows: {rec:.4f}")
+
+    pst = knng.merge(dS1, dG1, dS2, dG2, k, "l2", stream=stream, workspace=ws, out=out,
+                     profile=True, **kw)[2]
+    roof = join_roofline(pst, n, d, k, args.sample)
+    log(f"[bench] join: {roof['launches']} launches, {roof['avg_launch_ms']:.3f} ms avg, "
+        f"{roof['achieved']:.0f} GB/s algorithmic ({100 * roof['frac']:.1f}% of HBM peak); "
+        f"phases ms {json.dumps(pst['ms'])}")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16+f32",
+        "data": "synthetic",
+        "config": {"workload": "symmetric merge, 2 x 500,000 x d128 byte-valued clusters "
+                               "(1,000 centres, sigma 20), approximate k=20 input graphs "
+                               "(recall@20 ~0.9), merged to k=20, squared l2",
+                   "n1": n1, "n2": n2, "d": d, "k": k, "keep_ratio": 0.5,
+                   "sample": args.sample, "delta": args.delta, "seed": args.seed,
+                   "precision": args.precision},
+        "recall@10": rec,
+        "rounds": st["rounds"], "scanning_rate": st["evals"] / (n * (n - 1) / 2.0),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log(f"[bench] timing the CPU oracle on 2 x {args.cpu_n} points ...")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_n, k, args.sample, args.delta, args.seed)
+        log(f"[bench] oracle: {line['cpu_baseline']['value']:.0f} points/s")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

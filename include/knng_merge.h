@@ -134,6 +134,7 @@ typedef struct {
     int64_t evals;               /* C of the scanning rate: distance evaluations
                                     of Append/Initialize and of the local joins */
     int64_t rescored;            /* BF16 path: pairs re-evaluated in FP32 */
+    int64_t insert_attempts;     /* list inserts tried after the worst-entry screen */
     int64_t updates[KNNG_STATS_ROUNDS];  /* c: entries inserted and kept, per round */
     int64_t pairs[KNNG_STATS_ROUNDS];    /* joined pairs per round */
     int64_t gathered[KNNG_STATS_ROUNDS]; /* neighbourhood members staged per round */

@@ -400,6 +400,7 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
         stats->rounds = rounds;
         stats->evals = (int64_t)h[C_EVALS];
         stats->rescored = (int64_t)h[C_RESCORE];
+        stats->insert_attempts = (int64_t)h[C_ATTEMPT];
         stats->max_group = (int32_t)h[C_MAXG];
     }
     prof.collect(stats);

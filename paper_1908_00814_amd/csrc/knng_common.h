@@ -41,6 +41,7 @@ enum : int {
     C_RESCORE = 4,  // pairs rescored in FP32 (BF16 path)
     C_MAXG = 5,     // largest neighbourhood (max)
     C_ERR = 6,      // error bits
+    C_ATTEMPT = 7,  // list inserts attempted after the screen
     C_WORDS = 8,
 };
 
@@ -162,33 +163,62 @@ __device__ __forceinline__ bool cas64(uint64_t *p, uint64_t expect, uint64_t des
 
 constexpr int SPIN_BUDGET = 1 << 16;
 
-// Insert `key` into the unordered bounded set slots[0..cap): when the key is
-// below the current maximum and (if `dedupe`) no slot holds the same
-// (distance, id), the maximum slot is replaced.  Linearises at the CAS:
-// slot values only ever decrease, so the maximum read before a successful
-// CAS is still the maximum, and the final content of the set after any
-// interleaving of inserts is the `cap` smallest distinct keys offered
-// (together with what it held).  Returns true when the key went in.
-__device__ inline bool bounded_insert(uint64_t *slots, int cap, uint64_t key, bool dedupe,
-                                      uint64_t *err_word)
+__device__ __forceinline__ void atomic_min_u64(uint64_t *p, uint64_t v)
 {
-    uint64_t kid = key_strip(key);
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Insert `key` into the unordered bounded set slots[0..cap) (cap <= KB): when
+// the key is below the current maximum and (if `dedupe`) no slot holds the
+// same (distance, id), the maximum slot is replaced by a CAS.
+//
+// Correctness: slot values only ever decrease and are pairwise distinct, so if
+// the CAS on the slot that held the maximum M of the values read succeeds,
+// that slot held M throughout and every other slot is <= what was read <= M:
+// M was still the maximum (this holds even when some reads were older than
+// others).  A duplicate present at CAS time would have replaced a value > M in
+// some slot before that slot was read, so the read would have seen it.  Hence
+// every interleaving of inserts leaves the `cap` smallest distinct keys offered.
+//
+// Slots are loaded in batches (all 20 of a k = 20 list at once) before any
+// decision on them, one memory round trip per batch.  On success, `live_worst` (when given) is lowered to an
+// upper bound of the new maximum: max(key, largest value read besides M).
+template <int KB>
+__device__ inline bool bounded_insert(uint64_t *slots, int cap, uint64_t key, bool dedupe,
+                                      uint64_t *live_worst, uint64_t *err_word)
+{
+    constexpr int B = KB <= 16 ? KB : (KB == 32 ? 20 : 16);
+    const uint64_t kid = key_strip(key);
     for (int spin = 0; spin < SPIN_BUDGET; spin++) {
-        uint64_t mx = 0;
+        uint64_t mx = 0, second = 0;
         int mj = 0;
-        for (int j = 0; j < cap; j++) {
-            uint64_t v = ld_agent(slots + j);
-            if (dedupe && key_strip(v) == kid)
-                return false;
-            if (j == 0 || v > mx) {
-                mx = v;
-                mj = j;
+        bool dup = false;
+        for (int j0 = 0; j0 < cap; j0 += B) {
+            uint64_t v[B];
+#pragma unroll
+            for (int j = 0; j < B; j++)
+                v[j] = j0 + j < cap ? ld_agent(slots + j0 + j) : 0ull;
+#pragma unroll
+            for (int j = 0; j < B; j++) {
+                if (j0 + j < cap) {
+                    dup |= dedupe && key_strip(v[j]) == kid;
+                    if (v[j] > mx) {
+                        second = mx;
+                        mx = v[j];
+                        mj = j0 + j;
+                    } else if (v[j] > second) {
+                        second = v[j];
+                    }
+                }
             }
         }
-        if (key >= mx)
+        if (dup || key >= mx)
             return false;
-        if (cas64(slots + mj, mx, key))
+        if (cas64(slots + mj, mx, key)) {
+            if (live_worst)
+                atomic_min_u64(live_worst, key > second ? key_strip(key) : key_strip(second));
             return true;
+        }
     }
     atomicOr((unsigned long long *)err_word, (unsigned long long)ERR_SPIN);
     return false;

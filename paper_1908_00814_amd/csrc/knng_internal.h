@@ -21,7 +21,8 @@ struct Rows {
 // Parameters of one iteration of the merge loop.
 struct RoundArgs {
     uint64_t *L;        // n x k list words
-    uint64_t *worst;    // n: maximum word of each list at the round start
+    uint64_t *worst;    // n: upper bound of each list's maximum word (set by the
+                        // sampling step, lowered by the join's inserts)
     int32_t *new_f;     // n x s
     int32_t *old_f;     // n x k
     int32_t *cnt_f;     // n x 2: (#new_f, #old_f)

@@ -9,14 +9,21 @@
 //   S-Merge: p and q from different sets (Algorithm 1);
 //   J-Merge: not both from the built set S1 (Algorithm 2).
 // l = m(p, q) is offered to both lists (UpdateNN in both directions) through
-// the lock-free bounded insert; a pair is first screened against the worst
-// entry each list had at the start of the round (the worst only decreases
-// during a round, so the screen never drops an edge that could stay).
+// the lock-free bounded insert; a pair is first screened against an upper
+// bound of each list's worst entry (set at the round start, lowered after
+// every successful insert, read when u's neighbourhood is formed).  The worst
+// entry only decreases during a round, so the screen never drops an edge that
+// could stay.
 //
-// One workgroup of 256 threads owns one u at a time (grid-stride over u).
-// The member vectors are staged in LDS in chunks of CH coordinates; each
-// thread accumulates up to PPT pairs in registers across chunks, so every
-// pair is evaluated in the canonical ascending-coordinate order.
+// Layout.  One wave owns one u at a time (4 independent waves per workgroup,
+// no workgroup barriers).  The members are placed in LDS in four regions, each
+// starting at a multiple of 4:  [ newA | oldA | newB | oldB ]  (A = first set,
+// B = second set).  The admitted pairs are then dense rectangles:
+//   R1 = newA x (newB u oldB)      R2 = newB x oldA
+//   R3 = newB x (newB u oldB), upper triangle on newB x newB (J-Merge only)
+// Coordinates are staged chunk by chunk, transposed ([coordinate][member]),
+// and each lane accumulates 2 x 4 register tiles of pairs in ascending
+// coordinate order, so every distance is the canonical FP32 value.
 #include "knng_common.h"
 #include "knng_internal.h"
 
@@ -24,187 +31,329 @@ namespace knng {
 
 namespace {
 
-constexpr int JOIN_THREADS = 256;
-constexpr int PPT = 4;  // pairs per thread per pass
+constexpr int JOIN_WAVES = 4;
+constexpr int CH = 16;         // coordinates per staged chunk
+constexpr int TPL = 1;         // 2x4 tiles per lane per batch
+constexpr int OLD_CAP = MAX_K + MAX_S;  // OLD candidates per neighbourhood
+constexpr int QCAP = 320;      // insert queue entries per wave
 
 __device__ __forceinline__ bool res_empty(uint64_t w) { return (uint32_t)w >= 0x40000000u; }
+__host__ __device__ __forceinline__ int r4(int x) { return (x + 3) & ~3; }
 
-struct JoinSmem {
-    int32_t grp[MAX_G];
-    uint64_t gworst[MAX_G];
-    int32_t cand[MAX_G];
-    int nn, ng, np, nc;
-    unsigned long long pairs, gathered;
-    int maxg;
+struct Regions {
+    int nA, oA, nB, oB;           // member counts
+    int offOA, offNB, offOB, GP;  // region starts and padded total
 };
 
-template <int METRIC>
-__global__ __launch_bounds__(JOIN_THREADS) void k_join_f32(Rows R, RoundArgs a, int CH,
-                                                           int g_max, int p_max)
+// tile t -> (row start, column start, rectangle); false past the last tile
+__device__ __forceinline__ bool tile_of(int t, const Regions &g, int joint, int &r0, int &c0,
+                                        int &reg)
 {
-    extern __shared__ float dyn[];
-    __shared__ JoinSmem sm;
-    float *vec = dyn;                                                   // g_max x (CH+1)
-    uint16_t *plist = reinterpret_cast<uint16_t *>(dyn + g_max * (CH + 1));  // p_max
-    const int tid = threadIdx.x;
-    const int s = a.s, k = a.k;
-    if (tid == 0) {
-        sm.pairs = 0;
-        sm.gathered = 0;
-        sm.maxg = 0;
+    const int colsB = g.GP - g.offNB;  // newB u oldB, padded
+    const int rt1 = (g.nA + 1) / 2, ct1 = colsB / 4;
+    const int T1 = rt1 * ct1;
+    if (t < T1) {
+        r0 = 2 * (t / ct1);
+        c0 = g.offNB + 4 * (t % ct1);
+        reg = 1;
+        return true;
     }
-    for (int64_t u = blockIdx.x; u < a.n; u += gridDim.x) {
-        __syncthreads();
-        if (tid == 0) {
-            sm.nn = 0;
-            sm.ng = 0;
-            sm.np = 0;
-            sm.nc = 0;
+    t -= T1;
+    const int rt2 = (g.nB + 1) / 2, ct2 = r4(g.oA) / 4;
+    const int T2 = rt2 * ct2;
+    if (t < T2) {
+        r0 = g.offNB + 2 * (t / ct2);
+        c0 = g.offOA + 4 * (t % ct2);
+        reg = 2;
+        return true;
+    }
+    t -= T2;
+    if (joint && t < rt2 * ct1) {
+        r0 = g.offNB + 2 * (t / ct1);
+        c0 = g.offNB + 4 * (t % ct1);
+        reg = 3;
+        return true;
+    }
+    return false;
+}
+
+// Drain a wave's insert queue: every entry is first re-checked against the
+// live worst bound of its target list (one 8-byte load), the survivors are
+// inserted.  Returns the number of inserts attempted (wave-uniform).
+template <int KB>
+__device__ inline int drain_queue(const uint64_t *qkey, const int32_t *qdst, int qn,
+                                  const RoundArgs &a)
+{
+    int attempted = 0;
+    for (int e0 = 0; e0 < qn; e0 += WAVE) {
+        const int e = e0 + lane_id();
+        bool go = false;
+        uint64_t key = 0;
+        int32_t dst = 0;
+        if (e < qn) {
+            key = qkey[e];
+            dst = qdst[e];
+            go = key < ld_agent(a.worst + dst);
         }
-        __syncthreads();
-        // ---- NEW group: forward NEW sample and reverse NEW sources
+        attempted += __popcll(__ballot(go));
+        if (go)
+            bounded_insert<KB>(a.L + (int64_t)dst * a.k, a.k, key, true, a.worst + dst,
+                               a.ctr + C_ERR);
+    }
+    return attempted;
+}
+
+template <int METRIC, int KB, int MAX_UNITS>
+__global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join(Rows R, RoundArgs a, int GS,
+                                                            int wave_bytes)
+{
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const int lane = lane_id();
+    const int w = threadIdx.x / WAVE;
+    unsigned char *base = dyn + (size_t)w * wave_bytes;
+    float *vecT = reinterpret_cast<float *>(base);                    // CH x GS
+    uint64_t *gw = reinterpret_cast<uint64_t *>(base + CH * GS * 4);  // GS
+    int32_t *grp = reinterpret_cast<int32_t *>(gw + GS);              // GS
+    float *gnorm = reinterpret_cast<float *>(grp + GS);               // GS (cosine)
+    int32_t *tnew = reinterpret_cast<int32_t *>(gnorm + GS);          // 2 MAX_S
+    int32_t *told = tnew + 2 * MAX_S;    // raw OLD candidates     (OLD_CAP)
+    int32_t *toldA = told + OLD_CAP;     // accepted OLD, first set  (OLD_CAP)
+    int32_t *toldB = toldA + OLD_CAP;    // accepted OLD, second set (OLD_CAP)
+    uint64_t *qkey = reinterpret_cast<uint64_t *>(toldB + OLD_CAP);  // QCAP insert keys
+    int32_t *qdst = reinterpret_cast<int32_t *>(qkey + QCAP);       // QCAP target rows
+
+    const int s = a.s, k = a.k;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t n_pairs = 0, n_gather = 0, n_attempt = 0;
+    int maxg = 0;
+    const int64_t nwaves = (int64_t)gridDim.x * JOIN_WAVES;
+    for (int64_t u = (int64_t)blockIdx.x * JOIN_WAVES + w; u < a.n; u += nwaves) {
+        __builtin_amdgcn_wave_barrier();
+        // ---- NEW candidates: forward NEW sample (lanes < s), reverse NEW (s..2s)
         const int cnt_new = a.cnt_f[2 * u], cnt_old = a.cnt_f[2 * u + 1];
         int32_t cid = -1;
-        if (tid < s) {
-            if (tid < cnt_new)
-                cid = a.new_f[u * s + tid];
-        } else if (tid < 2 * s) {
-            uint64_t w = a.rnew[u * s + (tid - s)];
-            if (!res_empty(w))
-                cid = (int32_t)(uint32_t)w;
+        if (lane < s) {
+            if (lane < cnt_new)
+                cid = a.new_f[u * s + lane];
+        } else if (lane < 2 * s) {
+            uint64_t wv = a.rnew[u * s + (lane - s)];
+            if (!res_empty(wv))
+                cid = (int32_t)(uint32_t)wv;
         }
-        if (tid < 2 * s)
-            sm.cand[tid] = cid;
-        __syncthreads();
-        if (tid < 2 * s && cid >= 0) {
-            bool dup = false;
-            for (int j = 0; j < tid; j++)
-                dup |= sm.cand[j] == cid;
-            if (!dup)
-                sm.grp[atomicAdd(&sm.nn, 1)] = cid;
+        bool keep = cid >= 0;
+        for (int j = 0; j < 2 * s; j++) {
+            int32_t o = __shfl(cid, j, WAVE);
+            keep = keep && !(j < lane && o == cid);
         }
-        __syncthreads();
-        const int nn = sm.nn;
-        if (nn == 0)
+        const bool isA = cid < a.n1;
+        const uint64_t mA = __ballot(keep && isA), mB = __ballot(keep && !isA);
+        const int nA = __popcll(mA), nB = __popcll(mB);
+        if (nA + nB == 0)
             continue;  // no NEW member: no pair to join at u
-        // ---- OLD group: forward OLD sample and reverse OLD sources, minus NEW
+        if (keep)
+            tnew[isA ? __popcll(mA & below) : nA + __popcll(mB & below)] = cid;
+        __builtin_amdgcn_wave_barrier();
+        // ---- OLD candidates: forward OLD (c < k), reverse OLD (k <= c < k+s),
+        //      minus NEW members and repeats
         const int nco = k + s;
-        cid = -1;
-        if (tid < k) {
-            if (tid < cnt_old)
-                cid = a.old_f[u * k + tid];
-        } else if (tid < nco) {
-            uint64_t w = a.rold[u * s + (tid - k)];
-            if (!res_empty(w))
-                cid = (int32_t)(uint32_t)w;
-        }
-        if (tid < nco)
-            sm.cand[tid] = cid;
-        __syncthreads();
-        if (tid < nco && cid >= 0) {
-            bool drop = false;
-            for (int j = 0; j < nn; j++)
-                drop |= sm.grp[j] == cid;
-            for (int j = 0; j < tid; j++)
-                drop |= sm.cand[j] == cid;
-            if (!drop)
-                sm.grp[nn + atomicAdd(&sm.ng, 1)] = cid;
-        }
-        __syncthreads();
-        const int G = nn + sm.ng;
-        if (tid < G)
-            sm.gworst[tid] = a.worst[sm.grp[tid]];
-        // ---- admitted pairs (a in NEW, a < b): compacted list in LDS
-        const int64_t p_all = (int64_t)nn * (G - 1) - (int64_t)nn * (nn - 1) / 2;
-        for (int64_t idx = tid; idx < p_all; idx += JOIN_THREADS) {
-            int ai = 0;
-            int64_t off = 0;
-            while (off + (G - 1 - ai) <= idx) {
-                off += G - 1 - ai;
-                ai++;
+        int oA = 0, oB = 0;
+        for (int pass = 0; pass * WAVE < nco; pass++) {
+            const int c = pass * WAVE + lane;
+            int32_t oc = -1;
+            if (c < k) {
+                if (c < cnt_old)
+                    oc = a.old_f[u * k + c];
+            } else if (c < nco) {
+                uint64_t wv = a.rold[u * s + (c - k)];
+                if (!res_empty(wv))
+                    oc = (int32_t)(uint32_t)wv;
             }
-            int bi = ai + 1 + (int)(idx - off);
-            int32_t p = sm.grp[ai], q = sm.grp[bi];
-            bool p1 = p < a.n1, q1 = q < a.n1;
-            bool ok = a.joint ? !(p1 && q1) : (p1 != q1);
+            if (c < nco)
+                told[c] = oc;
+            __builtin_amdgcn_wave_barrier();
+            bool ok = oc >= 0;
+            for (int j = 0; j < nA + nB && ok; j++)
+                ok = tnew[j] != oc;
+            for (int j = 0; j < c && ok; j++)
+                ok = told[j] != oc;
+            const bool oa = oc < a.n1;
+            const uint64_t moA = __ballot(ok && oa), moB = __ballot(ok && !oa);
             if (ok) {
-                int pos = atomicAdd(&sm.np, 1);
-                plist[pos] = (uint16_t)((ai << 8) | bi);
+                if (oa)
+                    toldA[oA + __popcll(moA & below)] = oc;
+                else
+                    toldB[oB + __popcll(moB & below)] = oc;
             }
+            oA += __popcll(moA);
+            oB += __popcll(moB);
+            __builtin_amdgcn_wave_barrier();
         }
-        __syncthreads();
-        const int np = sm.np;
-        if (tid == 0) {
-            sm.pairs += np;
-            sm.gathered += G;
-            sm.maxg = G > sm.maxg ? G : sm.maxg;
+        // ---- regions [newA | oldA | newB | oldB], each start a multiple of 4
+        Regions g;
+        g.nA = nA;
+        g.oA = oA;
+        g.nB = nB;
+        g.oB = oB;
+        g.offOA = r4(nA);
+        g.offNB = g.offOA + r4(oA);
+        g.offOB = g.offNB + r4(nB);
+        g.GP = g.offOB + r4(oB);
+        const int G = nA + oA + nB + oB;
+        for (int slot = lane; slot < g.GP; slot += WAVE) {
+            int32_t id = -1;
+            if (slot < nA)
+                id = tnew[slot];
+            else if (slot >= g.offOA && slot < g.offOA + oA)
+                id = toldA[slot - g.offOA];
+            else if (slot >= g.offNB && slot < g.offNB + nB)
+                id = tnew[nA + (slot - g.offNB)];
+            else if (slot >= g.offOB && slot < g.offOB + oB)
+                id = toldB[slot - g.offOB];
+            grp[slot] = id;
+            gw[slot] = id >= 0 ? a.worst[id] : 0ull;
+            if (METRIC == M_COS)
+                gnorm[slot] = id >= 0 ? R.norm[id] : 1.0f;
         }
-        // ---- distances, PPT pairs per thread per pass
-        for (int base = 0; base < np; base += JOIN_THREADS * PPT) {
-            float acc[PPT];
-            int pa[PPT], pb[PPT];
+        __builtin_amdgcn_wave_barrier();
+        n_gather += (uint64_t)G;
+        maxg = G > maxg ? G : maxg;
+
+        // ---- 2x4 tiles of the admitted rectangles
+        const int colsB = g.GP - g.offNB;
+        int T = ((nA + 1) / 2) * (colsB / 4) + ((nB + 1) / 2) * (r4(oA) / 4);
+        if (a.joint)
+            T += ((nB + 1) / 2) * (colsB / 4);
+        constexpr int q4 = CH / 4;
+        const int units = g.GP * q4;  // float4 units per staged chunk
+        for (int tb = 0; tb < T; tb += WAVE * TPL) {
+            float acc[TPL][2][4];
+            int tr0[TPL], tc0[TPL], treg[TPL];
+            bool tv[TPL];
 #pragma unroll
-            for (int j = 0; j < PPT; j++) {
-                acc[j] = 0.0f;
-                int pi = base + tid + j * JOIN_THREADS;
-                uint16_t e = pi < np ? plist[pi] : (uint16_t)0xFFFF;
-                pa[j] = pi < np ? (e >> 8) : -1;
-                pb[j] = pi < np ? (e & 0xFF) : -1;
+            for (int i = 0; i < TPL; i++) {
+                tv[i] = tile_of(tb + i * WAVE + lane, g, a.joint, tr0[i], tc0[i], treg[i]);
+#pragma unroll
+                for (int x = 0; x < 2; x++)
+#pragma unroll
+                    for (int y = 0; y < 4; y++)
+                        acc[i][x][y] = 0.0f;
             }
             for (int c0 = 0; c0 < R.dp; c0 += CH) {
+                // chunk -> LDS, transposed ([coordinate][member])
+                __builtin_amdgcn_wave_barrier();
+                float4 pre[MAX_UNITS];
+#pragma unroll
+                for (int j = 0; j < MAX_UNITS; j++) {
+                    const int e = lane + j * WAVE;
+                    pre[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (e < units) {
+                        const int m = e / q4, q = e - m * q4;
+                        const int32_t id = grp[m];
+                        if (id >= 0 && c0 + 4 * q < R.dp)
+                            pre[j] = *reinterpret_cast<const float4 *>(R.x + (int64_t)id * R.dp +
+                                                                       c0 + 4 * q);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < MAX_UNITS; j++) {
+                    const int e = lane + j * WAVE;
+                    if (e < units) {
+                        const int m = e / q4, q = e - m * q4;
+                        vecT[(4 * q + 0) * GS + m] = pre[j].x;
+                        vecT[(4 * q + 1) * GS + m] = pre[j].y;
+                        vecT[(4 * q + 2) * GS + m] = pre[j].z;
+                        vecT[(4 * q + 3) * GS + m] = pre[j].w;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
                 const int cw = R.dp - c0 < CH ? R.dp - c0 : CH;
-                const int q4 = cw / 4;
-                __syncthreads();
-                for (int e = tid; e < G * q4; e += JOIN_THREADS) {
-                    int m = e / q4, qq = e - m * q4;
-                    float4 v = *reinterpret_cast<const float4 *>(R.x + (int64_t)sm.grp[m] * R.dp +
-                                                                  c0 + 4 * qq);
-                    float *dst = vec + m * (CH + 1) + 4 * qq;
-                    dst[0] = v.x;
-                    dst[1] = v.y;
-                    dst[2] = v.z;
-                    dst[3] = v.w;
-                }
-                __syncthreads();
 #pragma unroll
-                for (int j = 0; j < PPT; j++) {
-                    if (pa[j] < 0)
+                for (int i = 0; i < TPL; i++) {
+                    if (!tv[i])
                         continue;
-                    const float *x = vec + pa[j] * (CH + 1);
-                    const float *y = vec + pb[j] * (CH + 1);
-                    float t_acc = acc[j];
-                    for (int t = 0; t < cw; t++)
-                        t_acc = canon_step<METRIC>(t_acc, x[t], y[t]);
-                    acc[j] = t_acc;
-                }
-            }
-            // ---- screen and insert in both directions (UpdateNN)
+#pragma unroll 2
+                    for (int t = 0; t < cw; t++) {
+                        const float2 xr =
+                            *reinterpret_cast<const float2 *>(vecT + t * GS + tr0[i]);
+                        const float4 xc =
+                            *reinterpret_cast<const float4 *>(vecT + t * GS + tc0[i]);
+                        const float xrs[2] = {xr.x, xr.y};
+                        const float xcs[4] = {xc.x, xc.y, xc.z, xc.w};
 #pragma unroll
-            for (int j = 0; j < PPT; j++) {
-                if (pa[j] < 0)
-                    continue;
-                int32_t p = sm.grp[pa[j]], q = sm.grp[pb[j]];
-                float na = 0.0f, nb = 0.0f;
-                if constexpr (METRIC == M_COS) {
-                    na = R.norm[p];
-                    nb = R.norm[q];
+                        for (int x = 0; x < 2; x++)
+#pragma unroll
+                            for (int y = 0; y < 4; y++)
+                                acc[i][x][y] = canon_step<METRIC>(acc[i][x][y], xrs[x], xcs[y]);
+                    }
                 }
-                float l = canon_finish<METRIC>(acc[j], na, nb);
-                uint64_t kp = make_key(l, (uint32_t)q, F_NEW | F_FRESH);
-                uint64_t kq = make_key(l, (uint32_t)p, F_NEW | F_FRESH);
-                if (kp < sm.gworst[pa[j]])
-                    bounded_insert(a.L + (int64_t)p * k, k, kp, true, a.ctr + C_ERR);
-                if (kq < sm.gworst[pb[j]])
-                    bounded_insert(a.L + (int64_t)q * k, k, kq, true, a.ctr + C_ERR);
             }
+            // ---- screen; survivors go through the wave's insert queue, drained
+            //      by all lanes together (UpdateNN in both directions)
+            int qn = 0;
+#pragma unroll
+            for (int i = 0; i < TPL; i++) {
+#pragma unroll
+                for (int x = 0; x < 2; x++) {
+                    const int r = tr0[i] + x;
+#pragma unroll
+                    for (int y = 0; y < 4; y++) {
+                        const int c = tc0[i] + y;
+                        const int32_t p = tv[i] ? grp[r] : -1;
+                        const int32_t q = tv[i] ? grp[c] : -1;
+                        const bool valid = p >= 0 && q >= 0 && !(treg[i] == 3 && c <= r);
+                        n_pairs += valid;
+                        float na = 0.0f, nb = 0.0f;
+                        if (METRIC == M_COS && valid) {
+                            na = gnorm[r];
+                            nb = gnorm[c];
+                        }
+                        const float l = canon_finish<METRIC>(acc[i][x][y], na, nb);
+                        const uint64_t kp = make_key(l, (uint32_t)q, F_NEW | F_FRESH);
+                        const uint64_t kq = make_key(l, (uint32_t)p, F_NEW | F_FRESH);
+                        const bool vp = valid && kp < gw[r];
+                        const bool vq = valid && kq < gw[c];
+                        const uint64_t mp = __ballot(vp), mq = __ballot(vq);
+                        if (vp) {
+                            const int pos = qn + __popcll(mp & below);
+                            qkey[pos] = kp;
+                            qdst[pos] = p;
+                        }
+                        qn += __popcll(mp);
+                        if (vq) {
+                            const int pos = qn + __popcll(mq & below);
+                            qkey[pos] = kq;
+                            qdst[pos] = q;
+                        }
+                        qn += __popcll(mq);
+                        if (qn > QCAP - 2 * WAVE) {
+                            __builtin_amdgcn_wave_barrier();
+                            n_attempt += drain_queue<KB>(qkey, qdst, qn, a);
+                            qn = 0;
+                            __builtin_amdgcn_wave_barrier();
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            n_attempt += drain_queue<KB>(qkey, qdst, qn, a);
+            __builtin_amdgcn_wave_barrier();
         }
     }
-    __syncthreads();
-    if (tid == 0) {
-        atomicAdd((unsigned long long *)(a.ctr + C_PAIRS), sm.pairs);
-        atomicAdd((unsigned long long *)(a.ctr + C_EVALS), sm.pairs);
-        atomicAdd((unsigned long long *)(a.ctr + C_GATHER), sm.gathered);
-        atomicMax((unsigned long long *)(a.ctr + C_MAXG), (unsigned long long)sm.maxg);
+    // ---- counters: one atomic per wave
+    uint64_t tp = n_pairs, ta = n_attempt;  // pairs: per lane; attempts: per wave
+    for (int o = WAVE / 2; o > 0; o >>= 1)
+        tp += __shfl_xor(tp, o, WAVE);
+    if (lane == 0) {
+        if (tp) {
+            atomicAdd((unsigned long long *)(a.ctr + C_PAIRS), (unsigned long long)tp);
+            atomicAdd((unsigned long long *)(a.ctr + C_EVALS), (unsigned long long)tp);
+        }
+        if (n_gather)
+            atomicAdd((unsigned long long *)(a.ctr + C_GATHER), (unsigned long long)n_gather);
+        if (ta)
+            atomicAdd((unsigned long long *)(a.ctr + C_ATTEMPT), (unsigned long long)ta);
+        if (maxg)
+            atomicMax((unsigned long long *)(a.ctr + C_MAXG), (unsigned long long)maxg);
     }
 }
 
@@ -213,19 +362,20 @@ __global__ __launch_bounds__(JOIN_THREADS) void k_join_f32(Rows R, RoundArgs a, 
 hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, hipStream_t st)
 {
     (void)bf16;
+    // member slots: four regions, each rounded up to a multiple of 4 (+12),
+    // plus 4 to spread the LDS banks of consecutive coordinate rows
     const int g_max = 3 * a.s + a.k;
-    const int nn_max = 2 * a.s;
-    const int p_max = nn_max * (g_max - 1) - nn_max * (nn_max - 1) / 2;
-    // chunk of coordinates staged per pass: at most ~40 KB of member vectors
-    int ch = (40 * 1024 / 4) / g_max - 1;
-    ch = ch / 4 * 4;
-    if (ch > R.dp)
-        ch = R.dp;
-    if (ch < 4)
-        ch = 4;
-    size_t shmem = (size_t)g_max * (ch + 1) * 4 + (size_t)p_max * 2;
-    shmem = (shmem + 15) / 16 * 16;
-    int64_t grid = a.n < 8192 ? a.n : 8192;
+    const int GS = r4(g_max) + 16;
+    int wave_bytes = CH * GS * 4 + GS * 8 + GS * 4 + GS * 4 + (2 * MAX_S + 3 * OLD_CAP) * 4 +
+                     QCAP * 12;
+    wave_bytes = (wave_bytes + 15) / 16 * 16;
+    const size_t shmem = (size_t)wave_bytes * JOIN_WAVES;
+    const int units = GS * (CH / 4);
+    if (units > 12 * WAVE)
+        return hipErrorInvalidValue;  // neighbourhood larger than the staging bound
+    const bool small = units <= 8 * WAVE;
+    const int64_t waves = a.n < 32768 ? a.n : 32768;
+    int64_t grid = (waves + JOIN_WAVES - 1) / JOIN_WAVES;
     if (grid < 1)
         grid = 1;
     auto go = [&](auto kern) -> hipError_t {
@@ -236,12 +386,22 @@ hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, 
             if (e != hipSuccess)
                 return e;
         }
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(JOIN_THREADS), shmem, st, R, a, ch,
-                           g_max, p_max);
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(JOIN_WAVES * WAVE), shmem, st, R, a,
+                           GS, wave_bytes);
         return hipSuccess;
     };
-    hipError_t e = metric == M_L2 ? go(k_join_f32<M_L2>)
-                                  : (metric == M_COS ? go(k_join_f32<M_COS>) : go(k_join_f32<M_L1>));
+    auto by_metric = [&](auto l2, auto cs, auto l1) -> hipError_t {
+        return metric == M_L2 ? go(l2) : (metric == M_COS ? go(cs) : go(l1));
+    };
+#define KNNG_JOIN_SET(KBV, MU) by_metric(k_join<M_L2, KBV, MU>, k_join<M_COS, KBV, MU>, k_join<M_L1, KBV, MU>)
+    hipError_t e;
+    if (a.k <= 16)
+        e = small ? KNNG_JOIN_SET(16, 8) : KNNG_JOIN_SET(16, 12);
+    else if (a.k <= 32)
+        e = small ? KNNG_JOIN_SET(32, 8) : KNNG_JOIN_SET(32, 12);
+    else
+        e = small ? KNNG_JOIN_SET(64, 8) : KNNG_JOIN_SET(64, 12);
+#undef KNNG_JOIN_SET
     if (e != hipSuccess)
         return e;
     return hipGetLastError();

@@ -159,9 +159,11 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
     const int lane = lane_id();
     const int w = threadIdx.x / WAVE;
     int32_t *picked = picked_all[w];
-    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
-    if (i >= a.n)
-        return;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    uint64_t evals = 0;
+    for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE; i < a.n;
+         i += nwaves) {
+    __builtin_amdgcn_wave_barrier();
     const bool has_list = !a.joint || i < a.n1;
     int first, m;
     uint32_t N;
@@ -253,8 +255,12 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
         }
         a.L[i * a.k + lane] = key;
     }
-    if (lane == 0 && m > 0)
-        atomicAdd((unsigned long long *)(a.ctr + C_EVALS), (unsigned long long)m);
+    evals += (uint64_t)m;
+    __builtin_amdgcn_wave_barrier();
+    }
+    // one atomic per wave for the distance evaluations of all its rows
+    if (lane == 0 && evals)
+        atomicAdd((unsigned long long *)(a.ctr + C_EVALS), (unsigned long long)evals);
 }
 
 // one wave per row: top k of the list and the rear part, deduplicated
@@ -374,7 +380,8 @@ hipError_t launch_prep_input(const Rows &R, int metric, int64_t row0, int64_t nr
 
 hipError_t launch_init(const Rows &R, int metric, const InitArgs &a, hipStream_t st)
 {
-    dim3 grid(grid_for(a.n, 4)), block(256);
+    unsigned g = grid_for(a.n, 4);
+    dim3 grid(g > 8192u ? 8192u : g), block(256);
     if (metric == M_L2)
         hipLaunchKernelGGL(k_init<M_L2>, grid, block, 0, st, R, a);
     else if (metric == M_COS)

@@ -15,57 +15,60 @@ namespace knng {
 
 namespace {
 
-// one wave per row (k <= 64 lanes)
+// one wave per row (k <= 64 lanes), grid-stride over rows; the FRESH count is
+// accumulated per wave and added once
 __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
 {
     const int lane = lane_id();
-    const int64_t u = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
-    if (u >= a.n)
-        return;
-    const bool act = lane < a.k;
-    uint64_t v = act ? a.L[u * a.k + lane] : ~0ull;
-    const bool empty = !act || key_empty(v);
-    const bool fresh = !empty && (v & F_FRESH);
-    const bool isnew = !empty && (v & F_NEW);
-    const bool isold = !empty && !(v & F_NEW);
-    const uint32_t id = key_id(v);
-    uint64_t pk = ~0ull;
-    if (isnew) {
-        uint64_t h = hash5(a.seed, TAG_FWD, (uint64_t)a.round, (uint64_t)u, (uint64_t)id);
-        pk = ((h >> 32) << 32) | id;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    int fresh_total = 0;
+    for (int64_t u = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE; u < a.n;
+         u += nwaves) {
+        const bool act = lane < a.k;
+        uint64_t v = act ? a.L[u * a.k + lane] : ~0ull;
+        const bool empty = !act || key_empty(v);
+        const bool fresh = !empty && (v & F_FRESH);
+        const bool isnew = !empty && (v & F_NEW);
+        const bool isold = !empty && !(v & F_NEW);
+        const uint32_t id = key_id(v);
+        uint64_t pk = ~0ull;
+        if (isnew) {
+            uint64_t h = hash5(a.seed, TAG_FWD, (uint64_t)a.round, (uint64_t)u, (uint64_t)id);
+            pk = ((h >> 32) << 32) | id;
+        }
+        int rank = 0, nnew = 0;
+        for (int j = 0; j < a.k; j++) {
+            uint64_t o = __shfl(pk, j, WAVE);
+            rank += o < pk;
+            nnew += o != ~0ull;
+        }
+        const bool sampled = isnew && rank < a.s;
+        if (sampled)
+            a.new_f[u * a.s + rank] = (int32_t)id;
+        uint64_t nv = v & ~(uint64_t)F_FRESH;
+        if (sampled)
+            nv &= ~(uint64_t)F_NEW;
+        if (act && !empty && nv != v)
+            a.L[u * a.k + lane] = nv;
+        const uint64_t below = (1ull << lane) - 1ull;
+        const uint64_t om = __ballot(isold);
+        if (isold)
+            a.old_f[u * a.k + __popcll(om & below)] = (int32_t)id;
+        uint64_t wv = act ? (empty ? v : key_strip(nv)) : 0ull;
+        wv = wave_max_u64(wv);
+        fresh_total += wave_sum((int)fresh);
+        if (lane == 0) {
+            a.worst[u] = wv;
+            a.cnt_f[2 * u] = nnew < a.s ? nnew : a.s;
+            a.cnt_f[2 * u + 1] = __popcll(om);
+        }
+        if (lane < a.s) {
+            a.rnew[u * a.s + lane] = empty_key(lane);
+            a.rold[u * a.s + lane] = empty_key(lane);
+        }
     }
-    int rank = 0, nnew = 0;
-    for (int j = 0; j < a.k; j++) {
-        uint64_t o = __shfl(pk, j, WAVE);
-        rank += o < pk;
-        nnew += o != ~0ull;
-    }
-    const bool sampled = isnew && rank < a.s;
-    if (sampled)
-        a.new_f[u * a.s + rank] = (int32_t)id;
-    uint64_t nv = v & ~(uint64_t)F_FRESH;
-    if (sampled)
-        nv &= ~(uint64_t)F_NEW;
-    if (act && !empty && nv != v)
-        a.L[u * a.k + lane] = nv;
-    const uint64_t below = (1ull << lane) - 1ull;
-    const uint64_t om = __ballot(isold);
-    if (isold)
-        a.old_f[u * a.k + __popcll(om & below)] = (int32_t)id;
-    uint64_t wv = act ? (empty ? v : key_strip(nv)) : 0ull;
-    wv = wave_max_u64(wv);
-    int nfresh = wave_sum((int)fresh);
-    if (lane == 0) {
-        a.worst[u] = wv;
-        a.cnt_f[2 * u] = nnew < a.s ? nnew : a.s;
-        a.cnt_f[2 * u + 1] = __popcll(om);
-        if (nfresh)
-            atomicAdd((unsigned long long *)(a.ctr + C_FRESH), (unsigned long long)nfresh);
-    }
-    if (lane < a.s) {
-        a.rnew[u * a.s + lane] = empty_key(lane);
-        a.rold[u * a.s + lane] = empty_key(lane);
-    }
+    if (lane == 0 && fresh_total)
+        atomicAdd((unsigned long long *)(a.ctr + C_FRESH), (unsigned long long)fresh_total);
 }
 
 // one thread per sampled edge u -> v
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
         }
         uint64_t h = hash5(a.seed, tag, (uint64_t)a.round, (uint64_t)v, (uint64_t)u);
         uint64_t key = ((h >> 32) << 32) | (uint64_t)u;
-        bounded_insert(res + (int64_t)v * a.s, a.s, key, false, a.ctr + C_ERR);
+        bounded_insert<MAX_S>(res + (int64_t)v * a.s, a.s, key, false, nullptr, a.ctr + C_ERR);
     }
 }
 
@@ -127,7 +130,7 @@ inline unsigned grid_for(int64_t items, int per_block, unsigned cap)
 
 hipError_t launch_sample(const RoundArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sample, dim3(grid_for(a.n, 4, 0x7FFFFFFFu)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_sample, dim3(grid_for(a.n, 4, 8192)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

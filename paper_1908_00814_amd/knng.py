@@ -46,6 +46,7 @@ class Graph(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("max_group", ctypes.c_int32),
                 ("evals", ctypes.c_int64), ("rescored", ctypes.c_int64),
+                ("insert_attempts", ctypes.c_int64),
                 ("updates", ctypes.c_int64 * STATS_ROUNDS),
                 ("pairs", ctypes.c_int64 * STATS_ROUNDS),
                 ("gathered", ctypes.c_int64 * STATS_ROUNDS),
@@ -57,7 +58,8 @@ class Stats(ctypes.Structure):
     def to_dict(self):
         r = min(self.rounds, STATS_ROUNDS)
         return {"rounds": self.rounds, "max_group": self.max_group, "evals": self.evals,
-                "rescored": self.rescored, "c": list(self.updates[:r]),
+                "rescored": self.rescored, "insert_attempts": self.insert_attempts,
+                "c": list(self.updates[:r]),
                 "pairs": list(self.pairs[:r]), "gathered": list(self.gathered[:r]),
                 "ms": {"prep": self.ms_prep, "init": self.ms_init, "sample": self.ms_sample,
                        "reverse": self.ms_reverse, "join": self.ms_join,
