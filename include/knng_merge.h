@@ -135,6 +135,8 @@ typedef struct {
                                     of Append/Initialize and of the local joins */
     int64_t rescored;            /* BF16 path: pairs re-evaluated in FP32 */
     int64_t insert_attempts;     /* list inserts tried after the worst-entry screen */
+    int64_t screen_violations;   /* BF16 path: rescored pairs whose bf16 distance left
+                                    the proven error margin (0 unless the bound fails) */
     int64_t updates[KNNG_STATS_ROUNDS];  /* c: entries inserted and kept, per round */
     int64_t pairs[KNNG_STATS_ROUNDS];    /* joined pairs per round */
     int64_t gathered[KNNG_STATS_ROUNDS]; /* neighbourhood members staged per round */

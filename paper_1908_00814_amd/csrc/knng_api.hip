@@ -47,7 +47,6 @@ knng_status ok()
     } while (0)
 
 int pad4(int d) { return (d + 3) / 4 * 4; }
-int pad32(int d) { return (d + 31) / 32 * 32; }
 
 // bump allocator over the caller's workspace; with base == nullptr it only
 // measures
@@ -66,11 +65,10 @@ struct Carve {
 
 struct Layout {
     uint64_t *ctr;
-    float *x, *norm, *sq;
-    uint16_t *xb;
+    float *x, *norm, *sq, *eb;
     uint64_t *gin, *L, *worst, *rnew, *rold;
     int32_t *new_f, *old_f, *cnt_f;
-    int dp, db, gstride;
+    int dp, gstride;
 };
 
 bool uses_bf16(knng_metric m, const knng_opts *o)
@@ -83,13 +81,12 @@ void carve_merge(Carve &c, Layout &w, int64_t n, int64_t n_list, int d, int k, i
                  knng_metric m, bool bf16)
 {
     w.dp = pad4(d);
-    w.db = pad32(d);
     w.gstride = gstride;
     w.ctr = c.take<uint64_t>(C_WORDS);
     w.x = c.take<float>((size_t)n * w.dp);
     w.norm = m == KNNG_COSINE ? c.take<float>(n) : nullptr;
-    w.xb = bf16 ? c.take<uint16_t>((size_t)n * w.db) : nullptr;
     w.sq = bf16 ? c.take<float>(n) : nullptr;
+    w.eb = bf16 ? c.take<float>(n) : nullptr;
     w.gin = c.take<uint64_t>((size_t)(n_list > 0 ? n_list : 1) * (gstride > 0 ? gstride : 1));
     w.L = c.take<uint64_t>((size_t)n * k);
     w.worst = c.take<uint64_t>(n);
@@ -281,19 +278,17 @@ knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
 {
     const int d = B->d;
     HIP_TRY(launch_zero_counters(w.ctr, C_WORDS, st));
-    HIP_TRY(launch_pack(A->n ? A->x : nullptr, n1, B->x, n - n1, d, w.dp, w.x, bf16 ? w.db : 0,
-                        w.xb, w.ctr, st));
+    HIP_TRY(launch_pack(A->n ? A->x : nullptr, n1, B->x, n - n1, d, w.dp, w.x, w.ctr, st));
     R.x = w.x;
     R.norm = w.norm;
-    R.xb = w.xb;
     R.sq = w.sq;
+    R.eb = w.eb;
     R.n = n;
     R.d = d;
     R.dp = w.dp;
-    R.db = w.db;
     if (w.norm || w.sq)
-        HIP_TRY(launch_norms(w.x, n, w.dp, w.norm, w.sq, w.xb, w.db, metric == KNNG_COSINE,
-                             w.ctr, st));
+        HIP_TRY(launch_norms(w.x, n, w.dp, w.norm, w.sq, w.eb, metric == KNNG_COSINE, w.ctr,
+                             st));
     uint64_t h[C_WORDS];
     knng_status s = read_ctr(w.ctr, h, st);
     if (s != KNNG_OK)
@@ -401,6 +396,7 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
         stats->evals = (int64_t)h[C_EVALS];
         stats->rescored = (int64_t)h[C_RESCORE];
         stats->insert_attempts = (int64_t)h[C_ATTEMPT];
+        stats->screen_violations = (int64_t)h[C_VIOL];
         stats->max_group = (int32_t)h[C_MAXG];
     }
     prof.collect(stats);
@@ -578,7 +574,6 @@ knng_status knng_merge_bruteforce(const knng_set *S1, const knng_graph *G1, cons
     Carve c(workspace);
     Layout w{};
     w.dp = pad4(S1->d);
-    w.db = 0;
     w.gstride = G1->k > G2->k ? G1->k : G2->k;
     w.ctr = c.take<uint64_t>(C_WORDS);
     w.x = c.take<float>((size_t)n * w.dp);

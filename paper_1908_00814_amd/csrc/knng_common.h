@@ -42,7 +42,8 @@ enum : int {
     C_MAXG = 5,     // largest neighbourhood (max)
     C_ERR = 6,      // error bits
     C_ATTEMPT = 7,  // list inserts attempted after the screen
-    C_WORDS = 8,
+    C_VIOL = 8,     // BF16 path: rescored pairs outside the screening margin
+    C_WORDS = 10,
 };
 
 // ---------------------------------------------------------------- keys
@@ -139,6 +140,7 @@ __device__ __forceinline__ float canon_dist(const float *__restrict__ a, const f
     float acc = 0.0f;
     const float4 *a4 = reinterpret_cast<const float4 *>(a);
     const float4 *b4 = reinterpret_cast<const float4 *>(b);
+#pragma unroll 4
     for (int t = 0; t < dp / 4; t++) {
         float4 x = a4[t], y = b4[t];
         acc = canon_step<METRIC>(acc, x.x, y.x);
@@ -148,6 +150,15 @@ __device__ __forceinline__ float canon_dist(const float *__restrict__ a, const f
     }
     return canon_finish<METRIC>(acc, na, nb);
 }
+
+// round-to-nearest-even fp32 -> bf16 (bits in the high half), finite inputs
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ---------------------------------------------------------------- atomics
 __device__ __forceinline__ uint64_t ld_agent(const uint64_t *p)

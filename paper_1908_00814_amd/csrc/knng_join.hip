@@ -21,9 +21,26 @@
 // B = second set).  The admitted pairs are then dense rectangles:
 //   R1 = newA x (newB u oldB)      R2 = newB x oldA
 //   R3 = newB x (newB u oldB), upper triangle on newB x newB (J-Merge only)
-// Coordinates are staged chunk by chunk, transposed ([coordinate][member]),
-// and each lane accumulates 2 x 4 register tiles of pairs in ascending
-// coordinate order, so every distance is the canonical FP32 value.
+// Coordinates are staged chunk by chunk, transposed ([coordinate][member]).
+//
+// FP32 path (k_join): each lane accumulates a 2 x 4 register tile of pairs in
+// ascending coordinate order, so every distance is the canonical FP32 value.
+//
+// BF16 path (k_join_bf16, l2 and cosine): 16 x 16 tiles of dot products of the
+// bf16-rounded members on MFMA (v_mfma_f32_16x16x16_bf16, FP32 accumulation);
+// d~ = |p~|^2 + |q~|^2 - 2 p~.q~ screens a pair against the list's worst W with
+// a margin M that bounds |d~ - d_canonical| whenever d_canonical <= W:
+//   M = W g1 + 2 E sqrt(W (1 + g1)) + E^2 + g2 (|p~| + |q~|)^2
+// with E = |p - p~| + |q - q~| (exact per-row bf16 rounding norms),
+// g1 = (dp + 8) 2^-24 (canonical FP32 accumulation) and g2 = (2 dp + 16) 2^-24
+// (FP32 accumulation of the MFMA chain and of the norms).  Pairs that pass
+// are rescored in canonical FP32 before any insert, so the result is the FP32
+// path's, bit for bit.  Each rescored pair also checks |d~ - d| <= M(d); a
+// failure (never expected) is counted as a screen violation.  Rows certified
+// exact at layout time (integer coordinates in [0, 256], squared norm below
+// 2^23) need no rescore between each other: every product and partial sum of
+// d~ and of the canonical sum is then an integer below 2^24, so d~ is the
+// canonical value.
 #include "knng_common.h"
 #include "knng_internal.h"
 
@@ -32,10 +49,13 @@ namespace knng {
 namespace {
 
 constexpr int JOIN_WAVES = 4;
-constexpr int CH = 16;         // coordinates per staged chunk
-constexpr int TPL = 1;         // 2x4 tiles per lane per batch
+constexpr int CH = 16;                  // coordinates per staged chunk
 constexpr int OLD_CAP = MAX_K + MAX_S;  // OLD candidates per neighbourhood
-constexpr int QCAP = 320;      // insert queue entries per wave
+constexpr int QCAP = 256;               // insert-queue entries per wave
+constexpr int TMAX = 4;                 // MFMA tiles held per batch
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bool res_empty(uint64_t w) { return (uint32_t)w >= 0x40000000u; }
 __host__ __device__ __forceinline__ int r4(int x) { return (x + 3) & ~3; }
@@ -45,7 +65,178 @@ struct Regions {
     int offOA, offNB, offOB, GP;  // region starts and padded total
 };
 
-// tile t -> (row start, column start, rectangle); false past the last tile
+// per-wave LDS carve
+struct WaveLds {
+    float *vecT;     // CH x GS staged coordinates, transposed
+    uint64_t *gw;    // GS worst bound of each member's list
+    uint64_t *q64;   // QCAP queue words
+    int32_t *grp;    // GS member ids (-1 = padding)
+    float *gnorm;    // GS canonical norms (cosine)
+    float *gsq;      // GS squared norms of bf16 rows (BF16 path)
+    float *gerr;     // GS bf16 rounding-error norms (BF16 path)
+    int32_t *tnew;   // 2 MAX_S NEW members, first set then second
+    int32_t *told;   // OLD_CAP raw OLD candidates
+    int32_t *toldA;  // OLD_CAP accepted OLD members of the first set
+    int32_t *toldB;  // OLD_CAP accepted OLD members of the second set
+};
+
+__host__ __device__ inline int wave_lds_bytes(int GS)
+{
+    int b = CH * GS * 4 + GS * 8 + QCAP * 8 + 4 * GS * 4 + (2 * MAX_S + 3 * OLD_CAP) * 4;
+    return (b + 15) / 16 * 16;
+}
+
+__device__ inline WaveLds carve_lds(unsigned char *base, int GS)
+{
+    WaveLds L;
+    L.vecT = reinterpret_cast<float *>(base);
+    L.gw = reinterpret_cast<uint64_t *>(base + CH * GS * 4);
+    L.q64 = L.gw + GS;
+    L.grp = reinterpret_cast<int32_t *>(L.q64 + QCAP);
+    L.gnorm = reinterpret_cast<float *>(L.grp + GS);
+    L.gsq = L.gnorm + GS;
+    L.gerr = L.gsq + GS;
+    L.tnew = reinterpret_cast<int32_t *>(L.gerr + GS);
+    L.told = L.tnew + 2 * MAX_S;
+    L.toldA = L.told + OLD_CAP;
+    L.toldB = L.toldA + OLD_CAP;
+    return L;
+}
+
+// Forms u's neighbourhood in LDS (regions, ids, worst bounds, norms).
+// Returns false when u has no NEW member (no pair to join).
+template <int METRIC, bool BF>
+__device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a, const WaveLds &L,
+                                   Regions &g)
+{
+    const int lane = lane_id();
+    const int s = a.s, k = a.k;
+    const uint64_t below = (1ull << lane) - 1ull;
+    // NEW candidates: forward NEW sample (lanes < s), reverse NEW (s..2s)
+    const int cnt_new = a.cnt_f[2 * u], cnt_old = a.cnt_f[2 * u + 1];
+    int32_t cid = -1;
+    if (lane < s) {
+        if (lane < cnt_new)
+            cid = a.new_f[u * s + lane];
+    } else if (lane < 2 * s) {
+        uint64_t wv = a.rnew[u * s + (lane - s)];
+        if (!res_empty(wv))
+            cid = (int32_t)(uint32_t)wv;
+    }
+    bool keep = cid >= 0;
+    for (int j = 0; j < 2 * s; j++) {
+        int32_t o = __shfl(cid, j, WAVE);
+        keep = keep && !(j < lane && o == cid);
+    }
+    const bool isA = cid < a.n1;
+    const uint64_t mA = __ballot(keep && isA), mB = __ballot(keep && !isA);
+    const int nA = __popcll(mA), nB = __popcll(mB);
+    if (nA + nB == 0)
+        return false;
+    if (keep)
+        L.tnew[isA ? __popcll(mA & below) : nA + __popcll(mB & below)] = cid;
+    __builtin_amdgcn_wave_barrier();
+    // OLD candidates: forward OLD (c < k), reverse OLD (k <= c < k+s), minus
+    // NEW members and repeats
+    const int nco = k + s;
+    int oA = 0, oB = 0;
+    for (int pass = 0; pass * WAVE < nco; pass++) {
+        const int c = pass * WAVE + lane;
+        int32_t oc = -1;
+        if (c < k) {
+            if (c < cnt_old)
+                oc = a.old_f[u * k + c];
+        } else if (c < nco) {
+            uint64_t wv = a.rold[u * s + (c - k)];
+            if (!res_empty(wv))
+                oc = (int32_t)(uint32_t)wv;
+        }
+        if (c < nco)
+            L.told[c] = oc;
+        __builtin_amdgcn_wave_barrier();
+        bool ok = oc >= 0;
+        for (int j = 0; j < nA + nB && ok; j++)
+            ok = L.tnew[j] != oc;
+        for (int j = 0; j < c && ok; j++)
+            ok = L.told[j] != oc;
+        const bool oa = oc < a.n1;
+        const uint64_t moA = __ballot(ok && oa), moB = __ballot(ok && !oa);
+        if (ok) {
+            if (oa)
+                L.toldA[oA + __popcll(moA & below)] = oc;
+            else
+                L.toldB[oB + __popcll(moB & below)] = oc;
+        }
+        oA += __popcll(moA);
+        oB += __popcll(moB);
+        __builtin_amdgcn_wave_barrier();
+    }
+    g.nA = nA;
+    g.oA = oA;
+    g.nB = nB;
+    g.oB = oB;
+    g.offOA = r4(nA);
+    g.offNB = g.offOA + r4(oA);
+    g.offOB = g.offNB + r4(nB);
+    g.GP = g.offOB + r4(oB);
+    for (int slot = lane; slot < g.GP; slot += WAVE) {
+        int32_t id = -1;
+        if (slot < nA)
+            id = L.tnew[slot];
+        else if (slot >= g.offOA && slot < g.offOA + oA)
+            id = L.toldA[slot - g.offOA];
+        else if (slot >= g.offNB && slot < g.offNB + nB)
+            id = L.tnew[nA + (slot - g.offNB)];
+        else if (slot >= g.offOB && slot < g.offOB + oB)
+            id = L.toldB[slot - g.offOB];
+        L.grp[slot] = id;
+        L.gw[slot] = id >= 0 ? a.worst[id] : 0ull;
+        if (METRIC == M_COS)
+            L.gnorm[slot] = id >= 0 ? R.norm[id] : 1.0f;
+        if (BF) {
+            L.gsq[slot] = id >= 0 ? R.sq[id] : 0.0f;
+            L.gerr[slot] = id >= 0 ? R.eb[id] : 0.0f;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    return true;
+}
+
+// Stage coordinates [c0, c0+CH) of every member slot into LDS, transposed.
+template <int MU>
+__device__ inline void stage_chunk(const Rows &R, const WaveLds &L, int GP, int GS, int c0)
+{
+    constexpr int q4 = CH / 4;
+    const int lane = lane_id();
+    const int units = GP * q4;
+    __builtin_amdgcn_wave_barrier();
+    float4 pre[MU];
+#pragma unroll
+    for (int j = 0; j < MU; j++) {
+        const int e = lane + j * WAVE;
+        pre[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < units) {
+            const int m = e / q4, q = e - m * q4;
+            const int32_t id = L.grp[m];
+            if (id >= 0 && c0 + 4 * q < R.dp)
+                pre[j] = *reinterpret_cast<const float4 *>(R.x + (int64_t)id * R.dp + c0 + 4 * q);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < MU; j++) {
+        const int e = lane + j * WAVE;
+        if (e < units) {
+            const int m = e / q4, q = e - m * q4;
+            L.vecT[(4 * q + 0) * GS + m] = pre[j].x;
+            L.vecT[(4 * q + 1) * GS + m] = pre[j].y;
+            L.vecT[(4 * q + 2) * GS + m] = pre[j].z;
+            L.vecT[(4 * q + 3) * GS + m] = pre[j].w;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// tile t -> (row start, column start, rectangle) for 2 x 4 tiles
 __device__ __forceinline__ bool tile_of(int t, const Regions &g, int joint, int &r0, int &c0,
                                         int &reg)
 {
@@ -77,298 +268,388 @@ __device__ __forceinline__ bool tile_of(int t, const Regions &g, int joint, int 
     return false;
 }
 
-// Drain a wave's insert queue: every entry is first re-checked against the
-// live worst bound of its target list (one 8-byte load), the survivors are
-// inserted.  Returns the number of inserts attempted (wave-uniform).
+// Drain a queue of (target row, key) words: every entry is offered to its
+// list (the insert's own read of the list rejects entries that no longer beat
+// its worst).  Returns the number of inserts attempted (wave-uniform).
 template <int KB>
-__device__ inline int drain_queue(const uint64_t *qkey, const int32_t *qdst, int qn,
-                                  const RoundArgs &a)
+__device__ inline int drain_keys(const uint64_t *qkey, const int32_t *qdst, int qn,
+                                 const RoundArgs &a)
 {
-    int attempted = 0;
     for (int e0 = 0; e0 < qn; e0 += WAVE) {
         const int e = e0 + lane_id();
-        bool go = false;
-        uint64_t key = 0;
-        int32_t dst = 0;
         if (e < qn) {
-            key = qkey[e];
-            dst = qdst[e];
-            go = key < ld_agent(a.worst + dst);
-        }
-        attempted += __popcll(__ballot(go));
-        if (go)
-            bounded_insert<KB>(a.L + (int64_t)dst * a.k, a.k, key, true, a.worst + dst,
+            const int32_t dst = qdst[e];
+            bounded_insert<KB>(a.L + (int64_t)dst * a.k, a.k, qkey[e], true, a.worst + dst,
                                a.ctr + C_ERR);
+        }
     }
-    return attempted;
+    return qn;
 }
 
-template <int METRIC, int KB, int MAX_UNITS>
+__device__ inline void flush_counters(const RoundArgs &a, uint64_t pairs_lane, uint64_t gathered,
+                                      uint64_t attempts, uint64_t rescored_lane,
+                                      uint64_t viol_lane, int maxg)
+{
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        pairs_lane += __shfl_xor(pairs_lane, o, WAVE);
+        rescored_lane += __shfl_xor(rescored_lane, o, WAVE);
+        viol_lane += __shfl_xor(viol_lane, o, WAVE);
+    }
+    if (lane_id() == 0) {
+        unsigned long long *c = (unsigned long long *)a.ctr;
+        if (pairs_lane) {
+            atomicAdd(c + C_PAIRS, (unsigned long long)pairs_lane);
+            atomicAdd(c + C_EVALS, (unsigned long long)pairs_lane);
+        }
+        if (gathered)
+            atomicAdd(c + C_GATHER, (unsigned long long)gathered);
+        if (attempts)
+            atomicAdd(c + C_ATTEMPT, (unsigned long long)attempts);
+        if (rescored_lane)
+            atomicAdd(c + C_RESCORE, (unsigned long long)rescored_lane);
+        if (viol_lane)
+            atomicAdd(c + C_VIOL, (unsigned long long)viol_lane);
+        if (maxg)
+            atomicMax(c + C_MAXG, (unsigned long long)maxg);
+    }
+}
+
+// ============================================================ FP32 path
+template <int METRIC, int KB, int MU>
 __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join(Rows R, RoundArgs a, int GS,
                                                             int wave_bytes)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     const int lane = lane_id();
-    const int w = threadIdx.x / WAVE;
-    unsigned char *base = dyn + (size_t)w * wave_bytes;
-    float *vecT = reinterpret_cast<float *>(base);                    // CH x GS
-    uint64_t *gw = reinterpret_cast<uint64_t *>(base + CH * GS * 4);  // GS
-    int32_t *grp = reinterpret_cast<int32_t *>(gw + GS);              // GS
-    float *gnorm = reinterpret_cast<float *>(grp + GS);               // GS (cosine)
-    int32_t *tnew = reinterpret_cast<int32_t *>(gnorm + GS);          // 2 MAX_S
-    int32_t *told = tnew + 2 * MAX_S;    // raw OLD candidates     (OLD_CAP)
-    int32_t *toldA = told + OLD_CAP;     // accepted OLD, first set  (OLD_CAP)
-    int32_t *toldB = toldA + OLD_CAP;    // accepted OLD, second set (OLD_CAP)
-    uint64_t *qkey = reinterpret_cast<uint64_t *>(toldB + OLD_CAP);  // QCAP insert keys
-    int32_t *qdst = reinterpret_cast<int32_t *>(qkey + QCAP);       // QCAP target rows
-
-    const int s = a.s, k = a.k;
+    const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS);
+    uint64_t *qkey = L.q64;
+    int32_t *qdst = L.told;  // the OLD candidate lists are consumed before the queue fills
     const uint64_t below = (1ull << lane) - 1ull;
     uint64_t n_pairs = 0, n_gather = 0, n_attempt = 0;
     int maxg = 0;
     const int64_t nwaves = (int64_t)gridDim.x * JOIN_WAVES;
-    for (int64_t u = (int64_t)blockIdx.x * JOIN_WAVES + w; u < a.n; u += nwaves) {
+    for (int64_t u = (int64_t)blockIdx.x * JOIN_WAVES + threadIdx.x / WAVE; u < a.n;
+         u += nwaves) {
         __builtin_amdgcn_wave_barrier();
-        // ---- NEW candidates: forward NEW sample (lanes < s), reverse NEW (s..2s)
-        const int cnt_new = a.cnt_f[2 * u], cnt_old = a.cnt_f[2 * u + 1];
-        int32_t cid = -1;
-        if (lane < s) {
-            if (lane < cnt_new)
-                cid = a.new_f[u * s + lane];
-        } else if (lane < 2 * s) {
-            uint64_t wv = a.rnew[u * s + (lane - s)];
-            if (!res_empty(wv))
-                cid = (int32_t)(uint32_t)wv;
-        }
-        bool keep = cid >= 0;
-        for (int j = 0; j < 2 * s; j++) {
-            int32_t o = __shfl(cid, j, WAVE);
-            keep = keep && !(j < lane && o == cid);
-        }
-        const bool isA = cid < a.n1;
-        const uint64_t mA = __ballot(keep && isA), mB = __ballot(keep && !isA);
-        const int nA = __popcll(mA), nB = __popcll(mB);
-        if (nA + nB == 0)
-            continue;  // no NEW member: no pair to join at u
-        if (keep)
-            tnew[isA ? __popcll(mA & below) : nA + __popcll(mB & below)] = cid;
-        __builtin_amdgcn_wave_barrier();
-        // ---- OLD candidates: forward OLD (c < k), reverse OLD (k <= c < k+s),
-        //      minus NEW members and repeats
-        const int nco = k + s;
-        int oA = 0, oB = 0;
-        for (int pass = 0; pass * WAVE < nco; pass++) {
-            const int c = pass * WAVE + lane;
-            int32_t oc = -1;
-            if (c < k) {
-                if (c < cnt_old)
-                    oc = a.old_f[u * k + c];
-            } else if (c < nco) {
-                uint64_t wv = a.rold[u * s + (c - k)];
-                if (!res_empty(wv))
-                    oc = (int32_t)(uint32_t)wv;
-            }
-            if (c < nco)
-                told[c] = oc;
-            __builtin_amdgcn_wave_barrier();
-            bool ok = oc >= 0;
-            for (int j = 0; j < nA + nB && ok; j++)
-                ok = tnew[j] != oc;
-            for (int j = 0; j < c && ok; j++)
-                ok = told[j] != oc;
-            const bool oa = oc < a.n1;
-            const uint64_t moA = __ballot(ok && oa), moB = __ballot(ok && !oa);
-            if (ok) {
-                if (oa)
-                    toldA[oA + __popcll(moA & below)] = oc;
-                else
-                    toldB[oB + __popcll(moB & below)] = oc;
-            }
-            oA += __popcll(moA);
-            oB += __popcll(moB);
-            __builtin_amdgcn_wave_barrier();
-        }
-        // ---- regions [newA | oldA | newB | oldB], each start a multiple of 4
         Regions g;
-        g.nA = nA;
-        g.oA = oA;
-        g.nB = nB;
-        g.oB = oB;
-        g.offOA = r4(nA);
-        g.offNB = g.offOA + r4(oA);
-        g.offOB = g.offNB + r4(nB);
-        g.GP = g.offOB + r4(oB);
-        const int G = nA + oA + nB + oB;
-        for (int slot = lane; slot < g.GP; slot += WAVE) {
-            int32_t id = -1;
-            if (slot < nA)
-                id = tnew[slot];
-            else if (slot >= g.offOA && slot < g.offOA + oA)
-                id = toldA[slot - g.offOA];
-            else if (slot >= g.offNB && slot < g.offNB + nB)
-                id = tnew[nA + (slot - g.offNB)];
-            else if (slot >= g.offOB && slot < g.offOB + oB)
-                id = toldB[slot - g.offOB];
-            grp[slot] = id;
-            gw[slot] = id >= 0 ? a.worst[id] : 0ull;
-            if (METRIC == M_COS)
-                gnorm[slot] = id >= 0 ? R.norm[id] : 1.0f;
-        }
-        __builtin_amdgcn_wave_barrier();
+        if (!build_group<METRIC, false>(u, R, a, L, g))
+            continue;
+        const int G = g.nA + g.oA + g.nB + g.oB;
         n_gather += (uint64_t)G;
         maxg = G > maxg ? G : maxg;
-
-        // ---- 2x4 tiles of the admitted rectangles
         const int colsB = g.GP - g.offNB;
-        int T = ((nA + 1) / 2) * (colsB / 4) + ((nB + 1) / 2) * (r4(oA) / 4);
+        int T = ((g.nA + 1) / 2) * (colsB / 4) + ((g.nB + 1) / 2) * (r4(g.oA) / 4);
         if (a.joint)
-            T += ((nB + 1) / 2) * (colsB / 4);
-        constexpr int q4 = CH / 4;
-        const int units = g.GP * q4;  // float4 units per staged chunk
-        for (int tb = 0; tb < T; tb += WAVE * TPL) {
-            float acc[TPL][2][4];
-            int tr0[TPL], tc0[TPL], treg[TPL];
-            bool tv[TPL];
+            T += ((g.nB + 1) / 2) * (colsB / 4);
+        for (int tb = 0; tb < T; tb += WAVE) {
+            float acc[2][4];
+            int tr0 = 0, tc0 = 0, treg = 0;
+            const bool tv = tile_of(tb + lane, g, a.joint, tr0, tc0, treg);
 #pragma unroll
-            for (int i = 0; i < TPL; i++) {
-                tv[i] = tile_of(tb + i * WAVE + lane, g, a.joint, tr0[i], tc0[i], treg[i]);
+            for (int x = 0; x < 2; x++)
 #pragma unroll
-                for (int x = 0; x < 2; x++)
-#pragma unroll
-                    for (int y = 0; y < 4; y++)
-                        acc[i][x][y] = 0.0f;
-            }
+                for (int y = 0; y < 4; y++)
+                    acc[x][y] = 0.0f;
             for (int c0 = 0; c0 < R.dp; c0 += CH) {
-                // chunk -> LDS, transposed ([coordinate][member])
-                __builtin_amdgcn_wave_barrier();
-                float4 pre[MAX_UNITS];
-#pragma unroll
-                for (int j = 0; j < MAX_UNITS; j++) {
-                    const int e = lane + j * WAVE;
-                    pre[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (e < units) {
-                        const int m = e / q4, q = e - m * q4;
-                        const int32_t id = grp[m];
-                        if (id >= 0 && c0 + 4 * q < R.dp)
-                            pre[j] = *reinterpret_cast<const float4 *>(R.x + (int64_t)id * R.dp +
-                                                                       c0 + 4 * q);
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < MAX_UNITS; j++) {
-                    const int e = lane + j * WAVE;
-                    if (e < units) {
-                        const int m = e / q4, q = e - m * q4;
-                        vecT[(4 * q + 0) * GS + m] = pre[j].x;
-                        vecT[(4 * q + 1) * GS + m] = pre[j].y;
-                        vecT[(4 * q + 2) * GS + m] = pre[j].z;
-                        vecT[(4 * q + 3) * GS + m] = pre[j].w;
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
+                stage_chunk<MU>(R, L, g.GP, GS, c0);
                 const int cw = R.dp - c0 < CH ? R.dp - c0 : CH;
-#pragma unroll
-                for (int i = 0; i < TPL; i++) {
-                    if (!tv[i])
-                        continue;
+                if (tv) {
 #pragma unroll 2
                     for (int t = 0; t < cw; t++) {
                         const float2 xr =
-                            *reinterpret_cast<const float2 *>(vecT + t * GS + tr0[i]);
+                            *reinterpret_cast<const float2 *>(L.vecT + t * GS + tr0);
                         const float4 xc =
-                            *reinterpret_cast<const float4 *>(vecT + t * GS + tc0[i]);
+                            *reinterpret_cast<const float4 *>(L.vecT + t * GS + tc0);
                         const float xrs[2] = {xr.x, xr.y};
                         const float xcs[4] = {xc.x, xc.y, xc.z, xc.w};
 #pragma unroll
                         for (int x = 0; x < 2; x++)
 #pragma unroll
                             for (int y = 0; y < 4; y++)
-                                acc[i][x][y] = canon_step<METRIC>(acc[i][x][y], xrs[x], xcs[y]);
+                                acc[x][y] = canon_step<METRIC>(acc[x][y], xrs[x], xcs[y]);
                     }
                 }
             }
-            // ---- screen; survivors go through the wave's insert queue, drained
-            //      by all lanes together (UpdateNN in both directions)
+            // screen; survivors go through the wave's insert queue, drained by
+            // all lanes together (UpdateNN in both directions)
             int qn = 0;
 #pragma unroll
-            for (int i = 0; i < TPL; i++) {
+            for (int x = 0; x < 2; x++) {
+                const int r = tr0 + x;
 #pragma unroll
-                for (int x = 0; x < 2; x++) {
-                    const int r = tr0[i] + x;
-#pragma unroll
-                    for (int y = 0; y < 4; y++) {
-                        const int c = tc0[i] + y;
-                        const int32_t p = tv[i] ? grp[r] : -1;
-                        const int32_t q = tv[i] ? grp[c] : -1;
-                        const bool valid = p >= 0 && q >= 0 && !(treg[i] == 3 && c <= r);
-                        n_pairs += valid;
-                        float na = 0.0f, nb = 0.0f;
-                        if (METRIC == M_COS && valid) {
-                            na = gnorm[r];
-                            nb = gnorm[c];
-                        }
-                        const float l = canon_finish<METRIC>(acc[i][x][y], na, nb);
-                        const uint64_t kp = make_key(l, (uint32_t)q, F_NEW | F_FRESH);
-                        const uint64_t kq = make_key(l, (uint32_t)p, F_NEW | F_FRESH);
-                        const bool vp = valid && kp < gw[r];
-                        const bool vq = valid && kq < gw[c];
-                        const uint64_t mp = __ballot(vp), mq = __ballot(vq);
-                        if (vp) {
-                            const int pos = qn + __popcll(mp & below);
-                            qkey[pos] = kp;
-                            qdst[pos] = p;
-                        }
-                        qn += __popcll(mp);
-                        if (vq) {
-                            const int pos = qn + __popcll(mq & below);
-                            qkey[pos] = kq;
-                            qdst[pos] = q;
-                        }
-                        qn += __popcll(mq);
-                        if (qn > QCAP - 2 * WAVE) {
-                            __builtin_amdgcn_wave_barrier();
-                            n_attempt += drain_queue<KB>(qkey, qdst, qn, a);
-                            qn = 0;
-                            __builtin_amdgcn_wave_barrier();
-                        }
+                for (int y = 0; y < 4; y++) {
+                    const int c = tc0 + y;
+                    const int32_t p = tv ? L.grp[r] : -1;
+                    const int32_t q = tv ? L.grp[c] : -1;
+                    const bool valid = p >= 0 && q >= 0 && !(treg == 3 && c <= r);
+                    n_pairs += valid;
+                    float na = 0.0f, nb = 0.0f;
+                    if (METRIC == M_COS && valid) {
+                        na = L.gnorm[r];
+                        nb = L.gnorm[c];
+                    }
+                    const float l = canon_finish<METRIC>(acc[x][y], na, nb);
+                    const uint64_t kp = make_key(l, (uint32_t)q, F_NEW | F_FRESH);
+                    const uint64_t kq = make_key(l, (uint32_t)p, F_NEW | F_FRESH);
+                    const bool vp = valid && kp < L.gw[r];
+                    const bool vq = valid && kq < L.gw[c];
+                    const uint64_t mp = __ballot(vp), mq = __ballot(vq);
+                    if (vp) {
+                        const int pos = qn + __popcll(mp & below);
+                        qkey[pos] = kp;
+                        qdst[pos] = p;
+                    }
+                    qn += __popcll(mp);
+                    if (vq) {
+                        const int pos = qn + __popcll(mq & below);
+                        qkey[pos] = kq;
+                        qdst[pos] = q;
+                    }
+                    qn += __popcll(mq);
+                    if (qn > QCAP - 2 * WAVE) {
+                        __builtin_amdgcn_wave_barrier();
+                        n_attempt += drain_keys<KB>(qkey, qdst, qn, a);
+                        qn = 0;
+                        __builtin_amdgcn_wave_barrier();
                     }
                 }
             }
             __builtin_amdgcn_wave_barrier();
-            n_attempt += drain_queue<KB>(qkey, qdst, qn, a);
+            n_attempt += drain_keys<KB>(qkey, qdst, qn, a);
             __builtin_amdgcn_wave_barrier();
         }
     }
-    // ---- counters: one atomic per wave
-    uint64_t tp = n_pairs, ta = n_attempt;  // pairs: per lane; attempts: per wave
-    for (int o = WAVE / 2; o > 0; o >>= 1)
-        tp += __shfl_xor(tp, o, WAVE);
-    if (lane == 0) {
-        if (tp) {
-            atomicAdd((unsigned long long *)(a.ctr + C_PAIRS), (unsigned long long)tp);
-            atomicAdd((unsigned long long *)(a.ctr + C_EVALS), (unsigned long long)tp);
-        }
-        if (n_gather)
-            atomicAdd((unsigned long long *)(a.ctr + C_GATHER), (unsigned long long)n_gather);
-        if (ta)
-            atomicAdd((unsigned long long *)(a.ctr + C_ATTEMPT), (unsigned long long)ta);
-        if (maxg)
-            atomicMax((unsigned long long *)(a.ctr + C_MAXG), (unsigned long long)maxg);
+    flush_counters(a, n_pairs, n_gather, n_attempt, 0, 0, maxg);
+}
+
+// ============================================================ BF16 path
+// 16 x 16 tile t of the rectangles -> packed (row origin | col origin << 8 |
+// rectangle << 16), rectangle 0 = none
+__device__ __forceinline__ int tile16_of(int t, const Regions &g, int joint)
+{
+    const int colsB = g.GP - g.offNB;
+    const int ct1 = (colsB + 15) / 16;
+    const int T1 = ((g.nA + 15) / 16) * ct1;
+    if (t < T1)
+        return (16 * (t / ct1)) | ((g.offNB + 16 * (t % ct1)) << 8) | (1 << 16);
+    t -= T1;
+    const int rt2 = (g.nB + 15) / 16, ct2 = (g.oA + 15) / 16;
+    const int T2 = rt2 * ct2;
+    if (t < T2)
+        return (g.offNB + 16 * (t / ct2)) | ((g.offOA + 16 * (t % ct2)) << 8) | (2 << 16);
+    t -= T2;
+    if (joint && t < rt2 * ct1)
+        return (g.offNB + 16 * (t / ct1)) | ((g.offNB + 16 * (t % ct1)) << 8) | (3 << 16);
+    return 0;
+}
+
+// is (r, c) inside rectangle `reg` (and above the diagonal for rectangle 3)?
+__device__ __forceinline__ bool in_rect(int reg, int r, int c, const Regions &g)
+{
+    if (reg == 1)
+        return r < g.nA && c >= g.offNB && c < g.GP;
+    if (reg == 2)
+        return r >= g.offNB && r < g.offNB + g.nB && c >= g.offOA && c < g.offOA + g.oA;
+    if (reg == 3)
+        return r >= g.offNB && r < g.offNB + g.nB && c > r && c < g.GP;
+    return false;
+}
+
+__device__ __forceinline__ int tiles16(const Regions &g, int joint)
+{
+    const int ct1 = (g.GP - g.offNB + 15) / 16;
+    int T = ((g.nA + 15) / 16) * ct1 + ((g.nB + 15) / 16) * ((g.oA + 15) / 16);
+    if (joint)
+        T += ((g.nB + 15) / 16) * ct1;
+    return T;
+}
+
+// screening margin in l2 space (see the file header)
+__device__ __forceinline__ float bf16_margin(float W, float E, float N2, int dp)
+{
+    const float g1 = (float)(dp + 8) * 0x1p-24f;
+    const float g2 = (float)(2 * dp + 16) * 0x1p-24f;
+    const float m = W * g1 + 2.0f * E * __builtin_sqrtf(W * (1.0f + g1)) + E * E + g2 * N2;
+    return m * (1.0f + 0x1p-16f) + 1e-30f;
+}
+
+// the worst entry of a list as an l2-space threshold (+inf when not full)
+template <int METRIC>
+__device__ __forceinline__ float l2_threshold(uint64_t worst, float na, float nb)
+{
+    if (key_empty(worst))
+        return __uint_as_float(0x7F800000u);
+    const float W = key_dist(worst);
+    if (METRIC == M_COS) {
+        // canonical cosine r = (D - (na-nb)^2) / (2 na nb) is increasing in D;
+        // r <= W implies D <= W 2 na nb + (na-nb)^2 up to a few roundings
+        const float e = na - nb;
+        return (W * (2.0f * na * nb) + e * e) * (1.0f + 0x1p-19f) + 1e-30f;
     }
+    return W;
+}
+
+template <int METRIC, int KB, int MU>
+__global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundArgs a, int GS,
+                                                                 int wave_bytes)
+{
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const int lane = lane_id();
+    const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS);
+    // queue word: slot r | slot c << 8 | (p gets q) << 16 | (q gets p) << 17 in
+    // the low half, the screening distance's bits in the high half
+    uint64_t *qw = L.q64;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const float inf = __uint_as_float(0x7F800000u);
+    uint64_t n_pairs = 0, n_gather = 0, n_attempt = 0, n_rescore = 0, n_viol = 0;
+    int maxg = 0;
+    const int64_t nwaves = (int64_t)gridDim.x * JOIN_WAVES;
+    for (int64_t u = (int64_t)blockIdx.x * JOIN_WAVES + threadIdx.x / WAVE; u < a.n;
+         u += nwaves) {
+        __builtin_amdgcn_wave_barrier();
+        Regions g;
+        if (!build_group<METRIC, true>(u, R, a, L, g))
+            continue;
+        const int G = g.nA + g.oA + g.nB + g.oB;
+        n_gather += (uint64_t)G;
+        maxg = G > maxg ? G : maxg;
+        const int T = tiles16(g, a.joint);
+        const int kq = 4 * (lane >> 4);  // this lane's 4 coordinates of a 16-chunk
+        for (int tb = 0; tb < T; tb += TMAX) {
+            f32x4 acc[TMAX];
+            int tl[TMAX];
+#pragma unroll
+            for (int i = 0; i < TMAX; i++) {
+                acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+                tl[i] = tile16_of(tb + i, g, a.joint);
+            }
+            for (int c0 = 0; c0 < R.dp; c0 += CH) {
+                stage_chunk<MU>(R, L, g.GP, GS, c0);
+#pragma unroll
+                for (int i = 0; i < TMAX; i++) {
+                    if (tl[i] == 0)
+                        continue;
+                    const int row = (tl[i] & 0xFF) + (lane & 15);
+                    const int col = ((tl[i] >> 8) & 0xFF) + (lane & 15);
+                    bf16x4 A, B;
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        A[j] = (short)f32_to_bf16(L.vecT[(kq + j) * GS + row]);
+                        B[j] = (short)f32_to_bf16(L.vecT[(kq + j) * GS + col]);
+                    }
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[i], 0, 0, 0);
+                }
+            }
+            // screen whole tiles into the queue while one more tile fits, then
+            // drain it (one drain site); this lane holds rows rb + kq + rr of
+            // column cb + lane % 16 of each tile
+            int done = 0;
+            while (done < TMAX) {
+                int qn = 0;
+#pragma unroll
+                for (int i = 0; i < TMAX; i++) {
+                    if (i < done || qn > QCAP - 4 * WAVE)
+                        continue;
+                    done = i + 1;
+                    const int reg = tl[i] >> 16;
+#pragma unroll
+                    for (int rr = 0; rr < 4; rr++) {
+                        const int r = (tl[i] & 0xFF) + kq + rr;
+                        const int c = ((tl[i] >> 8) & 0xFF) + (lane & 15);
+                        bool valid = in_rect(reg, r, c, g);
+                        const int32_t p = valid ? L.grp[r] : -1, q = valid ? L.grp[c] : -1;
+                        valid = valid && p >= 0 && q >= 0;
+                        n_pairs += valid;
+                        bool vp = false, vq = false;
+                        float dbf = 0.0f;
+                        if (valid) {
+                            const float sp = L.gsq[r], sq = L.gsq[c];
+                            dbf = __builtin_fmaf(-2.0f, acc[i][rr], sp + sq);
+                            const float E =
+                                (fabsf(L.gerr[r]) + fabsf(L.gerr[c])) * (1.0f + 0x1p-22f);
+                            const float nn = __builtin_sqrtf(sp) + __builtin_sqrtf(sq);
+                            const float N2 = nn * nn * (1.0f + 0x1p-20f);
+                            const float na = METRIC == M_COS ? L.gnorm[r] : 0.0f;
+                            const float nb = METRIC == M_COS ? L.gnorm[c] : 0.0f;
+                            const float Wp = l2_threshold<METRIC>(L.gw[r], na, nb);
+                            const float Wq = l2_threshold<METRIC>(L.gw[c], na, nb);
+                            vp = Wp == inf ||
+                                 dbf <= (Wp + bf16_margin(Wp, E, N2, R.dp)) * (1.0f + 0x1p-22f);
+                            vq = Wq == inf ||
+                                 dbf <= (Wq + bf16_margin(Wq, E, N2, R.dp)) * (1.0f + 0x1p-22f);
+                        }
+                        const bool any = vp || vq;
+                        const uint64_t m = __ballot(any);
+                        if (any) {
+                            const uint32_t lo = (uint32_t)r | ((uint32_t)c << 8) |
+                                                ((uint32_t)vp << 16) | ((uint32_t)vq << 17);
+                            qw[qn + __popcll(m & below)] =
+                                ((uint64_t)__float_as_uint(dbf) << 32) | lo;
+                        }
+                        qn += __popcll(m);
+                    }
+                }
+                // rescore in canonical FP32, then insert (UpdateNN both ways)
+                __builtin_amdgcn_wave_barrier();
+                for (int e0 = 0; e0 < qn; e0 += WAVE) {
+                    const int e = e0 + lane;
+                    bool gp = false, gq = false;
+                    int32_t pp = 0, qq = 0;
+                    uint64_t kp = 0, kqk = 0;
+                    if (e < qn) {
+                        const uint64_t w = qw[e];
+                        const int sr = (int)(w & 0xFF), sc = (int)((w >> 8) & 0xFF);
+                        pp = L.grp[sr];
+                        qq = L.grp[sc];
+                        const float db = __uint_as_float((uint32_t)(w >> 32));
+                        float D = db;
+                        // two certified exact rows: the bf16 distance is the
+                        // canonical value; otherwise rescore in canonical FP32
+                        if (!(signbit(L.gerr[sr]) && signbit(L.gerr[sc]))) {
+                            D = canon_dist<M_L2>(R.x + (int64_t)pp * R.dp,
+                                                 R.x + (int64_t)qq * R.dp, R.dp, 0.0f, 0.0f);
+                            n_rescore++;
+                            // the margin also bounds |d~ - d| at d itself
+                            const float sp = L.gsq[sr], sq2 = L.gsq[sc];
+                            const float E =
+                                (fabsf(L.gerr[sr]) + fabsf(L.gerr[sc])) * (1.0f + 0x1p-22f);
+                            const float nn = __builtin_sqrtf(sp) + __builtin_sqrtf(sq2);
+                            const float M =
+                                bf16_margin(D, E, nn * nn * (1.0f + 0x1p-20f), R.dp);
+                            n_viol += !(fabsf(db - D) <= M * (1.0f + 0x1p-20f));
+                        }
+                        float l = D;
+                        if (METRIC == M_COS)
+                            l = cos_finish(D, L.gnorm[sr], L.gnorm[sc]);
+                        kp = make_key(l, (uint32_t)qq, F_NEW | F_FRESH);
+                        kqk = make_key(l, (uint32_t)pp, F_NEW | F_FRESH);
+                        gp = ((w >> 16) & 1) && kp < ld_agent(a.worst + pp);
+                        gq = ((w >> 17) & 1) && kqk < ld_agent(a.worst + qq);
+                    }
+                    n_attempt += __popcll(__ballot(gp)) + __popcll(__ballot(gq));
+                    if (gp)
+                        bounded_insert<KB>(a.L + (int64_t)pp * a.k, a.k, kp, true, a.worst + pp,
+                                           a.ctr + C_ERR);
+                    if (gq)
+                        bounded_insert<KB>(a.L + (int64_t)qq * a.k, a.k, kqk, true,
+                                           a.worst + qq, a.ctr + C_ERR);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    flush_counters(a, n_pairs, n_gather, n_attempt, n_rescore, n_viol, maxg);
 }
 
 } // namespace
 
 hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, hipStream_t st)
 {
-    (void)bf16;
-    // member slots: four regions, each rounded up to a multiple of 4 (+12),
-    // plus 4 to spread the LDS banks of consecutive coordinate rows
+    // member slots: four regions, each rounded up to a multiple of 4 (+12);
+    // the BF16 tiles read 16 slots past a region start (+16); +4 spreads banks
     const int g_max = 3 * a.s + a.k;
-    const int GS = r4(g_max) + 16;
-    int wave_bytes = CH * GS * 4 + GS * 8 + GS * 4 + GS * 4 + (2 * MAX_S + 3 * OLD_CAP) * 4 +
-                     QCAP * 12;
-    wave_bytes = (wave_bytes + 15) / 16 * 16;
+    const int GS = r4(g_max) + 12 + 16 + 4;
+    const int wave_bytes = wave_lds_bytes(GS);
     const size_t shmem = (size_t)wave_bytes * JOIN_WAVES;
     const int units = GS * (CH / 4);
     if (units > 12 * WAVE)
@@ -390,18 +671,29 @@ hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, 
                            GS, wave_bytes);
         return hipSuccess;
     };
-    auto by_metric = [&](auto l2, auto cs, auto l1) -> hipError_t {
-        return metric == M_L2 ? go(l2) : (metric == M_COS ? go(cs) : go(l1));
-    };
-#define KNNG_JOIN_SET(KBV, MU) by_metric(k_join<M_L2, KBV, MU>, k_join<M_COS, KBV, MU>, k_join<M_L1, KBV, MU>)
     hipError_t e;
-    if (a.k <= 16)
-        e = small ? KNNG_JOIN_SET(16, 8) : KNNG_JOIN_SET(16, 12);
-    else if (a.k <= 32)
-        e = small ? KNNG_JOIN_SET(32, 8) : KNNG_JOIN_SET(32, 12);
-    else
-        e = small ? KNNG_JOIN_SET(64, 8) : KNNG_JOIN_SET(64, 12);
-#undef KNNG_JOIN_SET
+#define KNNG_FP32_SET(KBV, MUV)                                                                 \
+    (metric == M_L2 ? go(k_join<M_L2, KBV, MUV>)                                                \
+                    : (metric == M_COS ? go(k_join<M_COS, KBV, MUV>) : go(k_join<M_L1, KBV, MUV>)))
+#define KNNG_BF16_SET(KBV, MUV)                                                                 \
+    (metric == M_L2 ? go(k_join_bf16<M_L2, KBV, MUV>) : go(k_join_bf16<M_COS, KBV, MUV>))
+    if (bf16 && metric != M_L1) {
+        if (a.k <= 16)
+            e = small ? KNNG_BF16_SET(16, 8) : KNNG_BF16_SET(16, 12);
+        else if (a.k <= 32)
+            e = small ? KNNG_BF16_SET(32, 8) : KNNG_BF16_SET(32, 12);
+        else
+            e = small ? KNNG_BF16_SET(64, 8) : KNNG_BF16_SET(64, 12);
+    } else {
+        if (a.k <= 16)
+            e = small ? KNNG_FP32_SET(16, 8) : KNNG_FP32_SET(16, 12);
+        else if (a.k <= 32)
+            e = small ? KNNG_FP32_SET(32, 8) : KNNG_FP32_SET(32, 12);
+        else
+            e = small ? KNNG_FP32_SET(64, 8) : KNNG_FP32_SET(64, 12);
+    }
+#undef KNNG_FP32_SET
+#undef KNNG_BF16_SET
     if (e != hipSuccess)
         return e;
     return hipGetLastError();

@@ -11,29 +11,17 @@ namespace knng {
 
 namespace {
 
-// round-to-nearest-even fp32 -> bf16 bits (inputs are finite)
-__device__ __forceinline__ uint16_t f32_to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// concatenate the two sets into one zero-padded fp32 array (+ bf16 copy)
+// concatenate the two sets into one zero-padded fp32 array
 __global__ void k_pack(const float *__restrict__ x1, int64_t n1, const float *__restrict__ x2,
-                       int64_t n2, int d, int dp, float *__restrict__ x, int db,
-                       uint16_t *__restrict__ xb, uint64_t *ctr)
+                       int64_t n2, int d, int dp, float *__restrict__ x, uint64_t *ctr)
 {
-    int64_t n = n1 + n2;
-    int wmax = dp > db ? dp : db;
-    int64_t total = n * (int64_t)wmax;
+    const int64_t n = n1 + n2;
+    const int64_t total = n * (int64_t)dp;
     uint32_t bad = 0;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        int64_t r = e / wmax;
-        int c = (int)(e - r * wmax);
+        const int64_t r = e / dp;
+        const int c = (int)(e - r * dp);
         float v = 0.0f;
         if (c < d) {
             v = r < n1 ? x1[r * d + c] : x2[(r - n1) * d + c];
@@ -42,26 +30,25 @@ __global__ void k_pack(const float *__restrict__ x1, int64_t n1, const float *__
                 v = 0.0f;
             }
         }
-        if (c < dp)
-            x[r * dp + c] = v;
-        if (xb && c < db)
-            xb[r * db + c] = f32_to_bf16(v);
+        x[r * dp + c] = v;
     }
     if (bad)
         atomicOr((unsigned long long *)(ctr + C_ERR), (unsigned long long)ERR_NONFINITE);
 }
 
 // canonical norms (ascending fused accumulation, correctly rounded sqrt) and,
-// for the BF16 path, the squared norms of the bf16-rounded rows
+// for the BF16 path, per row: the squared norm of the bf16-rounded row
+// (ascending fused accumulation) and an upper bound of |x - bf16(x)|
+// (accumulated in FP64, rounded up)
 __global__ void k_norms(const float *__restrict__ x, int64_t n, int dp, float *__restrict__ norm,
-                        float *__restrict__ sq, const uint16_t *__restrict__ xb, int db,
-                        int check_zero, uint64_t *ctr)
+                        float *__restrict__ sq, float *__restrict__ eb, int check_zero,
+                        uint64_t *ctr)
 {
-    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= n)
         return;
+    const float4 *p = reinterpret_cast<const float4 *>(x + r * dp);
     if (norm) {
-        const float4 *p = reinterpret_cast<const float4 *>(x + r * dp);
         float acc = 0.0f;
         for (int t = 0; t < dp / 4; t++) {
             float4 v = p[t];
@@ -76,13 +63,34 @@ __global__ void k_norms(const float *__restrict__ x, int64_t n, int dp, float *_
             atomicOr((unsigned long long *)(ctr + C_ERR), (unsigned long long)ERR_ZERO_NORM);
     }
     if (sq) {
-        // exact enough: a sum of squares of bf16 values accumulated in fp32
         float acc = 0.0f;
-        for (int t = 0; t < db; t++) {
-            float v = bf16_to_f32(xb[r * db + t]);
-            acc = __builtin_fmaf(v, v, acc);
+        double e2 = 0.0;
+        bool integral = true;  // every coordinate an integer in [0, 256]
+        for (int t = 0; t < dp / 4; t++) {
+            float4 v = p[t];
+            float vs[4] = {v.x, v.y, v.z, v.w};
+            for (int j = 0; j < 4; j++) {
+                float b = bf16_to_f32(f32_to_bf16(vs[j]));
+                acc = __builtin_fmaf(b, b, acc);
+                double dd = (double)vs[j] - (double)b;
+                e2 += dd * dd;
+                integral = integral && vs[j] == rintf(vs[j]) && vs[j] >= 0.0f && vs[j] <= 256.0f;
+            }
         }
         sq[r] = acc;
+        // the FP64 sum of exact squares is within (dp * 2^-53) relative;
+        // inflate it and the sqrt so the fp32 value is an upper bound
+        float e = __double2float_ru(__builtin_sqrt(e2 * (1.0 + 0x1p-36)) * (1.0 + 0x1p-50));
+        // Exactness certificate, stored as the sign of the bound: coordinates
+        // are integers in [0, 256] (bf16-exact) and |x|^2 < 2^23.  For two
+        // certified rows p, q: every partial dot product is at most
+        // |p||q| < 2^23, |p|^2 + |q|^2 < 2^24, and (p_t - q_t)^2 <= p_t^2 + q_t^2
+        // bounds every canonical partial sum by |p|^2 + |q|^2 < 2^24; all are
+        // integers, so both evaluations are exact and the bf16 distance equals
+        // the canonical FP32 value bit for bit.
+        if (integral && acc < 0x1p23f)
+            e = -0.0f;
+        eb[r] = e;
     }
 }
 
@@ -338,23 +346,21 @@ inline unsigned grid_for(int64_t items, int per_block)
 } // namespace
 
 hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2, int d, int dp,
-                       float *x, int db, uint16_t *xb, uint64_t *ctr, hipStream_t st)
+                       float *x, uint64_t *ctr, hipStream_t st)
 {
-    int64_t total = (n1 + n2) * (int64_t)(dp > db ? dp : db);
+    const int64_t total = (n1 + n2) * (int64_t)dp;
     unsigned grid = grid_for(total, 256);
     if (grid > 65536u)
         grid = 65536u;
-    hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, x1, n1, x2, n2, d, dp, x, db, xb,
-                       ctr);
+    hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, x1, n1, x2, n2, d, dp, x, ctr);
     return hipGetLastError();
 }
 
 hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float *sq_bf16,
-                        const uint16_t *xb, int db, int check_zero, uint64_t *ctr,
-                        hipStream_t st)
+                        float *err_bf16, int check_zero, uint64_t *ctr, hipStream_t st)
 {
     hipLaunchKernelGGL(k_norms, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, dp, norm,
-                       sq_bf16, xb, db, check_zero, ctr);
+                       sq_bf16, err_bf16, check_zero, ctr);
     return hipGetLastError();
 }
 

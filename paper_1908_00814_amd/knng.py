@@ -46,7 +46,7 @@ class Graph(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("max_group", ctypes.c_int32),
                 ("evals", ctypes.c_int64), ("rescored", ctypes.c_int64),
-                ("insert_attempts", ctypes.c_int64),
+                ("insert_attempts", ctypes.c_int64), ("screen_violations", ctypes.c_int64),
                 ("updates", ctypes.c_int64 * STATS_ROUNDS),
                 ("pairs", ctypes.c_int64 * STATS_ROUNDS),
                 ("gathered", ctypes.c_int64 * STATS_ROUNDS),
@@ -59,6 +59,7 @@ class Stats(ctypes.Structure):
         r = min(self.rounds, STATS_ROUNDS)
         return {"rounds": self.rounds, "max_group": self.max_group, "evals": self.evals,
                 "rescored": self.rescored, "insert_attempts": self.insert_attempts,
+                "screen_violations": self.screen_violations,
                 "c": list(self.updates[:r]),
                 "pairs": list(self.pairs[:r]), "gathered": list(self.gathered[:r]),
                 "ms": {"prep": self.ms_prep, "init": self.ms_init, "sample": self.ms_sample,

@@ -250,3 +250,57 @@ def _host_pointer_call(hip, S1, G1, S2, G2):
     rc = lib.knng_merge(ctypes.byref(s1), ctypes.byref(g), ctypes.byref(s2), ctypes.byref(g), 6,
                         0, ctypes.byref(o), ctypes.byref(g), None, 0, None, None)
     hip._check(rc)
+
+
+# ---------------------------------------------------------------- BF16-MFMA screen
+
+@pytest.mark.parametrize("metric", ["l2", "cos"])
+def test_bf16_smerge_identical_to_oracle(hip, metric):
+    # MFMA screen + canonical FP32 rescore gives the FP32 path's result exactly
+    S1, S2 = ragged_sets(700, 513, 19, 104)
+    G1 = oracle.exact_graph(S1, 10, metric)
+    G2 = oracle.exact_graph(S2, 10, metric)
+    oi, od, ost = oracle.smerge(S1, G1, S2, G2, 10, metric, sample=8, seed=77)
+    gi, gd, gst = hip.merge(dev(S1), (dev(G1[0]), dev(G1[1])), dev(S2), (dev(G2[0]), dev(G2[1])),
+                            10, metric, sample=8, seed=77, precision="bf16")
+    assert_same_graph(host(gi), host(gd), oi, od, f"bf16 smerge {metric}")
+    _same_stats(gst, ost)
+    assert gst["screen_violations"] == 0
+    assert 0 < gst["rescored"] < sum(gst["pairs"])
+
+
+def test_bf16_integer_data_and_large_d(hip):
+    # byte-valued rows (bf16-exact) at d = 128, the benchmark's value law
+    X = synth.byte_cluster_points(1500, 128, 12, 20.0, workload=2)
+    S1, S2 = X[:800], X[800:]
+    G1 = oracle.exact_graph(S1, 12)
+    G2 = oracle.exact_graph(S2, 12)
+    oi, od, ost = oracle.smerge(S1, G1, S2, G2, 12, sample=6, seed=3)
+    gi, gd, gst = hip.merge(dev(S1), (dev(G1[0]), dev(G1[1])), dev(S2), (dev(G2[0]), dev(G2[1])),
+                            12, sample=6, seed=3, precision="bf16")
+    assert_same_graph(host(gi), host(gd), oi, od, "bf16 integer")
+    _same_stats(gst, ost)
+    assert gst["screen_violations"] == 0
+
+
+@pytest.mark.parametrize("metric", ["l2", "cos"])
+def test_bf16_jmerge_identical_to_oracle(hip, metric):
+    Sb, Sr = ragged_sets(650, 277, 21, 107)
+    G = oracle.exact_graph(Sb, 10, metric)
+    oi, od, ost = oracle.jmerge(Sb, G, Sr, 10, metric, sample=7, seed=5)
+    gi, gd, gst = hip.expand(dev(Sb), (dev(G[0]), dev(G[1])), dev(Sr), 10, metric, sample=7,
+                             seed=5, precision="bf16")
+    assert_same_graph(host(gi), host(gd), oi, od, f"bf16 jmerge {metric}")
+    _same_stats(gst, ost)
+    assert gst["screen_violations"] == 0
+
+
+def test_bf16_l1_runs_the_fp32_path(hip):
+    S1, S2 = ragged_sets(300, 200, 9, 112)
+    G1 = oracle.exact_graph(S1, 8, "l1")
+    G2 = oracle.exact_graph(S2, 8, "l1")
+    oi, od, _ = oracle.smerge(S1, G1, S2, G2, 8, "l1", sample=5, seed=2)
+    gi, gd, gst = hip.merge(dev(S1), (dev(G1[0]), dev(G1[1])), dev(S2), (dev(G2[0]), dev(G2[1])),
+                            8, "l1", sample=5, seed=2, precision="bf16")
+    assert_same_graph(host(gi), host(gd), oi, od, "bf16 l1")
+    assert gst["rescored"] == 0
