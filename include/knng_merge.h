@@ -188,6 +188,29 @@ size_t knng_expand_workspace_size(int64_t n_base, int64_t n_raw, int32_t d, int3
                                   int32_t kin, knng_metric metric, const knng_opts *opts);
 
 /*
+ * Merge of many blocks by repeated S-Merge: Section 1 merges more than two
+ * graphs by recursive calls of the two-graph merge, and Section 3.1 (last
+ * paragraph) merges sub-graphs built in parallel pairwise until one graph
+ * remains.  Blocks are consecutive row ranges of X: block b holds rows
+ * [starts[b], starts[b+1]) (`starts` is a HOST array of nblocks+1 entries,
+ * starts[0] = 0, starts[nblocks] = X->n) and G[b] is its graph with ids local
+ * to the block (any G[b].k >= k1; a block carried up unmerged needs >= k).
+ * Level by level, neighbouring ranges (0,1), (2,3), ... are merged with
+ * knng_merge; an odd last range moves up unchanged.  out: X->n rows, k
+ * columns, ids = row indices of X.  stats (may be NULL): totals over all
+ * merges; updates[l] holds the distance evaluations of level l and pairs[l]
+ * its rounds.  Synchronises the stream.
+ */
+knng_status knng_merge_tree(const knng_set *X, const int64_t *starts, const knng_graph *G,
+                            int32_t nblocks, int32_t k, knng_metric metric,
+                            const knng_opts *opts, knng_graph *out, void *workspace,
+                            size_t workspace_bytes, void *stream, knng_stats *stats);
+
+size_t knng_merge_tree_workspace_size(int64_t n, int32_t d, int32_t nblocks,
+                                      const int64_t *starts, int32_t k, int32_t kin_max,
+                                      knng_metric metric, const knng_opts *opts);
+
+/*
  * Brute-force cross merge (Section 1): row i of S1 becomes the top k of
  * G1[i] and every (m(x_i, y_j), n1+j); S2 rows likewise against S1.
  * Deterministic: equal to the exact result in canonical FP32 with ties broken

@@ -243,6 +243,28 @@ def jmerge(Xb, G, Xr, k, metric="l2", keep_ratio=0.5, sample=10, delta=0.0, max_
     return ids, dist, _stats_dict(st)
 
 
+def merge_tree(X, starts, graphs, k, metric="l2", **kw):
+    """Many blocks merged by repeated S-Merge (Section 1: recursive two-graph
+    merging; Section 3.1: sub-graphs merged pairwise).  Level by level the
+    neighbouring row ranges (0,1), (2,3), ... are merged; an odd last range
+    moves up unchanged.  Returns (ids, dist) over all rows of X."""
+    X = _f32(X)
+    segs = [(starts[b], starts[b + 1], graphs[b]) for b in range(len(graphs))]
+    while len(segs) > 1:
+        nxt = []
+        for i in range(0, len(segs) - 1, 2):
+            a, b, g1 = segs[i]
+            _, c, g2 = segs[i + 1]
+            ids, dist, _ = smerge(X[a:b], g1, X[b:c], g2, k, metric, **kw)
+            nxt.append((a, c, (ids, dist)))
+        if len(segs) % 2 == 1:
+            a, c, g = segs[-1]
+            nxt.append((a, c, (np.ascontiguousarray(g[0][:, :k]),
+                               np.ascontiguousarray(g[1][:, :k]))))
+        segs = nxt
+    return segs[0][2]
+
+
 # --------------------------------------------------------------------------
 # evaluation (Section 5.1)
 # --------------------------------------------------------------------------

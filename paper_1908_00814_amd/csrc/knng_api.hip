@@ -66,9 +66,10 @@ struct Carve {
 struct Layout {
     uint64_t *ctr;
     float *x, *norm, *sq, *eb;
+    uint16_t *xb;
     uint64_t *gin, *L, *worst, *rnew, *rold;
     int32_t *new_f, *old_f, *cnt_f;
-    int dp, gstride;
+    int dp, db, gstride;
 };
 
 bool uses_bf16(knng_metric m, const knng_opts *o)
@@ -81,10 +82,12 @@ void carve_merge(Carve &c, Layout &w, int64_t n, int64_t n_list, int d, int k, i
                  knng_metric m, bool bf16)
 {
     w.dp = pad4(d);
+    w.db = (d + 31) / 32 * 32;
     w.gstride = gstride;
     w.ctr = c.take<uint64_t>(C_WORDS);
     w.x = c.take<float>((size_t)n * w.dp);
     w.norm = m == KNNG_COSINE ? c.take<float>(n) : nullptr;
+    w.xb = bf16 ? c.take<uint16_t>((size_t)n * w.db) : nullptr;
     w.sq = bf16 ? c.take<float>(n) : nullptr;
     w.eb = bf16 ? c.take<float>(n) : nullptr;
     w.gin = c.take<uint64_t>((size_t)(n_list > 0 ? n_list : 1) * (gstride > 0 ? gstride : 1));
@@ -278,8 +281,11 @@ knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
 {
     const int d = B->d;
     HIP_TRY(launch_zero_counters(w.ctr, C_WORDS, st));
-    HIP_TRY(launch_pack(A->n ? A->x : nullptr, n1, B->x, n - n1, d, w.dp, w.x, w.ctr, st));
+    HIP_TRY(launch_pack(A->n ? A->x : nullptr, n1, B->x, n - n1, d, w.dp, w.x,
+                        bf16 ? w.db : 0, bf16 ? w.xb : nullptr, w.ctr, st));
     R.x = w.x;
+    R.xb = bf16 ? w.xb : nullptr;
+    R.db = w.db;
     R.norm = w.norm;
     R.sq = w.sq;
     R.eb = w.eb;
@@ -532,6 +538,174 @@ knng_status knng_expand(const knng_set *S, const knng_graph *G, const knng_set *
         return s;
     return run_merge(R, w, metric, bf16, opts, n, nb, k, nb > 0 ? k1 : 0, 1, nb, out, st, stats,
                      prof);
+}
+
+// ---------------------------------------------------------------- merge tree
+namespace {
+
+struct Seg {
+    int64_t a, c;  // rows [a, c) of X
+    int32_t *ids;  // local ids (row - a)
+    float *dist;
+    int32_t kk;
+};
+
+// two ping-pong levels of ids and distances, then the merge workspace at the
+// next 256-byte boundary (the same carve sizes and places them)
+struct TreeBufs {
+    int32_t *ids[2];
+    float *dist[2];
+};
+
+void carve_tree(Carve &c, TreeBufs &t, int64_t n, int k)
+{
+    t.ids[0] = c.take<int32_t>((size_t)n * k);
+    t.ids[1] = c.take<int32_t>((size_t)n * k);
+    t.dist[0] = c.take<float>((size_t)n * k);
+    t.dist[1] = c.take<float>((size_t)n * k);
+    c.off = (c.off + 255) / 256 * 256;
+}
+
+size_t tree_merge_ws(const int64_t *starts, int nb, int d, int k, int kin_max, knng_metric m,
+                     const knng_opts *o)
+{
+    // the largest single merge of the tree; every level merges neighbours
+    std::vector<int64_t> b(starts, starts + nb + 1);
+    size_t best = 0;
+    int kin = kin_max;
+    while (b.size() > 2) {
+        std::vector<int64_t> nxt;
+        nxt.push_back(b[0]);
+        for (size_t i = 0; i + 2 < b.size(); i += 2) {
+            size_t w = knng_merge_workspace_size(b[i + 1] - b[i], b[i + 2] - b[i + 1], d, k, kin,
+                                                 kin, m, o);
+            best = w > best ? w : best;
+            nxt.push_back(b[i + 2]);
+        }
+        if ((b.size() - 1) % 2 == 1)
+            nxt.push_back(b.back());
+        b.swap(nxt);
+        kin = kin > k ? kin : k;
+    }
+    return best;
+}
+
+} // namespace
+
+extern "C" size_t knng_merge_tree_workspace_size(int64_t n, int32_t d, int32_t nblocks,
+                                                 const int64_t *starts, int32_t k,
+                                                 int32_t kin_max, knng_metric metric,
+                                                 const knng_opts *opts)
+{
+    if (!starts || nblocks < 2 || n < 2 || d < 1 || k < 1 || !opts || starts[nblocks] != n)
+        return 0;
+    Carve c(nullptr);
+    TreeBufs t;
+    carve_tree(c, t, n, k);
+    const int kin = kin_max > k ? kin_max : k;
+    return c.off + 256 + tree_merge_ws(starts, nblocks, d, k, kin, metric, opts);
+}
+
+extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
+                                       const knng_graph *G, int32_t nblocks, int32_t k,
+                                       knng_metric metric, const knng_opts *opts,
+                                       knng_graph *out, void *workspace, size_t workspace_bytes,
+                                       void *stream, knng_stats *stats)
+{
+    knng_status s;
+    if ((s = check_metric(metric)) || (s = check_set(X, "X")) || (s = check_opts(opts, k)))
+        return s;
+    if (!starts || !G || nblocks < 2)
+        return fail(KNNG_EINVAL, "merge tree needs at least 2 blocks");
+    const int64_t n = X->n;
+    if (starts[0] != 0 || starts[nblocks] != n)
+        return fail(KNNG_EINVAL, "block starts must run from 0 to X->n");
+    int kin_max = 0;
+    for (int b = 0; b < nblocks; b++) {
+        if (starts[b + 1] - starts[b] < 2)
+            return fail(KNNG_EINVAL, "block %d has fewer than 2 rows", b);
+        kin_max = G[b].k > kin_max ? G[b].k : kin_max;
+    }
+    if (k < 1 || k > MAX_K || k > n - 1)
+        return fail(KNNG_EINVAL, "k = %d out of range", k);
+    if ((s = check_out(out, n, k)))
+        return s;
+    const size_t need =
+        knng_merge_tree_workspace_size(n, X->d, nblocks, starts, k, kin_max, metric, opts);
+    if (!workspace || workspace_bytes < need)
+        return fail(KNNG_ENOMEM, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    Carve c(workspace);
+    TreeBufs t;
+    carve_tree(c, t, n, k);
+    int32_t *const *ids = t.ids;
+    float *const *dist = t.dist;
+    uint8_t *mws = static_cast<uint8_t *>(workspace) + c.off;
+    const size_t mws_bytes = workspace_bytes - c.off;
+    knng_stats total;
+    memset(&total, 0, sizeof total);
+    std::vector<Seg> segs;
+    for (int b = 0; b < nblocks; b++)
+        segs.push_back({starts[b], starts[b + 1], G[b].ids, G[b].dist, G[b].k});
+    int level = 0;
+    while (segs.size() > 1) {
+        const bool last = segs.size() == 2;
+        int32_t *li = last ? out->ids : ids[level & 1];
+        float *ld = last ? out->dist : dist[level & 1];
+        std::vector<Seg> nxt;
+        for (size_t i = 0; i + 1 < segs.size(); i += 2) {
+            const Seg &p = segs[i], &q = segs[i + 1];
+            knng_set s1{p.c - p.a, X->d, X->x + p.a * X->d};
+            knng_set s2{q.c - q.a, X->d, X->x + q.a * X->d};
+            knng_graph g1{p.c - p.a, p.kk, p.ids, p.dist};
+            knng_graph g2{q.c - q.a, q.kk, q.ids, q.dist};
+            knng_graph o{q.c - p.a, k, li + p.a * k, ld + p.a * k};
+            knng_stats one;
+            s = knng_merge(&s1, &g1, &s2, &g2, k, metric, opts, &o, mws, mws_bytes, stream, &one);
+            if (s != KNNG_OK)
+                return s;
+            total.rounds += one.rounds;
+            total.evals += one.evals;
+            total.rescored += one.rescored;
+            total.insert_attempts += one.insert_attempts;
+            total.screen_violations += one.screen_violations;
+            total.max_group = one.max_group > total.max_group ? one.max_group : total.max_group;
+            total.ms_prep += one.ms_prep;
+            total.ms_init += one.ms_init;
+            total.ms_sample += one.ms_sample;
+            total.ms_reverse += one.ms_reverse;
+            total.ms_join += one.ms_join;
+            total.ms_final += one.ms_final;
+            total.join_launches += one.join_launches;
+            if (level < KNNG_STATS_ROUNDS) {
+                total.updates[level] += one.evals;  // distance evaluations per level
+                total.pairs[level] += one.rounds;   // rounds per level
+            }
+            nxt.push_back({p.a, q.c, li + p.a * k, ld + p.a * k, k});
+        }
+        if (segs.size() % 2 == 1) {
+            // an odd last block moves up unchanged (copied: the next level
+            // writes into the buffer it lives in)
+            const Seg &r = segs.back();
+            const int64_t rows = r.c - r.a;
+            if (r.kk < k || !r.dist)
+                return fail(KNNG_EINVAL, "a block carried up unmerged needs k_in >= k and "
+                                         "distances");
+            HIP_TRY(hipMemcpy2DAsync(li + r.a * k, (size_t)k * 4, r.ids, (size_t)r.kk * 4,
+                                     (size_t)(r.kk < k ? r.kk : k) * 4, (size_t)rows,
+                                     hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpy2DAsync(ld + r.a * k, (size_t)k * 4, r.dist, (size_t)r.kk * 4,
+                                     (size_t)(r.kk < k ? r.kk : k) * 4, (size_t)rows,
+                                     hipMemcpyDeviceToDevice, st));
+            nxt.push_back({r.a, r.c, li + r.a * k, ld + r.a * k, k});
+        }
+        segs.swap(nxt);
+        level++;
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    if (stats)
+        *stats = total;
+    return ok();
 }
 
 size_t knng_bruteforce_workspace_size(int64_t n1, int64_t n2, int32_t d, int32_t k,

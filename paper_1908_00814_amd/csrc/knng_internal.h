@@ -12,10 +12,11 @@ namespace knng {
 struct Rows {
     const float *x;  // n x dp fp32, zero-padded
     const float *norm;  // n canonical norms (cosine) or nullptr
+    const uint16_t *xb; // BF16 path: n x db bf16 copy (round to nearest even), or nullptr
     const float *sq;    // BF16 path: squared norms of the bf16-rounded rows, or nullptr
     const float *eb;    // BF16 path: upper bounds of |x - bf16(x)| per row, or nullptr
     int64_t n;
-    int d, dp;
+    int d, dp, db;  // db: bf16 row stride, d rounded up to 32
 };
 
 // Parameters of one iteration of the merge loop.
@@ -39,7 +40,7 @@ struct RoundArgs {
 
 // ---- knng_prep.hip
 hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2, int d, int dp,
-                       float *x, uint64_t *ctr, hipStream_t st);
+                       float *x, int db, uint16_t *xb, uint64_t *ctr, hipStream_t st);
 hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float *sq_bf16,
                         float *err_bf16, int check_zero, uint64_t *ctr, hipStream_t st);
 // Input graph rows [row0, row0+nrows) of the concatenated set: local ids +

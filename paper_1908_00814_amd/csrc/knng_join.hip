@@ -27,7 +27,8 @@
 // ascending coordinate order, so every distance is the canonical FP32 value.
 //
 // BF16 path (k_join_bf16, l2 and cosine): 16 x 16 tiles of dot products of the
-// bf16-rounded members on MFMA (v_mfma_f32_16x16x16_bf16, FP32 accumulation);
+// bf16-rounded members on MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation),
+// operands gathered straight from a bf16 copy of the rows into registers;
 // d~ = |p~|^2 + |q~|^2 - 2 p~.q~ screens a pair against the list's worst W with
 // a margin M that bounds |d~ - d_canonical| whenever d_canonical <= W:
 //   M = W g1 + 2 E sqrt(W (1 + g1)) + E^2 + g2 (|p~| + |q~|)^2
@@ -54,7 +55,7 @@ constexpr int OLD_CAP = MAX_K + MAX_S;  // OLD candidates per neighbourhood
 constexpr int QCAP = 256;               // insert-queue entries per wave
 constexpr int TMAX = 4;                 // MFMA tiles held per batch
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bool res_empty(uint64_t w) { return (uint32_t)w >= 0x40000000u; }
@@ -489,7 +490,7 @@ __device__ __forceinline__ float l2_threshold(uint64_t worst, float na, float nb
     return W;
 }
 
-template <int METRIC, int KB, int MU>
+template <int METRIC, int KB>
 __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundArgs a, int GS,
                                                                  int wave_bytes)
 {
@@ -501,6 +502,8 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
     uint64_t *qw = L.q64;
     const uint64_t below = (1ull << lane) - 1ull;
     const float inf = __uint_as_float(0x7F800000u);
+    const int ksteps = R.db / 32;
+    const int koff = 8 * (lane >> 4);  // this lane's 8 coordinates of a 32-step
     uint64_t n_pairs = 0, n_gather = 0, n_attempt = 0, n_rescore = 0, n_viol = 0;
     int maxg = 0;
     const int64_t nwaves = (int64_t)gridDim.x * JOIN_WAVES;
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
         n_gather += (uint64_t)G;
         maxg = G > maxg ? G : maxg;
         const int T = tiles16(g, a.joint);
-        const int kq = 4 * (lane >> 4);  // this lane's 4 coordinates of a 16-chunk
+        const int kq = 4 * (lane >> 4);  // this lane's output rows of a tile
         for (int tb = 0; tb < T; tb += TMAX) {
             f32x4 acc[TMAX];
             int tl[TMAX];
@@ -523,21 +526,26 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
                 acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
                 tl[i] = tile16_of(tb + i, g, a.joint);
             }
-            for (int c0 = 0; c0 < R.dp; c0 += CH) {
-                stage_chunk<MU>(R, L, g.GP, GS, c0);
+            // operands straight from the bf16 rows: lane l holds row (l % 16)
+            // of the tile's row band and of its column band, 8 coordinates
 #pragma unroll
-                for (int i = 0; i < TMAX; i++) {
-                    if (tl[i] == 0)
-                        continue;
-                    const int row = (tl[i] & 0xFF) + (lane & 15);
-                    const int col = ((tl[i] >> 8) & 0xFF) + (lane & 15);
-                    bf16x4 A, B;
-#pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        A[j] = (short)f32_to_bf16(L.vecT[(kq + j) * GS + row]);
-                        B[j] = (short)f32_to_bf16(L.vecT[(kq + j) * GS + col]);
-                    }
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[i], 0, 0, 0);
+            for (int i = 0; i < TMAX; i++) {
+                if (tl[i] == 0)
+                    continue;
+                const int rs = (tl[i] & 0xFF) + (lane & 15);
+                const int cs = ((tl[i] >> 8) & 0xFF) + (lane & 15);
+                const int32_t ir = rs < g.GP ? L.grp[rs] : -1;
+                const int32_t ic = cs < g.GP ? L.grp[cs] : -1;
+                const bf16x8 *pa =
+                    reinterpret_cast<const bf16x8 *>(R.xb + (int64_t)(ir < 0 ? 0 : ir) * R.db + koff);
+                const bf16x8 *pb =
+                    reinterpret_cast<const bf16x8 *>(R.xb + (int64_t)(ic < 0 ? 0 : ic) * R.db + koff);
+                const bf16x8 zero = {};
+#pragma unroll 4
+                for (int ks = 0; ks < ksteps; ks++) {
+                    const bf16x8 A = ir >= 0 ? pa[4 * ks] : zero;
+                    const bf16x8 B = ic >= 0 ? pb[4 * ks] : zero;
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[i], 0, 0, 0);
                 }
             }
             // screen whole tiles into the queue while one more tile fits, then
@@ -565,18 +573,25 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
                         if (valid) {
                             const float sp = L.gsq[r], sq = L.gsq[c];
                             dbf = __builtin_fmaf(-2.0f, acc[i][rr], sp + sq);
-                            const float E =
-                                (fabsf(L.gerr[r]) + fabsf(L.gerr[c])) * (1.0f + 0x1p-22f);
-                            const float nn = __builtin_sqrtf(sp) + __builtin_sqrtf(sq);
-                            const float N2 = nn * nn * (1.0f + 0x1p-20f);
                             const float na = METRIC == M_COS ? L.gnorm[r] : 0.0f;
                             const float nb = METRIC == M_COS ? L.gnorm[c] : 0.0f;
-                            const float Wp = l2_threshold<METRIC>(L.gw[r], na, nb);
-                            const float Wq = l2_threshold<METRIC>(L.gw[c], na, nb);
-                            vp = Wp == inf ||
-                                 dbf <= (Wp + bf16_margin(Wp, E, N2, R.dp)) * (1.0f + 0x1p-22f);
-                            vq = Wq == inf ||
-                                 dbf <= (Wq + bf16_margin(Wq, E, N2, R.dp)) * (1.0f + 0x1p-22f);
+                            if (signbit(L.gerr[r]) && signbit(L.gerr[c])) {
+                                // certified exact pair: d~ is the canonical value
+                                const float l = METRIC == M_COS ? cos_finish(dbf, na, nb) : dbf;
+                                vp = make_key(l, (uint32_t)q, F_NEW | F_FRESH) < L.gw[r];
+                                vq = make_key(l, (uint32_t)p, F_NEW | F_FRESH) < L.gw[c];
+                            } else {
+                                const float E =
+                                    (fabsf(L.gerr[r]) + fabsf(L.gerr[c])) * (1.0f + 0x1p-22f);
+                                const float nn = __builtin_sqrtf(sp) + __builtin_sqrtf(sq);
+                                const float N2 = nn * nn * (1.0f + 0x1p-20f);
+                                const float Wp = l2_threshold<METRIC>(L.gw[r], na, nb);
+                                const float Wq = l2_threshold<METRIC>(L.gw[c], na, nb);
+                                vp = Wp == inf || dbf <= (Wp + bf16_margin(Wp, E, N2, R.dp)) *
+                                                             (1.0f + 0x1p-22f);
+                                vq = Wq == inf || dbf <= (Wq + bf16_margin(Wq, E, N2, R.dp)) *
+                                                             (1.0f + 0x1p-22f);
+                            }
                         }
                         const bool any = vp || vq;
                         const uint64_t m = __ballot(any);
@@ -589,7 +604,8 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
                         qn += __popcll(m);
                     }
                 }
-                // rescore in canonical FP32, then insert (UpdateNN both ways)
+                // rescore in canonical FP32 (unless certified), then insert
+                // (UpdateNN both ways)
                 __builtin_amdgcn_wave_barrier();
                 for (int e0 = 0; e0 < qn; e0 += WAVE) {
                     const int e = e0 + lane;
@@ -603,8 +619,6 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
                         qq = L.grp[sc];
                         const float db = __uint_as_float((uint32_t)(w >> 32));
                         float D = db;
-                        // two certified exact rows: the bf16 distance is the
-                        // canonical value; otherwise rescore in canonical FP32
                         if (!(signbit(L.gerr[sr]) && signbit(L.gerr[sc]))) {
                             D = canon_dist<M_L2>(R.x + (int64_t)pp * R.dp,
                                                  R.x + (int64_t)qq * R.dp, R.dp, 0.0f, 0.0f);
@@ -623,8 +637,8 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
                             l = cos_finish(D, L.gnorm[sr], L.gnorm[sc]);
                         kp = make_key(l, (uint32_t)qq, F_NEW | F_FRESH);
                         kqk = make_key(l, (uint32_t)pp, F_NEW | F_FRESH);
-                        gp = ((w >> 16) & 1) && kp < ld_agent(a.worst + pp);
-                        gq = ((w >> 17) & 1) && kqk < ld_agent(a.worst + qq);
+                        gp = ((w >> 16) & 1) != 0;
+                        gq = ((w >> 17) & 1) != 0;
                     }
                     n_attempt += __popcll(__ballot(gp)) + __popcll(__ballot(gq));
                     if (gp)
@@ -676,7 +690,7 @@ hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, 
     (metric == M_L2 ? go(k_join<M_L2, KBV, MUV>)                                                \
                     : (metric == M_COS ? go(k_join<M_COS, KBV, MUV>) : go(k_join<M_L1, KBV, MUV>)))
 #define KNNG_BF16_SET(KBV, MUV)                                                                 \
-    (metric == M_L2 ? go(k_join_bf16<M_L2, KBV, MUV>) : go(k_join_bf16<M_COS, KBV, MUV>))
+    (metric == M_L2 ? go(k_join_bf16<M_L2, KBV>) : go(k_join_bf16<M_COS, KBV>))
     if (bf16 && metric != M_L1) {
         if (a.k <= 16)
             e = small ? KNNG_BF16_SET(16, 8) : KNNG_BF16_SET(16, 12);

@@ -11,17 +11,20 @@ namespace knng {
 
 namespace {
 
-// concatenate the two sets into one zero-padded fp32 array
+// concatenate the two sets into one zero-padded fp32 array (and, for the
+// BF16 path, a zero-padded bf16 copy with rows of db elements)
 __global__ void k_pack(const float *__restrict__ x1, int64_t n1, const float *__restrict__ x2,
-                       int64_t n2, int d, int dp, float *__restrict__ x, uint64_t *ctr)
+                       int64_t n2, int d, int dp, float *__restrict__ x, int db,
+                       uint16_t *__restrict__ xb, uint64_t *ctr)
 {
     const int64_t n = n1 + n2;
-    const int64_t total = n * (int64_t)dp;
+    const int w = xb && db > dp ? db : dp;
+    const int64_t total = n * (int64_t)w;
     uint32_t bad = 0;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / dp;
-        const int c = (int)(e - r * dp);
+        const int64_t r = e / w;
+        const int c = (int)(e - r * w);
         float v = 0.0f;
         if (c < d) {
             v = r < n1 ? x1[r * d + c] : x2[(r - n1) * d + c];
@@ -30,7 +33,10 @@ __global__ void k_pack(const float *__restrict__ x1, int64_t n1, const float *__
                 v = 0.0f;
             }
         }
-        x[r * dp + c] = v;
+        if (c < dp)
+            x[r * dp + c] = v;
+        if (xb && c < db)
+            xb[r * db + c] = f32_to_bf16(v);
     }
     if (bad)
         atomicOr((unsigned long long *)(ctr + C_ERR), (unsigned long long)ERR_NONFINITE);
@@ -346,13 +352,14 @@ inline unsigned grid_for(int64_t items, int per_block)
 } // namespace
 
 hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2, int d, int dp,
-                       float *x, uint64_t *ctr, hipStream_t st)
+                       float *x, int db, uint16_t *xb, uint64_t *ctr, hipStream_t st)
 {
-    const int64_t total = (n1 + n2) * (int64_t)dp;
+    const int64_t total = (n1 + n2) * (int64_t)(xb && db > dp ? db : dp);
     unsigned grid = grid_for(total, 256);
     if (grid > 65536u)
         grid = 65536u;
-    hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, x1, n1, x2, n2, d, dp, x, ctr);
+    hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, x1, n1, x2, n2, d, dp, x, db, xb,
+                       ctr);
     return hipGetLastError();
 }
 

@@ -24,7 +24,8 @@ STATUS = {0: "KNNG_OK", 1: "KNNG_EINVAL", 2: "KNNG_ENOMEM", 3: "KNNG_EDEVICE"}
 ENTRY_POINTS = ["knng_opts_default", "knng_merge", "knng_merge_workspace_size", "knng_expand",
                 "knng_expand_workspace_size", "knng_merge_bruteforce",
                 "knng_bruteforce_workspace_size", "knng_exact_graph",
-                "knng_exact_graph_workspace_size", "knng_last_error", "knng_version"]
+                "knng_exact_graph_workspace_size", "knng_last_error", "knng_version",
+                "knng_merge_tree", "knng_merge_tree_workspace_size"]
 
 
 class Opts(ctypes.Structure):
@@ -106,6 +107,10 @@ def load():
     lib.knng_exact_graph.argtypes = [pS, I32, ctypes.c_int, pG, P, SZ, P]
     lib.knng_exact_graph_workspace_size.restype = SZ
     lib.knng_exact_graph_workspace_size.argtypes = [I64, I32, I32, ctypes.c_int]
+    lib.knng_merge_tree.restype = ctypes.c_int
+    lib.knng_merge_tree.argtypes = [pS, P, pG, I32, I32, ctypes.c_int, pO, pG, P, SZ, P, pSt]
+    lib.knng_merge_tree_workspace_size.restype = SZ
+    lib.knng_merge_tree_workspace_size.argtypes = [I64, I32, I32, P, I32, I32, ctypes.c_int, pO]
     lib.knng_last_error.restype = ctypes.c_char_p
     lib.knng_last_error.argtypes = []
     lib.knng_version.restype = ctypes.c_int
@@ -250,6 +255,34 @@ def exact_graph(S, k, metric="l2", stream=None):
     _check(lib.knng_exact_graph(ctypes.byref(s), k, _metric(metric), ctypes.byref(go), _ptr(ws),
                                 ws.numel(), _stream(stream)))
     return ids, dist
+
+
+def merge_tree(X, starts, graphs, k, metric="l2", stream=None, workspace=None, **kw):
+    """Merge of consecutive row blocks of X by repeated S-Merge (knng_merge_tree).
+    `starts`: nblocks+1 row offsets; `graphs`: per block (ids, dist or None),
+    ids local to the block.  Returns (ids, dist, stats dict) over all of X."""
+    lib = load()
+    o = opts(**kw)
+    xs = _set(X)
+    nb = len(graphs)
+    st_arr = (ctypes.c_int64 * (nb + 1))(*[int(v) for v in starts])
+    garr = (Graph * nb)(*[_graph(*g) for g in graphs])
+    kin_max = max(g[0].shape[1] for g in graphs)
+    need = lib.knng_merge_tree_workspace_size(X.shape[0], X.shape[1], nb, st_arr, k, kin_max,
+                                              _metric(metric), ctypes.byref(o))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    ids, dist = _out(X.shape[0], k, X.device)
+    go = _graph(ids, dist)
+    st = Stats()
+    _check(lib.knng_merge_tree(ctypes.byref(xs), st_arr, garr, nb, k, _metric(metric),
+                               ctypes.byref(o), ctypes.byref(go), _ptr(workspace),
+                               workspace.numel(), _stream(stream), ctypes.byref(st)))
+    d = st.to_dict()
+    levels = [lvl for lvl in range(STATS_ROUNDS) if st.pairs[lvl]]
+    d["level_evals"] = [st.updates[lvl] for lvl in levels]
+    d["level_rounds"] = [st.pairs[lvl] for lvl in levels]
+    return ids, dist, d
 
 
 def version():

@@ -57,3 +57,29 @@ def test_host_queries(lib):
     # struct layouts agree with the header's field order
     assert ctypes.sizeof(knng.Opts) == 32
     assert ctypes.sizeof(knng.Set) == 24 and ctypes.sizeof(knng.Graph) == 32
+
+
+@pytest.mark.parametrize("sizes", [(300, 257, 310, 280), (260, 240, 301), (1000, 3, 2, 7, 999)])
+def test_merge_tree_workspace_covers_every_merge(lib, sizes):
+    # the tree keeps two ping-pong n x k levels (ids and distances, each on its
+    # own 256-byte boundary) in front of the workspace of its largest merge
+    from paper_1908_00814_amd import knng
+    k, d, n = 8, 10, sum(sizes)
+    o = knng.opts(sample=6)
+    starts = [0]
+    for m in sizes:
+        starts.append(starts[-1] + m)
+    arr = (ctypes.c_int64 * len(starts))(*starts)
+    got = lib.knng_merge_tree_workspace_size(n, d, len(sizes), arr, k, k, 2, ctypes.byref(o))
+    bufs = 4 * ((n * k * 4 + 255) // 256 * 256)
+    b, biggest = list(starts), 0
+    while len(b) > 2:
+        nxt = [b[0]]
+        for i in range(0, len(b) - 2, 2):
+            biggest = max(biggest, lib.knng_merge_workspace_size(
+                b[i + 1] - b[i], b[i + 2] - b[i + 1], d, k, k, k, 2, ctypes.byref(o)))
+            nxt.append(b[i + 2])
+        if (len(b) - 1) % 2:
+            nxt.append(b[-1])
+        b = nxt
+    assert got >= bufs + biggest

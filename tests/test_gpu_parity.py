@@ -304,3 +304,20 @@ def test_bf16_l1_runs_the_fp32_path(hip):
                             8, "l1", sample=5, seed=2, precision="bf16")
     assert_same_graph(host(gi), host(gd), oi, od, "bf16 l1")
     assert gst["rescored"] == 0
+
+
+# ---------------------------------------------------------------- merge tree
+
+@pytest.mark.parametrize("sizes,metric", [((300, 257, 310, 280), "l1"), ((260, 240, 301), "l2")])
+def test_merge_tree_identical_to_oracle(hip, sizes, metric):
+    # blocks merged pairwise level by level (an odd block moves up unchanged)
+    g = synth.rng(113)
+    X = np.concatenate([(g.standard_normal((n, 10)) + 0.5 * b).astype(np.float32)
+                        for b, n in enumerate(sizes)])
+    starts = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    graphs = [oracle.exact_graph(X[starts[b]:starts[b + 1]], 8, metric) for b in range(len(sizes))]
+    oi, od = oracle.merge_tree(X, starts, graphs, 8, metric, sample=6, seed=21)
+    gi, gd, gst = hip.merge_tree(dev(X), starts, [(dev(a), dev(b)) for a, b in graphs], 8, metric,
+                                 sample=6, seed=21)
+    assert_same_graph(host(gi), host(gd), oi, od, f"merge tree {metric}")
+    assert len(gst["level_rounds"]) == (2 if len(sizes) == 4 else 2)
