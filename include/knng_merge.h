@@ -55,6 +55,7 @@ typedef enum {
     KNNG_EINVAL = 1,  /* bad argument or invalid input data */
     KNNG_ENOMEM = 2,  /* workspace smaller than required */
     KNNG_EDEVICE = 3, /* a HIP call failed; see knng_last_error() */
+    KNNG_EBUSY = 4,   /* knng_server_wait: the request has not finished in time */
 } knng_status;
 
 typedef enum {
@@ -75,6 +76,16 @@ typedef enum {
 
 /* opts.flags */
 #define KNNG_FLAG_PROFILE 1u /* time each phase with HIP events (stats.ms_*) */
+/* knng_expand only -- balanced append, for a raw set much smaller than the
+ * base (a case Section 5.2's size-ratio study stops short of): a base row
+ * takes part in Divide and Append only when a hash draw selects it, with
+ * probability min(1, n_raw/n_base); the other base rows keep their whole
+ * list, all OLD, and receive no samples.  Every raw row then meets about
+ * k - k1 base rows through Append, as in the balanced case.  With
+ * n_raw >= n_base every row is selected and the call is Algorithm 2 as
+ * printed.  The work of a round then scales with the rows touched, not with
+ * n_base (see knng_server_*). */
+#define KNNG_FLAG_BALANCED_APPEND 2u
 
 /*
  * Parameters of the merges.
@@ -85,8 +96,10 @@ typedef enum {
  *               each sampled reverse list (NN-Descent sampling, which
  *               Section 3.1 invokes by citation).  1..32.
  *   delta       the repeat loop of Algorithms 1-2 stops when the number of
- *               entries inserted in a round is <= delta*n*k (0 = until no
- *               update, as the paper states).
+ *               entries inserted in a round (and still present at its end)
+ *               is <= delta*n0*k, n0 = rows holding a NEW entry when the
+ *               loop starts: every row of the call, except under balanced
+ *               append (0 = until no update, as the paper states).
  *   max_rounds  cap on rounds (the paper has none).
  *   seed        seed of the counter-based random stream (SplitMix64).
  *   precision   knng_precision.
@@ -232,6 +245,107 @@ knng_status knng_exact_graph(const knng_set *S, int32_t k, knng_metric metric, k
                              void *workspace, size_t workspace_bytes, void *stream);
 
 size_t knng_exact_graph_workspace_size(int64_t n, int32_t d, int32_t k, knng_metric metric);
+
+/*
+ * ---------------------------------------------------------------- serving
+ * J-Merge as a service (Section 3.2: a built graph absorbs raw data without
+ * a rebuild).  A server holds a resident set -- the base rows and every row
+ * merged since -- with its k-NN graph in device memory it owns.  Requests of
+ * raw rows are queued; whenever the device is free, all waiting requests
+ * (in submission order, up to max_batch rows; a request is never split) form
+ * one batch, and the batch is one knng_expand of the resident set and graph
+ * with the batch's rows as the raw set, under KNNG_FLAG_BALANCED_APPEND, with
+ * seed opts->seed + batch index.  Afterwards the resident set includes the
+ * batch rows and the resident graph is that merge's output.
+ *
+ * Row ids: base rows 0..n_base-1, then the rows of each accepted request in
+ * submission order (knng_request_info.first_id).  A request's result is its
+ * rows' lists as they stood when its batch finished; later batches keep
+ * improving the resident graph (knng_server_snapshot).
+ *
+ * Given the same batches, results are deterministic; which requests share a
+ * batch depends on timing unless the server is created with manual = 1,
+ * where batches run only inside knng_server_step.
+ *
+ * Threads: submit, wait, step, snapshot and status may be called from any
+ * threads concurrently; destroy must not overlap any other call on the same
+ * server.  Work runs on the device that was current at creation, on streams
+ * the server owns.
+ */
+typedef struct knng_server knng_server;
+
+typedef struct {
+    int64_t capacity;   /* rows the server can ever hold: base + every request row */
+    int64_t max_batch;  /* most raw rows merged in one batch (also the largest request) */
+    uint64_t hbm_budget; /* device bytes the server may allocate; 0 = no limit */
+    int32_t manual;     /* 1: no worker thread; batches run in knng_server_step */
+    int32_t reserved;
+} knng_server_config;
+
+typedef struct {
+    int64_t first_id;   /* id of the request's first row */
+    int64_t batch;      /* index of the batch that merged it (-1: none) */
+    int64_t batch_rows; /* raw rows in that batch */
+    int64_t evals;      /* distance evaluations of that batch */
+    int32_t rounds;     /* rounds of that batch's repeat loop */
+    int32_t reserved;
+    /* host steady clock, microseconds since the server was created */
+    double submit_us;   /* knng_server_submit entered */
+    double start_us;    /* its batch started */
+    double done_us;     /* its batch finished (results on the host) */
+} knng_request_info;
+
+/* Device bytes a server of this shape allocates (kin: columns of the base
+ * graph). */
+size_t knng_server_bytes(int64_t capacity, int64_t max_batch, int32_t d, int32_t k, int32_t kin,
+                         knng_metric metric, const knng_opts *opts);
+
+/*
+ * Copies base (n_base x d, device) and its graph G (as for knng_expand: local
+ * ids, sorted with distances or dist NULL, G->k >= k1) into server memory,
+ * allocated once with hipMalloc (KNNG_ENOMEM beyond cfg->hbm_budget).
+ * Inputs are not kept.  *srv receives the server (NULL on error).
+ */
+knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_t k,
+                               knng_metric metric, const knng_opts *opts,
+                               const knng_server_config *cfg, knng_server **srv);
+
+/*
+ * Queues n_raw rows (n_raw x d fp32, host or device memory; read before
+ * return, so the buffer may be reused at once).  Rows are validated
+ * (KNNG_EINVAL: non-finite values, zero rows under cosine); KNNG_ENOMEM when
+ * the capacity would be exceeded, KNNG_EINVAL when n_raw > max_batch.
+ * *ticket identifies the request for knng_server_wait.
+ */
+knng_status knng_server_submit(knng_server *srv, const float *raw, int64_t n_raw,
+                               uint64_t *ticket);
+
+/* manual servers: runs one batch of the waiting requests (*ran = 0 when none
+ * was waiting) */
+knng_status knng_server_step(knng_server *srv, int32_t *ran);
+
+/*
+ * Waits up to timeout_us (< 0: no limit) for the request; KNNG_EBUSY when it
+ * has not finished.  On success ids / dist (n_raw x k, host or device; either
+ * may be NULL) receive its rows' lists with global ids, and the ticket is
+ * released (a second wait gives KNNG_EINVAL).  info (may be NULL) is filled
+ * also when the batch failed.
+ */
+knng_status knng_server_wait(knng_server *srv, uint64_t ticket, int64_t timeout_us,
+                             int32_t *ids, float *dist, knng_request_info *info);
+
+/* The resident graph (waits for a running batch): *n_rows receives the row
+ * count; out (device, out->n >= rows, out->k = k) receives the lists when
+ * not NULL. */
+knng_status knng_server_snapshot(knng_server *srv, knng_graph *out, int64_t *n_rows);
+
+/* rows merged, rows accepted but not merged yet, batches started */
+knng_status knng_server_status(knng_server *srv, int64_t *resident_rows, int64_t *pending_rows,
+                               int64_t *batches);
+
+/* Finishes a running batch, then frees everything.  Requests still queued
+ * are dropped. */
+void knng_server_destroy(knng_server *srv);
 
 /* thread-local text of the last error ("" after success) */
 const char *knng_last_error(void);

@@ -50,9 +50,16 @@
  *   - UpdateNN rejects self and ids already present, orders entries by
  *     (distance, id) and keeps at most k;
  *   - c is the number of entries present at the end of a round that were
- *     inserted during it; the loop stops when c <= delta*n*k or after
- *     max_rounds rounds;
- *   - Kept (Divide) entries start OLD, appended/initial entries start NEW.
+ *     inserted during it; the loop stops when c <= delta*n0*k or after
+ *     max_rounds rounds, n0 being the number of rows that hold a NEW entry
+ *     when the loop starts (every row in both algorithms as printed);
+ *   - Kept (Divide) entries start OLD, appended/initial entries start NEW;
+ *   - balanced append (J-Merge of a raw set much smaller than the base, a
+ *     case the paper's experiments stop short of): a base row takes part in
+ *     Divide and Append only when a hash draw selects it, with probability
+ *     min(1, n_raw/n_base); other base rows keep their whole list (OLD) and
+ *     receive no samples.  With n_raw >= n_base every row is selected, which
+ *     is Algorithm 2 as printed.
  */
 #include <math.h>
 #include <stdint.h>
@@ -72,6 +79,7 @@
 #define TAG_FWD 0xB1u
 #define TAG_RNEW 0xB2u
 #define TAG_ROLD 0xB3u
+#define TAG_SELECT 0xA3u
 
 /* ------------------------------------------------------------------------ */
 /* SplitMix64                                                                */
@@ -459,7 +467,7 @@ int orc_merge_bruteforce(const float *X1, int64_t n1, const float *X2, int64_t n
 typedef struct {
     float keep_ratio; /* r = k1 / k */
     int32_t sample;   /* s: NEW samples per list and per reverse list */
-    float delta;      /* stop when c <= delta * n * k */
+    float delta;      /* stop when c <= delta * n0 * k */
     int32_t max_rounds;
     uint64_t seed;
 } orc_params;
@@ -534,6 +542,14 @@ static int iterate(state_t *S, const orc_params *P, orc_stats *st)
     }
     st->rounds = 0;
     st->phi[0] = phi_of(S);
+    /* n0: rows that start the loop with a NEW entry (normaliser of delta) */
+    int64_t n0 = 0;
+    for (int64_t u = 0; u < n; u++) {
+        int any = 0;
+        for (int j = 0; j < S->G[u].cnt; j++)
+            any |= S->G[u].e[j].isnew;
+        n0 += any;
+    }
     for (int t = 0; t < P->max_rounds; t++) {
         /* forward sample: up to s NEW entries by smallest priority become
          * the NEW sample and are marked OLD; previously OLD entries are all
@@ -645,7 +661,7 @@ static int iterate(state_t *S, const orc_params *P, orc_stats *st)
             st->phi[t + 1] = phi_of(S);
         }
         st->rounds = t + 1;
-        if ((double)c <= (double)P->delta * (double)n * (double)k)
+        if ((double)c <= (double)P->delta * (double)n0 * (double)k)
             break;
     }
 done:
@@ -669,6 +685,17 @@ done:
     free(grp_new);
     free(grp_old);
     return rc;
+}
+
+/* balanced append: base row i joins Divide and Append when
+ * floor(hi32(H(seed, SELECT, i, 0, 0)) * nb / 2^32) < nr, i.e. with
+ * probability min(1, nr/nb); every row when nr >= nb or when not balanced */
+static int selected_base_row(uint64_t seed, int balanced, int64_t i, int64_t nb, int64_t nr)
+{
+    if (!balanced || nr >= nb)
+        return 1;
+    uint64_t h = orc_hash(seed, TAG_SELECT, (uint64_t)i, 0, 0);
+    return (int64_t)(((h >> 32) * (uint64_t)nb) >> 32) < nr;
 }
 
 static int check_params(const orc_params *P, int k)
@@ -800,7 +827,8 @@ out:
  */
 int orc_jmerge(const float *Xb, int64_t nb, const float *Xr, int64_t nr, int d,
                const int32_t *g_ids, const float *g_dist, int kin, int k, int metric,
-               const orc_params *P, int32_t *out_ids, float *out_dist, orc_stats *st)
+               const orc_params *P, int balanced, int32_t *out_ids, float *out_dist,
+               orc_stats *st)
 {
     if (nb < 0 || nr < 1 || d < 1 || check_params(P, k) != ORC_OK)
         return ORC_EINVAL;
@@ -842,16 +870,21 @@ int orc_jmerge(const float *Xb, int64_t nb, const float *Xr, int64_t nr, int d,
             break;
         S.G[i].e = S.store + i * k;
         S.G[i].cnt = 0;
-        for (int j = 0; j < k1; j++)
+        /* Divide keeps k1 entries of a selected row; an unselected row
+         * (balanced append only) keeps all it can hold */
+        int keep = selected_base_row(P->seed, balanced, i, nb, nr) ? k1 : (kin < k ? kin : k);
+        for (int j = 0; j < keep; j++)
             update_nn(&S.G[i], k, (int32_t)i, row[j].id, row[j].dist, 0, 0);
-        nrear[i] = kin - k1;
-        for (int j = k1; j < kin; j++)
-            rear[i * (kin + 1) + (j - k1)] = row[j];
+        nrear[i] = kin - keep;
+        for (int j = keep; j < kin; j++)
+            rear[i * (kin + 1) + (j - keep)] = row[j];
     }
     if (rc != ORC_OK)
         goto out;
-    /* base rows: Append k - k1 random raw samples (NEW) */
+    /* selected base rows: Append k - k1 random raw samples (NEW) */
     for (int64_t i = 0; i < nb; i++) {
+        if (!selected_base_row(P->seed, balanced, i, nb, nr))
+            continue;
         int m = (int64_t)(k - k1) < nr ? k - k1 : (int)nr;
         distinct_draws(P->seed, TAG_APPEND, (uint64_t)i, (uint32_t)nr, -1, m, draws);
         for (int j = 0; j < m; j++) {

@@ -76,8 +76,8 @@ def lib():
                                  ctypes.POINTER(Params), P, P, ctypes.POINTER(Stats)]
         L.orc_jmerge.restype = ctypes.c_int
         L.orc_jmerge.argtypes = [P, I64, P, I64, ctypes.c_int, P, P, ctypes.c_int,
-                                 ctypes.c_int, ctypes.c_int, ctypes.POINTER(Params), P, P,
-                                 ctypes.POINTER(Stats)]
+                                 ctypes.c_int, ctypes.c_int, ctypes.POINTER(Params), ctypes.c_int,
+                                 P, P, ctypes.POINTER(Stats)]
         L.orc_draws.restype = None
         L.orc_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                 ctypes.c_uint32, I64, ctypes.c_int, P]
@@ -217,10 +217,12 @@ def smerge(X1, G1, X2, G2, k, metric="l2", keep_ratio=0.5, sample=10, delta=0.0,
 
 
 def jmerge(Xb, G, Xr, k, metric="l2", keep_ratio=0.5, sample=10, delta=0.0, max_rounds=30,
-           seed=0):
+           seed=0, balanced=False):
     """J-Merge, Algorithm 2 (G = (ids, dist or None) of the base set; the
     base set may be empty, which makes the call an NN-Descent build of Xr).
-    Returns (ids, dist, stats)."""
+    balanced: only base rows selected with probability min(1, n_raw/n_base)
+    take part in Divide and Append (identical to Algorithm 2 when
+    n_raw >= n_base).  Returns (ids, dist, stats)."""
     Xr = _f32(Xr)
     nr, d = Xr.shape
     if Xb is None or len(Xb) == 0:
@@ -237,8 +239,8 @@ def jmerge(Xb, G, Xr, k, metric="l2", keep_ratio=0.5, sample=10, delta=0.0, max_
     st = Stats()
     P = _params(keep_ratio, sample, delta, max_rounds, seed)
     rc = lib().orc_jmerge(_ptr(Xb), nb, _ptr(Xr), nr, d, _ptr(gi), _ptr(gd), kin, k,
-                          _metric(metric), ctypes.byref(P), _ptr(ids), _ptr(dist),
-                          ctypes.byref(st))
+                          _metric(metric), ctypes.byref(P), int(bool(balanced)), _ptr(ids),
+                          _ptr(dist), ctypes.byref(st))
     _check(rc, "jmerge")
     return ids, dist, _stats_dict(st)
 

@@ -5,272 +5,13 @@
 // k-NN Graph", Sections 3.1-3.2): Divide/Append (or Initialize), then the
 // repeat loop -- per round: sampling, Reverse(G), local join -- until the
 // number of surviving insertions c drops to delta*n*k, then Merge and Sort.
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "../../include/knng_merge.h"
-#include "knng_common.h"
-#include "knng_internal.h"
+#include "knng_host.h"
 
 using namespace knng;
+using namespace knng::host;
 
-namespace {
-
-thread_local std::string g_err;
-
-knng_status fail(knng_status s, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return s;
-}
-
-knng_status ok()
-{
-    g_err.clear();
-    return KNNG_OK;
-}
-
-#define HIP_TRY(expr)                                                                     \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return fail(KNNG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
-    } while (0)
-
-int pad4(int d) { return (d + 3) / 4 * 4; }
-
-// bump allocator over the caller's workspace; with base == nullptr it only
-// measures
-struct Carve {
-    uint8_t *base;
-    size_t off = 0;
-    explicit Carve(void *b) : base((uint8_t *)b) {}
-    template <class T> T *take(size_t count)
-    {
-        off = (off + 255) / 256 * 256;
-        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-        off += count * sizeof(T);
-        return p;
-    }
-};
-
-struct Layout {
-    uint64_t *ctr;
-    float *x, *norm, *sq, *eb;
-    uint16_t *xb;
-    uint64_t *gin, *L, *worst, *rnew, *rold;
-    int32_t *new_f, *old_f, *cnt_f;
-    int dp, db, gstride;
-};
-
-bool uses_bf16(knng_metric m, const knng_opts *o)
-{
-    return o && o->precision == KNNG_BF16_RESCORE && m != KNNG_L1;
-}
-
-// one layout for S-Merge and J-Merge: n rows, input lists on `n_list` rows
-void carve_merge(Carve &c, Layout &w, int64_t n, int64_t n_list, int d, int k, int gstride, int s,
-                 knng_metric m, bool bf16)
-{
-    w.dp = pad4(d);
-    w.db = (d + 31) / 32 * 32;
-    w.gstride = gstride;
-    w.ctr = c.take<uint64_t>(C_WORDS);
-    w.x = c.take<float>((size_t)n * w.dp);
-    w.norm = m == KNNG_COSINE ? c.take<float>(n) : nullptr;
-    w.xb = bf16 ? c.take<uint16_t>((size_t)n * w.db) : nullptr;
-    w.sq = bf16 ? c.take<float>(n) : nullptr;
-    w.eb = bf16 ? c.take<float>(n) : nullptr;
-    w.gin = c.take<uint64_t>((size_t)(n_list > 0 ? n_list : 1) * (gstride > 0 ? gstride : 1));
-    w.L = c.take<uint64_t>((size_t)n * k);
-    w.worst = c.take<uint64_t>(n);
-    w.new_f = c.take<int32_t>((size_t)n * s);
-    w.old_f = c.take<int32_t>((size_t)n * k);
-    w.cnt_f = c.take<int32_t>((size_t)n * 2);
-    w.rnew = c.take<uint64_t>((size_t)n * s);
-    w.rold = c.take<uint64_t>((size_t)n * s);
-}
-
-bool is_device_ptr(const void *p)
-{
-    if (!p)
-        return false;
-    hipPointerAttribute_t attr;
-    hipError_t e = hipPointerGetAttributes(&attr, p);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
-    }
-    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
-}
-
-knng_status check_set(const knng_set *S, const char *name, bool allow_empty = false)
-{
-    if (!S)
-        return fail(KNNG_EINVAL, "%s is NULL", name);
-    if (S->n < (allow_empty ? 0 : 1) || S->n >= (1ll << 30) - 64)
-        return fail(KNNG_EINVAL, "%s->n = %lld out of range", name, (long long)S->n);
-    if (S->d < 1 || S->d > 65536)
-        return fail(KNNG_EINVAL, "%s->d = %d out of range", name, S->d);
-    if (S->n > 0 && !is_device_ptr(S->x))
-        return fail(KNNG_EINVAL, "%s->x is not device memory", name);
-    return KNNG_OK;
-}
-
-knng_status check_graph_in(const knng_graph *G, int64_t n, const char *name, int kmin)
-{
-    if (!G)
-        return fail(KNNG_EINVAL, "%s is NULL", name);
-    if (G->n != n)
-        return fail(KNNG_EINVAL, "%s->n = %lld, expected %lld", name, (long long)G->n,
-                    (long long)n);
-    if (G->k < kmin || G->k > MAX_K || G->k > n - 1)
-        return fail(KNNG_EINVAL, "%s->k = %d out of range [%d, min(64, n-1)]", name, G->k, kmin);
-    if (G->k > 0 && !is_device_ptr(G->ids))
-        return fail(KNNG_EINVAL, "%s->ids is not device memory", name);
-    if (G->dist && !is_device_ptr(G->dist))
-        return fail(KNNG_EINVAL, "%s->dist is not device memory", name);
-    return KNNG_OK;
-}
-
-knng_status check_out(const knng_graph *out, int64_t n, int k)
-{
-    if (!out)
-        return fail(KNNG_EINVAL, "out is NULL");
-    if (out->n != n || out->k != k)
-        return fail(KNNG_EINVAL, "out is %lld x %d, expected %lld x %d", (long long)out->n,
-                    out->k, (long long)n, k);
-    if (!is_device_ptr(out->ids) || !is_device_ptr(out->dist))
-        return fail(KNNG_EINVAL, "out->ids / out->dist must be device memory");
-    return KNNG_OK;
-}
-
-knng_status check_opts(const knng_opts *o, int k)
-{
-    if (!o)
-        return fail(KNNG_EINVAL, "opts is NULL");
-    if (!(o->keep_ratio >= 0.0f && o->keep_ratio <= 1.0f))
-        return fail(KNNG_EINVAL, "keep_ratio %g not in [0, 1]", (double)o->keep_ratio);
-    if (o->sample < 1 || o->sample > MAX_S)
-        return fail(KNNG_EINVAL, "sample %d not in [1, %d]", o->sample, MAX_S);
-    if (!(o->delta >= 0.0f))
-        return fail(KNNG_EINVAL, "delta must be >= 0");
-    if (o->max_rounds < 0)
-        return fail(KNNG_EINVAL, "max_rounds must be >= 0");
-    if (o->precision != KNNG_FP32 && o->precision != KNNG_BF16_RESCORE)
-        return fail(KNNG_EINVAL, "unknown precision %d", o->precision);
-    if (3 * o->sample + k > MAX_G)
-        return fail(KNNG_EINVAL, "3*sample + k = %d exceeds %d", 3 * o->sample + k, MAX_G);
-    return KNNG_OK;
-}
-
-knng_status check_metric(knng_metric m)
-{
-    if (m != KNNG_L2 && m != KNNG_COSINE && m != KNNG_L1)
-        return fail(KNNG_EINVAL, "unknown metric %d", (int)m);
-    return KNNG_OK;
-}
-
-const char *err_text(uint64_t bits)
-{
-    if (bits & ERR_NONFINITE)
-        return "input rows hold a non-finite value";
-    if (bits & ERR_ZERO_NORM)
-        return "cosine metric: an input row has zero norm";
-    if (bits & ERR_ID_RANGE)
-        return "input graph id out of range";
-    if (bits & ERR_SELF)
-        return "input graph row lists itself";
-    if (bits & ERR_DUP)
-        return "input graph row holds a duplicate id";
-    if (bits & ERR_UNSORTED)
-        return "input graph row not sorted by (distance, id)";
-    if (bits & ERR_BAD_DIST)
-        return "input graph distance negative or not finite";
-    if (bits & ERR_SPIN)
-        return "internal: list insert exceeded its retry budget";
-    if (bits & ERR_GROUP)
-        return "internal: neighbourhood exceeded the kernel bound";
-    return "unknown device error";
-}
-
-// reads the counter block; returns the error bits
-knng_status read_ctr(const uint64_t *dctr, uint64_t *h, hipStream_t st)
-{
-    HIP_TRY(hipMemcpyAsync(h, dctr, sizeof(uint64_t) * C_WORDS, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    return KNNG_OK;
-}
-
-// phase timing with HIP events (KNNG_FLAG_PROFILE)
-struct Prof {
-    bool on;
-    hipStream_t st;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
-    hipEvent_t cur = nullptr;
-    int cur_phase = -1;
-    void begin(int phase)
-    {
-        if (!on)
-            return;
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess)
-            return;
-        (void)hipEventRecord(e, st);
-        cur = e;
-        cur_phase = phase;
-    }
-    void end()
-    {
-        if (!on || !cur)
-            return;
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess)
-            return;
-        (void)hipEventRecord(e, st);
-        ev.push_back({cur_phase, {cur, e}});
-        cur = nullptr;
-    }
-    void collect(knng_stats *s)
-    {
-        if (!on)
-            return;
-        (void)hipStreamSynchronize(st);
-        for (auto &p : ev) {
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, p.second.first, p.second.second);
-            if (s) {
-                double *slot[] = {&s->ms_prep, &s->ms_init, &s->ms_sample, &s->ms_reverse,
-                                  &s->ms_join, &s->ms_final};
-                *slot[p.first] += ms;
-                if (p.first == 4)
-                    s->join_launches++;
-            }
-            (void)hipEventDestroy(p.second.first);
-            (void)hipEventDestroy(p.second.second);
-        }
-        ev.clear();
-    }
-    ~Prof()
-    {
-        for (auto &p : ev) {
-            (void)hipEventDestroy(p.second.first);
-            (void)hipEventDestroy(p.second.second);
-        }
-        if (cur)
-            (void)hipEventDestroy(cur);
-    }
-};
-enum { PH_PREP = 0, PH_INIT, PH_SAMPLE, PH_REVERSE, PH_JOIN, PH_FINAL };
+namespace knng {
+namespace host {
 
 // layout + input preparation shared by both merges.  Rows [0, n1) come from
 // set A (input lists of A on rows [0, n1)), rows [n1, n) from set B (input
@@ -319,10 +60,15 @@ knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
 knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool bf16,
                       const knng_opts *o, int64_t n, int64_t n1, int k, int k1, int joint,
                       int64_t rows_with_rear, knng_graph *out, hipStream_t st, knng_stats *stats,
-                      Prof &prof)
+                      Prof &prof, uint64_t *out_keys)
 {
+    const int balanced = joint && (o->flags & KNNG_FLAG_BALANCED_APPEND) ? 1 : 0;
     InitArgs ia;
     ia.L = w.L;
+    ia.worst = w.worst;
+    ia.dtag = w.dtag;
+    ia.atag = w.atag;
+    ia.balanced = balanced;
     ia.gin = w.gin;
     ia.kin = w.gstride;
     ia.k = k;
@@ -344,6 +90,8 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     a.cnt_f = w.cnt_f;
     a.rnew = w.rnew;
     a.rold = w.rold;
+    a.dtag = w.dtag;
+    a.atag = w.atag;
     a.ctr = w.ctr;
     a.n = n;
     a.n1 = n1;
@@ -351,7 +99,6 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     a.s = o->sample;
     a.joint = joint;
     a.seed = o->seed;
-    const double thr = (double)o->delta * (double)n * (double)k;
     uint64_t h[C_WORDS];
     int rounds = 0;
     for (int t = 0;; t++) {
@@ -375,13 +122,16 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
                 stats->gathered[t - 1] = (int64_t)h[C_GATHER];
             }
             rounds = t;
-            if ((double)h[C_FRESH] <= thr)
+            // delta is relative to the rows that started the loop with NEW
+            // entries (all rows, except under balanced append)
+            if ((double)h[C_FRESH] <= (double)o->delta * (double)h[C_N0] * (double)k)
                 break;
         }
         if (last)
             break;
         HIP_TRY(launch_zero_counters(w.ctr, C_ROUND_WORDS, st));
         prof.begin(PH_REVERSE);
+        HIP_TRY(launch_prep_active(a, st));
         HIP_TRY(launch_reverse(a, st));
         prof.end();
         prof.begin(PH_JOIN);
@@ -389,8 +139,21 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
         prof.end();
     }
     prof.begin(PH_FINAL);
-    HIP_TRY(launch_final(w.L, k, w.gin, w.gstride, k1, rows_with_rear, n, out->ids, out->dist,
-                         st));
+    FinalArgs fa;
+    fa.L = w.L;
+    fa.gin = w.gin;
+    fa.k = k;
+    fa.kin = w.gstride;
+    fa.k1 = k1;
+    fa.rows_with_rear = rows_with_rear;
+    fa.n = n;
+    fa.balanced = balanced;
+    fa.n_raw = n - n1;
+    fa.seed = o->seed;
+    fa.out_ids = out ? out->ids : nullptr;
+    fa.out_dist = out ? out->dist : nullptr;
+    fa.out_keys = out_keys;
+    HIP_TRY(launch_final(fa, st));
     prof.end();
     knng_status s = read_ctr(w.ctr, h, st);
     if (s != KNNG_OK)
@@ -409,9 +172,9 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     return ok();
 }
 
-int keep_count(const knng_opts *o, int k) { return (int)floorf(o->keep_ratio * (float)k); }
 
-} // namespace
+} // namespace host
+} // namespace knng
 
 extern "C" {
 

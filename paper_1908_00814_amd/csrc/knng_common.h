@@ -43,6 +43,7 @@ enum : int {
     C_ERR = 6,      // error bits
     C_ATTEMPT = 7,  // list inserts attempted after the screen
     C_VIOL = 8,     // BF16 path: rescored pairs outside the screening margin
+    C_N0 = 9,       // rows holding a NEW entry when the loop starts
     C_WORDS = 10,
 };
 
@@ -89,13 +90,24 @@ __device__ __forceinline__ uint64_t hash5(uint64_t seed, uint64_t tag, uint64_t 
     return sm64(h ^ c);
 }
 
-constexpr uint32_t TAG_APPEND = 0xA1u, TAG_INIT = 0xA2u, TAG_FWD = 0xB1u, TAG_RNEW = 0xB2u,
-                   TAG_ROLD = 0xB3u;
+constexpr uint32_t TAG_APPEND = 0xA1u, TAG_INIT = 0xA2u, TAG_SELECT = 0xA3u, TAG_FWD = 0xB1u,
+                   TAG_RNEW = 0xB2u, TAG_ROLD = 0xB3u;
 
 // uniform draw below N from the high 32 bits (multiply-shift)
 __device__ __forceinline__ uint32_t draw_below(uint64_t h, uint32_t N)
 {
     return (uint32_t)(((h >> 32) * (uint64_t)N) >> 32);
+}
+
+// Balanced append (J-Merge of a raw set smaller than the base): base row i
+// takes part in Divide and Append when draw_below(H(seed, SELECT, i), nb) <
+// nr, i.e. with probability nr/nb; all rows when nr >= nb or when off.
+__device__ __forceinline__ bool selected_base_row(uint64_t seed, int balanced, int64_t i,
+                                                  int64_t nb, int64_t nr)
+{
+    if (!balanced || nr >= nb)
+        return true;
+    return (int64_t)draw_below(hash5(seed, TAG_SELECT, (uint64_t)i, 0, 0), (uint32_t)nb) < nr;
 }
 
 // ---------------------------------------------------------------- canonical FP32

@@ -29,6 +29,18 @@ struct RoundArgs {
     int32_t *cnt_f;     // n x 2: (#new_f, #old_f)
     uint64_t *rnew;     // n x s reverse NEW reservoirs
     uint64_t *rold;     // n x s reverse OLD reservoirs
+    // Row tags (rounds are numbered from 0; -1 = never):
+    //   dtag[u] = t: u holds NEW entries to sample in round t (set by Divide/
+    //            Append/Initialize for t = 0, by an insert during round t-1,
+    //            or by round t-1's sampling when more than s NEW entries were
+    //            left).  Before round t's join, u is sampled in round t iff
+    //            dtag[u] >= t.
+    //   atag[u] = t: u's round-t neighbourhood has a NEW member (u sampled
+    //            NEW entries, or a row sampled u as a NEW entry).
+    // Rows outside both sets hold only OLD entries: their neighbourhood has no
+    // NEW member and joins nothing, and their whole list is their OLD sample.
+    int32_t *dtag;
+    int32_t *atag;
     uint64_t *ctr;      // counter words
     int64_t n;
     int64_t n1;         // first row of the second set
@@ -52,22 +64,41 @@ hipError_t launch_prep_input(const Rows &R, int metric, int64_t row0, int64_t nr
 // Divide + Append (rows with an input list) and Initialize (raw rows).
 struct InitArgs {
     uint64_t *L;
+    uint64_t *worst;    // n: maximum word of each list
+    int32_t *dtag, *atag;
     const uint64_t *gin;
     int kin, k, k1;
     int64_t n, n1;      // n1: rows of the first set (S1 or base)
     int joint;          // J-Merge: rows >= n1 are raw
+    int balanced;       // J-Merge: balanced append (base rows selected by hash)
     uint64_t seed;
     uint64_t *ctr;
 };
 hipError_t launch_init(const Rows &R, int metric, const InitArgs &a, hipStream_t st);
-// Merge and Sort: list + set-aside rear part -> output rows.
-hipError_t launch_final(const uint64_t *L, int k, const uint64_t *gin, int kin, int k1,
-                        int64_t rows_with_rear, int64_t n, int32_t *out_ids, float *out_dist,
-                        hipStream_t st);
+// Merge and Sort: list + set-aside rear part -> output rows.  Rows below
+// rows_with_rear have a rear part: gin entries from k1 on (or, for base rows
+// that balanced append leaves unselected, from min(kin, k) on).
+struct FinalArgs {
+    const uint64_t *L;
+    const uint64_t *gin;
+    int k, kin, k1;
+    int64_t rows_with_rear, n;
+    int balanced;
+    int64_t n_raw;
+    uint64_t seed;
+    int32_t *out_ids;    // n x k, or nullptr
+    float *out_dist;     // n x k, or nullptr
+    uint64_t *out_keys;  // n x kin sorted keys (may be gin itself), or nullptr
+};
+hipError_t launch_final(const FinalArgs &a, hipStream_t st);
+// sorted keys (stride kin) -> ids / distances (n x k); empty slots give -1 / +inf
+hipError_t launch_keys_to_graph(const uint64_t *keys, int kin, int64_t n, int k,
+                                int32_t *ids, float *dist, hipStream_t st);
 hipError_t launch_zero_counters(uint64_t *ctr, int words, hipStream_t st);
 
 // ---- knng_round.hip
 hipError_t launch_sample(const RoundArgs &a, hipStream_t st);
+hipError_t launch_prep_active(const RoundArgs &a, hipStream_t st);
 hipError_t launch_reverse(const RoundArgs &a, hipStream_t st);
 hipError_t launch_count_fresh(const RoundArgs &a, hipStream_t st);
 

@@ -269,6 +269,16 @@ __device__ __forceinline__ bool tile_of(int t, const Regions &g, int joint, int 
     return false;
 }
 
+// UpdateNN of one proposal: the list of row dst takes key if it beats the
+// worst entry and is not there yet; a row that took an entry is sampled in
+// the next round
+template <int KB>
+__device__ __forceinline__ void insert_into(const RoundArgs &a, int64_t dst, uint64_t key)
+{
+    if (bounded_insert<KB>(a.L + dst * a.k, a.k, key, true, a.worst + dst, a.ctr + C_ERR))
+        a.dtag[dst] = a.round + 1;
+}
+
 // Drain a queue of (target row, key) words: every entry is offered to its
 // list (the insert's own read of the list rejects entries that no longer beat
 // its worst).  Returns the number of inserts attempted (wave-uniform).
@@ -280,8 +290,7 @@ __device__ inline int drain_keys(const uint64_t *qkey, const int32_t *qdst, int 
         const int e = e0 + lane_id();
         if (e < qn) {
             const int32_t dst = qdst[e];
-            bounded_insert<KB>(a.L + (int64_t)dst * a.k, a.k, qkey[e], true, a.worst + dst,
-                               a.ctr + C_ERR);
+            insert_into<KB>(a, dst, qkey[e]);
         }
     }
     return qn;
@@ -329,8 +338,14 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join(Rows R, RoundArgs a,
     uint64_t n_pairs = 0, n_gather = 0, n_attempt = 0;
     int maxg = 0;
     const int64_t nwaves = (int64_t)gridDim.x * JOIN_WAVES;
-    for (int64_t u = (int64_t)blockIdx.x * JOIN_WAVES + threadIdx.x / WAVE; u < a.n;
-         u += nwaves) {
+    const int64_t wave0 = (int64_t)blockIdx.x * JOIN_WAVES + threadIdx.x / WAVE;
+    // rows wave0 + j*nwaves, 64 at a time; only rows with a NEW member join
+    for (int64_t b = wave0; b < a.n; b += nwaves * WAVE) {
+        const int64_t r = b + (int64_t)lane * nwaves;
+        uint64_t todo = __ballot(r < a.n && a.atag[r] == a.round);
+        while (todo) {
+        const int64_t u = b + (int64_t)__builtin_ctzll(todo) * nwaves;
+        todo &= todo - 1;
         __builtin_amdgcn_wave_barrier();
         Regions g;
         if (!build_group<METRIC, false>(u, R, a, L, g))
@@ -418,6 +433,7 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join(Rows R, RoundArgs a,
             __builtin_amdgcn_wave_barrier();
             n_attempt += drain_keys<KB>(qkey, qdst, qn, a);
             __builtin_amdgcn_wave_barrier();
+        }
         }
     }
     flush_counters(a, n_pairs, n_gather, n_attempt, 0, 0, maxg);
@@ -507,8 +523,14 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
     uint64_t n_pairs = 0, n_gather = 0, n_attempt = 0, n_rescore = 0, n_viol = 0;
     int maxg = 0;
     const int64_t nwaves = (int64_t)gridDim.x * JOIN_WAVES;
-    for (int64_t u = (int64_t)blockIdx.x * JOIN_WAVES + threadIdx.x / WAVE; u < a.n;
-         u += nwaves) {
+    const int64_t wave0 = (int64_t)blockIdx.x * JOIN_WAVES + threadIdx.x / WAVE;
+    // rows wave0 + j*nwaves, 64 at a time; only rows with a NEW member join
+    for (int64_t b = wave0; b < a.n; b += nwaves * WAVE) {
+        const int64_t r = b + (int64_t)lane * nwaves;
+        uint64_t todo = __ballot(r < a.n && a.atag[r] == a.round);
+        while (todo) {
+        const int64_t u = b + (int64_t)__builtin_ctzll(todo) * nwaves;
+        todo &= todo - 1;
         __builtin_amdgcn_wave_barrier();
         Regions g;
         if (!build_group<METRIC, true>(u, R, a, L, g))
@@ -642,14 +664,13 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
                     }
                     n_attempt += __popcll(__ballot(gp)) + __popcll(__ballot(gq));
                     if (gp)
-                        bounded_insert<KB>(a.L + (int64_t)pp * a.k, a.k, kp, true, a.worst + pp,
-                                           a.ctr + C_ERR);
+                        insert_into<KB>(a, pp, kp);
                     if (gq)
-                        bounded_insert<KB>(a.L + (int64_t)qq * a.k, a.k, kqk, true,
-                                           a.worst + qq, a.ctr + C_ERR);
+                        insert_into<KB>(a, qq, kqk);
                 }
                 __builtin_amdgcn_wave_barrier();
             }
+        }
         }
     }
     flush_counters(a, n_pairs, n_gather, n_attempt, n_rescore, n_viol, maxg);

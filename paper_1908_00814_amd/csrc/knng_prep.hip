@@ -175,6 +175,7 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
     int32_t *picked = picked_all[w];
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     uint64_t evals = 0;
+    int n0 = 0;
     for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE; i < a.n;
          i += nwaves) {
     __builtin_amdgcn_wave_barrier();
@@ -190,6 +191,11 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
         skip = -1;
         first = a.k1;
         m = (int64_t)(a.k - a.k1) < n_other ? a.k - a.k1 : (int)n_other;
+        if (a.joint && !selected_base_row(a.seed, a.balanced, i, a.n1, a.n - a.n1)) {
+            // balanced append, row not selected: the whole list stays (OLD)
+            first = a.kin < a.k ? a.kin : a.k;
+            m = 0;
+        }
     } else {
         // Initialize: k samples of S u raw, self excluded
         N = (uint32_t)a.n;
@@ -202,7 +208,8 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
     const uint32_t avail = N - (skip >= 0 ? 1u : 0u);
     // m distinct draws in draw order (the first m distinct values of the stream)
     int got = 0;
-    if ((uint32_t)m >= avail) {
+    if (m == 0) {
+    } else if ((uint32_t)m >= avail) {
         if (lane < m)
             picked[lane] = (int32_t)((skip >= 0 && lane >= skip) ? lane + 1 : lane);
         got = m;
@@ -255,10 +262,11 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
         got = __shfl(got, 0, WAVE);
     }
     __builtin_amdgcn_wave_barrier();
+    uint64_t key = 0;
     if (lane < a.k) {
-        uint64_t key;
         if (lane < first) {
-            key = key_strip(a.gin[i * a.kin + lane]);  // kept entries start OLD
+            key = a.gin[i * a.kin + lane];  // kept entries start OLD
+            key = key_empty(key) ? empty_key(lane) : key_strip(key);
         } else if (lane < first + m) {
             int64_t g = picked[lane - first] + cand_off;
             float na = R.norm ? R.norm[i] : 0.0f, nb = R.norm ? R.norm[g] : 0.0f;
@@ -269,21 +277,35 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
         }
         a.L[i * a.k + lane] = key;
     }
+    // the list's maximum word (an empty slot when the list is not full); the
+    // row is sampled in round 0 iff it holds a NEW entry
+    const uint64_t wv = wave_max_u64(key_empty(key) ? key : key_strip(key));
+    if (lane == 0) {
+        a.worst[i] = wv;
+        a.dtag[i] = m > 0 ? 0 : -1;
+        a.atag[i] = -1;
+    }
     evals += (uint64_t)m;
+    n0 += m > 0;
     __builtin_amdgcn_wave_barrier();
     }
     // one atomic per wave for the distance evaluations of all its rows
     if (lane == 0 && evals)
         atomicAdd((unsigned long long *)(a.ctr + C_EVALS), (unsigned long long)evals);
+    if (lane == 0 && n0)
+        atomicAdd((unsigned long long *)(a.ctr + C_N0), (unsigned long long)n0);
 }
 
 // one wave per row: top k of the list and the rear part, deduplicated
-__global__ __launch_bounds__(256) void k_final(const uint64_t *__restrict__ L, int k,
-                                               const uint64_t *__restrict__ gin, int kin, int k1,
-                                               int64_t rows_with_rear, int64_t n,
-                                               int32_t *__restrict__ out_ids,
-                                               float *__restrict__ out_dist)
+__global__ __launch_bounds__(256) void k_final(FinalArgs a)
 {
+    const uint64_t *__restrict__ L = a.L;
+    const uint64_t *gin = a.gin;
+    const int k = a.k, kin = a.kin;
+    const int64_t n = a.n;
+    int32_t *out_ids = a.out_ids;
+    float *out_dist = a.out_dist;
+    uint64_t *out_keys = a.out_keys;  // may alias gin: row i is read before it is written
     __shared__ uint64_t cand_all[4][2 * WAVE];
     __shared__ uint64_t kept_all[4][2 * WAVE];
     const int lane = lane_id();
@@ -293,9 +315,12 @@ __global__ __launch_bounds__(256) void k_final(const uint64_t *__restrict__ L, i
     const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
     if (i >= n)
         return;
-    const int nrear = i < rows_with_rear ? kin - k1 : 0;
+    int rear0 = a.k1;
+    if (!selected_base_row(a.seed, a.balanced, i, a.rows_with_rear, a.n_raw))
+        rear0 = kin < k ? kin : k;
+    const int nrear = i < a.rows_with_rear ? kin - rear0 : 0;
     uint64_t c0 = lane < k ? key_strip(L[i * k + lane]) : ~0ull;
-    uint64_t c1 = lane < nrear ? key_strip(gin[i * kin + k1 + lane]) : ~0ull;
+    uint64_t c1 = lane < nrear ? key_strip(gin[i * kin + rear0 + lane]) : ~0ull;
     if (key_empty(c0))
         c0 = ~0ull;
     if (key_empty(c1))
@@ -322,18 +347,45 @@ __global__ __launch_bounds__(256) void k_final(const uint64_t *__restrict__ L, i
         r1 += o < c1;
     }
     int nvalid = wave_sum((int)v0 + (int)v1);
-    if (v0 && r0 < k) {
-        out_ids[i * k + r0] = (int32_t)key_id(c0);
-        out_dist[i * k + r0] = key_dist(c0);
+    if (out_ids) {
+        if (v0 && r0 < k) {
+            out_ids[i * k + r0] = (int32_t)key_id(c0);
+            out_dist[i * k + r0] = key_dist(c0);
+        }
+        if (v1 && r1 < k) {
+            out_ids[i * k + r1] = (int32_t)key_id(c1);
+            out_dist[i * k + r1] = key_dist(c1);
+        }
+        if (lane >= nvalid && lane < k) {
+            out_ids[i * k + lane] = -1;
+            out_dist[i * k + lane] = __uint_as_float(0x7F800000u);
+        }
     }
-    if (v1 && r1 < k) {
-        out_ids[i * k + r1] = (int32_t)key_id(c1);
-        out_dist[i * k + r1] = key_dist(c1);
+    if (out_keys) {
+        __builtin_amdgcn_wave_barrier();  // every read of row i precedes its writes
+        if (v0 && r0 < k)
+            out_keys[i * kin + r0] = c0;
+        if (v1 && r1 < k)
+            out_keys[i * kin + r1] = c1;
+        if (lane >= (nvalid < k ? nvalid : k) && lane < kin)
+            out_keys[i * kin + lane] = ~0ull;
     }
-    if (lane >= nvalid && lane < k) {
-        out_ids[i * k + lane] = -1;
-        out_dist[i * k + lane] = __uint_as_float(0x7F800000u);
-    }
+}
+
+// one thread per entry
+__global__ __launch_bounds__(256) void k_keys_to_graph(const uint64_t *__restrict__ keys,
+                                                       int kin, int64_t n, int k,
+                                                       int32_t *__restrict__ ids,
+                                                       float *__restrict__ dist)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n * k)
+        return;
+    const int64_t i = e / k;
+    const uint64_t v = keys[i * kin + (e - i * k)];
+    const bool empty = key_empty(v);
+    ids[e] = empty ? -1 : (int32_t)key_id(v);
+    dist[e] = empty ? __uint_as_float(0x7F800000u) : key_dist(v);
 }
 
 __global__ void k_zero(uint64_t *p, int words)
@@ -404,12 +456,19 @@ hipError_t launch_init(const Rows &R, int metric, const InitArgs &a, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_final(const uint64_t *L, int k, const uint64_t *gin, int kin, int k1,
-                        int64_t rows_with_rear, int64_t n, int32_t *out_ids, float *out_dist,
-                        hipStream_t st)
+hipError_t launch_final(const FinalArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_final, dim3(grid_for(n, 4)), dim3(256), 0, st, L, k, gin, kin, k1,
-                       rows_with_rear, n, out_ids, out_dist);
+    hipLaunchKernelGGL(k_final, dim3(grid_for(a.n, 4)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys_to_graph(const uint64_t *keys, int kin, int64_t n, int k, int32_t *ids,
+                                float *dist, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_keys_to_graph, dim3(grid_for(n * k, 256)), dim3(256), 0, st, keys, kin,
+                       n, k, ids, dist);
     return hipGetLastError();
 }
 

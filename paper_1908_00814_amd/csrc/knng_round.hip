@@ -15,15 +15,27 @@ namespace knng {
 
 namespace {
 
-// one wave per row (k <= 64 lanes), grid-stride over rows; the FRESH count is
-// accumulated per wave and added once
+// Rows are visited wave-strided (row u by wave u mod W), 64 candidate rows at
+// a time: one tag load per lane and a ballot pick the rows to work on.
+#define FOR_TAGGED_ROWS(u, n, tagarr, want)                                                   \
+    const int64_t nwaves_ = (int64_t)gridDim.x * (blockDim.x / WAVE);                        \
+    const int64_t wave0_ = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;          \
+    for (int64_t b_ = wave0_; b_ < (n); b_ += nwaves_ * WAVE)                                 \
+        for (uint64_t todo_ = __ballot(b_ + (int64_t)lane_id() * nwaves_ < (n) &&            \
+                                       (tagarr)[b_ + (int64_t)lane_id() * nwaves_] == (want)); \
+             todo_; todo_ &= todo_ - 1)                                                       \
+            if (const int64_t u = b_ + (int64_t)__builtin_ctzll(todo_) * nwaves_; true)
+
+// Forward sample of round t over the rows holding NEW entries (dtag == t), one
+// wave per row (k <= 64 lanes).  Marks u and every sampled NEW entry as
+// active in round t; a row left with more than s NEW entries is sampled
+// again in round t+1.  The FRESH count of round t-1 is accumulated per wave.
 __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
 {
     const int lane = lane_id();
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     int fresh_total = 0;
-    for (int64_t u = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE; u < a.n;
-         u += nwaves) {
+    FOR_TAGGED_ROWS(u, a.n, a.dtag, a.round)
+    {
         const bool act = lane < a.k;
         uint64_t v = act ? a.L[u * a.k + lane] : ~0ull;
         const bool empty = !act || key_empty(v);
@@ -43,8 +55,10 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
             nnew += o != ~0ull;
         }
         const bool sampled = isnew && rank < a.s;
-        if (sampled)
+        if (sampled) {
             a.new_f[u * a.s + rank] = (int32_t)id;
+            a.atag[id] = a.round;
+        }
         uint64_t nv = v & ~(uint64_t)F_FRESH;
         if (sampled)
             nv &= ~(uint64_t)F_NEW;
@@ -61,17 +75,47 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
             a.worst[u] = wv;
             a.cnt_f[2 * u] = nnew < a.s ? nnew : a.s;
             a.cnt_f[2 * u + 1] = __popcll(om);
-        }
-        if (lane < a.s) {
-            a.rnew[u * a.s + lane] = empty_key(lane);
-            a.rold[u * a.s + lane] = empty_key(lane);
+            if (nnew > 0)
+                a.atag[u] = a.round;
+            if (nnew > a.s)
+                a.dtag[u] = a.round + 1;
         }
     }
     if (lane == 0 && fresh_total)
         atomicAdd((unsigned long long *)(a.ctr + C_FRESH), (unsigned long long)fresh_total);
 }
 
-// one thread per sampled edge u -> v
+// Rows active in round t: empty reverse reservoirs; a row that was not
+// sampled (all its entries OLD) takes its whole list as its OLD sample.
+__global__ __launch_bounds__(256) void k_prep_active(RoundArgs a)
+{
+    const int lane = lane_id();
+    FOR_TAGGED_ROWS(u, a.n, a.atag, a.round)
+    {
+        if (lane < a.s) {
+            a.rnew[u * a.s + lane] = empty_key(lane);
+            a.rold[u * a.s + lane] = empty_key(lane);
+        }
+        if (a.dtag[u] < a.round) {
+            const uint64_t v = lane < a.k ? a.L[u * a.k + lane] : ~0ull;
+            const bool has = lane < a.k && !key_empty(v);
+            const uint64_t m = __ballot(has);
+            if (has)
+                a.old_f[u * a.k + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)key_id(v);
+            if (lane == 0) {
+                a.cnt_f[2 * u] = 0;
+                a.cnt_f[2 * u + 1] = __popcll(m);
+            }
+        }
+    }
+}
+
+// Reverse(G) of round t, one thread per (row u, slot): a sampled edge u -> v
+// offers u to v's reverse list of its kind.  NEW edges come from the rows
+// sampled this round (their targets are active by construction); OLD edges
+// from every row (a row not sampled this round has only OLD entries) and
+// are kept only for active targets, the only rows whose neighbourhood is
+// joined.
 __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
 {
     const int per = a.s + a.k;
@@ -80,20 +124,30 @@ __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
          e += (int64_t)gridDim.x * blockDim.x) {
         int64_t u = e / per;
         int j = (int)(e - u * per);
+        const bool sampled = a.dtag[u] >= a.round;
         int32_t v;
         uint32_t tag;
         uint64_t *res;
         if (j < a.s) {
-            if (j >= a.cnt_f[2 * u])
+            if (!sampled || j >= a.cnt_f[2 * u])
                 continue;
             v = a.new_f[u * a.s + j];
             tag = TAG_RNEW;
             res = a.rnew;
         } else {
             j -= a.s;
-            if (j >= a.cnt_f[2 * u + 1])
+            if (sampled) {
+                if (j >= a.cnt_f[2 * u + 1])
+                    continue;
+                v = a.old_f[u * a.k + j];
+            } else {
+                const uint64_t w = a.L[u * a.k + j];
+                if (key_empty(w))
+                    continue;
+                v = (int32_t)key_id(w);
+            }
+            if (a.atag[v] != a.round)
                 continue;
-            v = a.old_f[u * a.k + j];
             tag = TAG_ROLD;
             res = a.rold;
         }
@@ -131,6 +185,12 @@ inline unsigned grid_for(int64_t items, int per_block, unsigned cap)
 hipError_t launch_sample(const RoundArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_sample, dim3(grid_for(a.n, 4, 8192)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_active(const RoundArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_prep_active, dim3(grid_for(a.n, 4, 8192)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -17,15 +17,19 @@ METRICS = {"l2": L2, "cos": COSINE, "cosine": COSINE, "l1": L1}
 FP32, BF16_RESCORE = 0, 1
 PRECISIONS = {"fp32": FP32, "bf16": BF16_RESCORE, "bf16_rescore": BF16_RESCORE}
 FLAG_PROFILE = 1
+FLAG_BALANCED_APPEND = 2
 STATS_ROUNDS = 64
 
-STATUS = {0: "KNNG_OK", 1: "KNNG_EINVAL", 2: "KNNG_ENOMEM", 3: "KNNG_EDEVICE"}
+STATUS = {0: "KNNG_OK", 1: "KNNG_EINVAL", 2: "KNNG_ENOMEM", 3: "KNNG_EDEVICE", 4: "KNNG_EBUSY"}
 
 ENTRY_POINTS = ["knng_opts_default", "knng_merge", "knng_merge_workspace_size", "knng_expand",
                 "knng_expand_workspace_size", "knng_merge_bruteforce",
                 "knng_bruteforce_workspace_size", "knng_exact_graph",
                 "knng_exact_graph_workspace_size", "knng_last_error", "knng_version",
-                "knng_merge_tree", "knng_merge_tree_workspace_size"]
+                "knng_merge_tree", "knng_merge_tree_workspace_size", "knng_server_bytes",
+                "knng_server_create", "knng_server_submit", "knng_server_step",
+                "knng_server_wait", "knng_server_snapshot", "knng_server_status",
+                "knng_server_destroy"]
 
 
 class Opts(ctypes.Structure):
@@ -67,6 +71,23 @@ class Stats(ctypes.Structure):
                        "reverse": self.ms_reverse, "join": self.ms_join,
                        "final": self.ms_final},
                 "join_launches": self.join_launches}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("max_batch", ctypes.c_int64),
+                ("hbm_budget", ctypes.c_uint64), ("manual", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("first_id", ctypes.c_int64), ("batch", ctypes.c_int64),
+                ("batch_rows", ctypes.c_int64), ("evals", ctypes.c_int64),
+                ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double),
+                ("done_us", ctypes.c_double)]
+
+    def to_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class KnngError(RuntimeError):
@@ -111,6 +132,24 @@ def load():
     lib.knng_merge_tree.argtypes = [pS, P, pG, I32, I32, ctypes.c_int, pO, pG, P, SZ, P, pSt]
     lib.knng_merge_tree_workspace_size.restype = SZ
     lib.knng_merge_tree_workspace_size.argtypes = [I64, I32, I32, P, I32, I32, ctypes.c_int, pO]
+    lib.knng_server_bytes.restype = SZ
+    lib.knng_server_bytes.argtypes = [I64, I64, I32, I32, I32, ctypes.c_int, pO]
+    lib.knng_server_create.restype = ctypes.c_int
+    lib.knng_server_create.argtypes = [pS, pG, I32, ctypes.c_int, pO,
+                                       ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
+    lib.knng_server_submit.restype = ctypes.c_int
+    lib.knng_server_submit.argtypes = [P, P, I64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.knng_server_step.restype = ctypes.c_int
+    lib.knng_server_step.argtypes = [P, ctypes.POINTER(I32)]
+    lib.knng_server_wait.restype = ctypes.c_int
+    lib.knng_server_wait.argtypes = [P, ctypes.c_uint64, I64, P, P, ctypes.POINTER(RequestInfo)]
+    lib.knng_server_snapshot.restype = ctypes.c_int
+    lib.knng_server_snapshot.argtypes = [P, pG, ctypes.POINTER(I64)]
+    lib.knng_server_status.restype = ctypes.c_int
+    lib.knng_server_status.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                       ctypes.POINTER(I64)]
+    lib.knng_server_destroy.restype = None
+    lib.knng_server_destroy.argtypes = [P]
     lib.knng_last_error.restype = ctypes.c_char_p
     lib.knng_last_error.argtypes = []
     lib.knng_version.restype = ctypes.c_int
@@ -146,7 +185,7 @@ def _metric(m):
 
 
 def opts(keep_ratio=0.5, sample=10, delta=0.0, max_rounds=30, seed=0, precision="fp32",
-         profile=False):
+         profile=False, balanced=False):
     o = Opts()
     load().knng_opts_default(ctypes.byref(o))
     o.keep_ratio = keep_ratio
@@ -155,7 +194,7 @@ def opts(keep_ratio=0.5, sample=10, delta=0.0, max_rounds=30, seed=0, precision=
     o.max_rounds = max_rounds
     o.seed = seed & (2 ** 64 - 1)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    o.flags = FLAG_PROFILE if profile else 0
+    o.flags = (FLAG_PROFILE if profile else 0) | (FLAG_BALANCED_APPEND if balanced else 0)
     return o
 
 
@@ -287,3 +326,82 @@ def merge_tree(X, starts, graphs, k, metric="l2", stream=None, workspace=None, *
 
 def version():
     return load().knng_version()
+
+
+class Server:
+    """J-Merge serving (knng_server_*): a resident base that absorbs requests
+    of raw rows, merged in batches.  base: device (n, d) fp32; G = (ids, dist
+    or None) of the base, local ids."""
+
+    def __init__(self, base, G, k, metric="l2", capacity=None, max_batch=None, hbm_budget=0,
+                 manual=False, **kw):
+        lib = load()
+        o = opts(**kw)
+        cfg = ServerConfig(int(capacity if capacity is not None else 2 * base.shape[0]),
+                           int(max_batch if max_batch is not None else base.shape[0]),
+                           int(hbm_budget), int(bool(manual)), 0)
+        h = ctypes.c_void_p()
+        _check(lib.knng_server_create(ctypes.byref(_set(base)), ctypes.byref(_graph(*G)), k,
+                                      _metric(metric), ctypes.byref(o), ctypes.byref(cfg),
+                                      ctypes.byref(h)))
+        self._h, self.k, self.d, self.device = h, k, base.shape[1], base.device
+
+    def submit(self, raw):
+        """Queues the rows of raw ((n, d) fp32, device tensor or host
+        tensor/array; copied before return).  Returns the ticket."""
+        if not isinstance(raw, torch.Tensor):
+            raw = torch.from_numpy(raw)
+        assert raw.dtype == torch.float32 and raw.dim() == 2 and raw.shape[1] == self.d
+        raw = raw.contiguous()
+        t = ctypes.c_uint64()
+        _check(load().knng_server_submit(self._h, ctypes.c_void_p(raw.data_ptr()), raw.shape[0],
+                                         ctypes.byref(t)))
+        return t.value
+
+    def step(self):
+        """Manual servers: runs one batch; False when nothing was waiting."""
+        ran = ctypes.c_int32()
+        _check(load().knng_server_step(self._h, ctypes.byref(ran)))
+        return bool(ran.value)
+
+    def wait(self, ticket, n_rows, timeout_us=-1):
+        """(ids, dist) host tensors of the request's rows and its info dict."""
+        ids = torch.empty((n_rows, self.k), dtype=torch.int32)
+        dist = torch.empty((n_rows, self.k), dtype=torch.float32)
+        info = RequestInfo()
+        _check(load().knng_server_wait(self._h, ticket, int(timeout_us),
+                                       ctypes.c_void_p(ids.data_ptr()),
+                                       ctypes.c_void_p(dist.data_ptr()), ctypes.byref(info)))
+        return ids, dist, info.to_dict()
+
+    def snapshot(self):
+        """The resident graph as device tensors (ids, dist)."""
+        n = ctypes.c_int64()
+        _check(load().knng_server_snapshot(self._h, None, ctypes.byref(n)))
+        ids, dist = _out(n.value, self.k, self.device)
+        g = _graph(ids, dist)
+        _check(load().knng_server_snapshot(self._h, ctypes.byref(g), ctypes.byref(n)))
+        return ids[:n.value], dist[:n.value]
+
+    def status(self):
+        r, p, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().knng_server_status(self._h, ctypes.byref(r), ctypes.byref(p),
+                                         ctypes.byref(b)))
+        return {"resident": r.value, "pending": p.value, "batches": b.value}
+
+    def close(self):
+        if self._h:
+            load().knng_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_bytes(capacity, max_batch, d, k, kin, metric="l2", **kw):
+    o = opts(**kw)
+    return load().knng_server_bytes(capacity, max_batch, d, k, kin, _metric(metric),
+                                    ctypes.byref(o))

@@ -189,6 +189,33 @@ def test_jmerge_tiny_raw_set(hip):
     assert_same_graph(gi, gd, oi, od, "jmerge tiny raw")
 
 
+@pytest.mark.parametrize("metric", ["l2", "cos", "l1"])
+def test_jmerge_balanced_identical_to_oracle(hip, metric):
+    # a raw set far smaller than the base: only hash-selected base rows are
+    # divided and appended to; rows that never see a NEW member are skipped
+    Sb, Sr = ragged_sets(1500, 70, 13, 114)
+    G = oracle.exact_graph(Sb, 10, metric)
+    (gi, gd, gst), (oi, od, ost) = _jmerge_both(hip, Sb, G, Sr, 10, metric, sample=7, seed=6,
+                                                balanced=True)
+    assert_same_graph(gi, gd, oi, od, f"jmerge balanced {metric}")
+    _same_stats(gst, ost)
+
+
+def test_jmerge_balanced_wide_input_delta_and_bf16(hip):
+    # input lists wider than k and without distances, a delta stop relative
+    # to the rows that start with NEW entries, and the BF16 screen
+    Sb, Sr = ragged_sets(900, 41, 20, 115)
+    G = oracle.exact_graph(Sb, 12)
+    G = (G[0][:, synth.rng(6).permutation(12)], None)
+    for kw in ({"delta": 0.02}, {"precision": "bf16"}, {"max_rounds": 1}):
+        okw = {a: b for a, b in kw.items() if a != "precision"}
+        oi, od, ost = oracle.jmerge(Sb, G, Sr, 9, "l2", sample=5, seed=8, balanced=True, **okw)
+        gi, gd, gst = hip.expand(dev(Sb), (dev(G[0]), None), dev(Sr), 9, "l2", sample=5, seed=8,
+                                 balanced=True, **kw)
+        assert_same_graph(host(gi), host(gd), oi, od, f"jmerge balanced {kw}")
+        _same_stats(gst, ost)
+
+
 # ---------------------------------------------------------------- behaviour
 
 def test_deterministic_repeat(hip):

@@ -410,3 +410,70 @@ def test_odd_k_and_keep_ratio():
         G2 = oracle.exact_graph(S2, k)
         ids, dist, _ = oracle.smerge(S1, G1, S2, G2, k, keep_ratio=r, sample=5, seed=1)
         _check_graph(ids, dist, np.concatenate([S1, S2]), "l2", k)
+
+
+def _selected_rows(seed, nb, nr):
+    # the balanced-append selection rule restated from its definition:
+    # floor(hi32(H(seed, 0xA3, i, 0, 0)) * nb / 2^32) < nr
+    return [i for i in range(nb)
+            if ((oracle.hash5(seed, 0xA3, i, 0, 0) >> 32) * nb) >> 32 < nr]
+
+
+def test_balanced_append_is_algorithm_2_when_raw_is_not_smaller():
+    S1, S2 = synth.gaussian_sets(150, 160, 5, workload=85)
+    G = oracle.exact_graph(S1, 8)
+    a = oracle.jmerge(S1, G, S2, 8, sample=6, seed=3)
+    b = oracle.jmerge(S1, G, S2, 8, sample=6, seed=3, balanced=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_balanced_append_selects_by_the_hash_rule():
+    # nr << nb: only the selected base rows are divided and receive
+    # min(k - k1, nr) appended samples; every raw row is initialised with k
+    # samples.  Round 0's evaluations then split into appends + init + joins.
+    S1, S2 = synth.gaussian_sets(600, 40, 5, workload=86)
+    nb, nr, k = 600, 40, 8
+    G = oracle.exact_graph(S1, k)
+    sel = _selected_rows(9, nb, nr)
+    assert 15 <= len(sel) <= 70        # binomial(600, 40/600): mean 40
+    ids, dist, st = oracle.jmerge(S1, G, S2, k, sample=6, seed=9, balanced=True, max_rounds=0)
+    assert st["evals"] == len(sel) * (k - k // 2) + nr * k
+    X = np.concatenate([S1, S2])
+    _check_graph(ids, dist, X, "l2", k)
+    # without rounds an unselected base row is its input list unchanged; a
+    # selected one is the top k of its input and its appended raw samples
+    unsel = np.setdiff1d(np.arange(nb), sel)
+    assert np.array_equal(ids[unsel], G[0][unsel]) and np.array_equal(dist[unsel], G[1][unsel])
+    changed = [i for i in sel if not np.array_equal(ids[i], G[0][i])]
+    assert all((ids[i] >= nb).any() for i in changed)
+    # with rounds: base rows only improve, base ids come from the input list
+    ids, dist, st = oracle.jmerge(S1, G, S2, k, sample=6, seed=9, balanced=True)
+    assert np.all(dist[:nb] <= G[1])
+    for i in range(nb):
+        row = ids[i]
+        assert set(row[row < nb].tolist()) <= set(G[0][i].tolist())
+    assert st["rounds"] >= 1
+
+
+def test_balanced_append_raw_rows_find_their_neighbours():
+    # a small request into a large base: the raw rows' lists come close to
+    # their exact lists over base u raw (hill climbing through the base graph)
+    recalls = []
+    for seed in range(4):
+        S1, S2 = synth.gaussian_sets(1500, 30, 4, workload=90 + seed)
+        G = oracle.exact_graph(S1, 10)
+        ids, _, _ = oracle.jmerge(S1, G, S2, 10, sample=10, seed=seed, balanced=True)
+        X = np.concatenate([S1, S2])
+        recalls.append(oracle.recall_at(ids, X, np.arange(1500, 1530), 10)[0])
+    assert np.mean(recalls) >= 0.9
+
+
+def test_delta_threshold_counts_rows_that_start_with_new_entries():
+    # delta is normalised by the rows holding a NEW entry when the loop
+    # starts: with balanced append that is the selected rows plus the raw rows
+    S1, S2 = synth.gaussian_sets(800, 50, 4, workload=87)
+    G = oracle.exact_graph(S1, 8)
+    n0 = len(_selected_rows(5, 800, 50)) + 50
+    _, _, st = oracle.jmerge(S1, G, S2, 8, sample=6, seed=5, balanced=True, delta=0.02)
+    assert st["c"][-1] <= 0.02 * n0 * 8
+    assert all(c > 0.02 * n0 * 8 for c in st["c"][:-1])
