@@ -77,7 +77,8 @@ namespace {
 // the device layout of a server; with base == nullptr it only measures
 void carve_server(Carve &c, knng_server &s, int s_sample)
 {
-    carve_merge(c, s.w, s.capacity, s.capacity, s.d, s.k, s.gstride, s_sample, s.metric, s.bf16);
+    carve_merge(c, s.w, s.capacity, s.capacity, s.d, s.k, s.gstride, s_sample, s.metric,
+                s.bf16);
     s.stage = c.take<float>((size_t)s.max_batch * s.d);
     s.sub_ctr = c.take<uint64_t>(C_WORDS);
 }
@@ -119,7 +120,8 @@ knng_status run_batch(knng_server *s, bool *ran)
             r.info.start_us = now_us(s->t0);
         }
         m = s->resident;
-        batch = s->batches++;
+        if (!tickets.empty())
+            batch = s->batches++;
     }
     *ran = !tickets.empty();
     if (tickets.empty())
