@@ -10,7 +10,13 @@ is points merged per second.  After the timed steps the script
     ground truth; the metric is quoted at recall@10 >= 0.95),
   - re-runs one merge with per-phase HIP-event timing to price the local-join
     kernel against the HBM roofline,
-  - times the CPU oracle on a bounded sample of the same workload.
+  - serving: a J-Merge server over a resident base of 2,000,000 rows of the
+    same mixture (exact k=20 graph) takes 1,000 requests of 1-20,000 rows
+    (log-uniform sizes) arriving as a Poisson stream at 0.7x the capacity
+    measured on a warm-up burst; p50/p99 of submit-to-result latency,
+  - merge tree: 8 blocks of 125,000 x d100 Gaussian-mixture rows with exact
+    k=16 l1 block graphs merged pairwise in 3 levels to 1,000,000 rows,
+  - times the CPU oracle on a bounded sample of the headline workload.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
@@ -33,29 +39,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def exact_kth_rows(X, rows, kk, device):
-    """FP64 distances of sampled rows to all rows and their exact kk-th
-    nearest distance (self excluded).  Integer rows: the GEMM form is exact."""
+def recall_at10(ids, X, rows, device, metric="l2"):
+    """Tie-tolerant recall@10 on sampled rows: a returned neighbour counts when
+    its FP64 distance is at most the exact 10th-nearest distance (self
+    excluded).  l2 on integer rows uses the GEMM form, which is exact there;
+    l1 is summed directly.  ids: host (n, k) array of the graph."""
     import torch
     Xd = torch.from_numpy(X).to(device=device, dtype=torch.float64)
-    sq = (Xd * Xd).sum(1)
-    out_kth = []
-    D_rows = []
-    for lo in range(0, len(rows), 250):
-        r = torch.from_numpy(rows[lo:lo + 250]).to(device)
-        D = sq[r, None] + sq[None, :] - 2.0 * (Xd[r] @ Xd.T)
+    sq = (Xd * Xd).sum(1) if metric == "l2" else None
+    hits = 0
+    for lo in range(0, len(rows), 100):
+        r = torch.from_numpy(rows[lo:lo + 100]).to(device)
+        if metric == "l2":
+            D = sq[r, None] + sq[None, :] - 2.0 * (Xd[r] @ Xd.T)
+        else:
+            D = torch.cdist(Xd[r], Xd, p=1.0)
         D[torch.arange(len(r), device=device), r] = float("inf")
-        out_kth.append(torch.topk(D, kk, dim=1, largest=False, sorted=True)[0][:, kk - 1])
-        D_rows.append(D)
-    return torch.cat(out_kth), torch.cat(D_rows)
-
-
-def recall_at10(ids, X, rows, device):
-    import torch
-    kth, D = exact_kth_rows(X, rows, 10, device)
-    got = torch.from_numpy(ids[rows, :10].astype(np.int64)).to(device)
-    dv = torch.gather(D, 1, got.clamp(min=0))
-    hits = ((dv <= kth[:, None]) & (got >= 0)).sum().item()
+        kth = torch.topk(D, 10, dim=1, largest=False, sorted=True)[0][:, 9]
+        got = torch.from_numpy(ids[rows[lo:lo + 100], :10].astype(np.int64)).to(device)
+        dv = torch.gather(D, 1, got.clamp(min=0))
+        hits += ((dv <= kth[:, None]) & (got >= 0)).sum().item()
+        del D
     return hits / (len(rows) * 10)
 
 
@@ -78,6 +82,127 @@ def join_roofline(st, n, d, k, s, prec="fp32"):
             "launches": launches,
             "algorithmic_bytes_per_launch": traffic / launches,
             "avg_launch_ms": st["ms"]["join"] / launches}
+
+
+def serve_bench(args, dev, precision):
+    """Serving workload: J-Merge server over a resident base, Poisson arrivals."""
+    import queue
+    import threading
+    import torch
+    import synth
+    from paper_1908_00814_amd import knng
+    k, nb = 20, args.serve_base
+    W, R = args.serve_warmup, args.serve_requests
+    t = time.perf_counter()
+    base = synth.byte_cluster_points(nb, workload=2, stream=51)
+    sizes = synth.request_sizes(W + R)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    req = synth.byte_cluster_points(int(offs[-1]), workload=2, stream=55)
+    log(f"[serve] base {nb:,} rows, {W}+{R} requests ({int(offs[-1]):,} rows) generated in "
+        f"{time.perf_counter() - t:.1f}s")
+    dB = torch.from_numpy(base).to(dev)
+    dR = torch.from_numpy(req).to(dev)
+    t = time.perf_counter()
+    gi, gd = knng.exact_graph(dB, k, "l2")
+    torch.cuda.synchronize()
+    log(f"[serve] exact k={k} base graph in {time.perf_counter() - t:.1f}s")
+    srv = knng.Server(dB, (gi, gd), k, "l2", capacity=nb + int(offs[-1]),
+                      max_batch=args.serve_max_batch, sample=args.sample, delta=args.delta,
+                      seed=args.seed + 5, precision=precision)
+    del gi, gd
+    try:
+        # warm-up burst: every request queued at once, the device saturated
+        tk = [srv.submit(dR[offs[i]:offs[i + 1]]) for i in range(W)]
+        inf = [srv.wait(tk[i], int(sizes[i]))[2] for i in range(W)]
+        span = (max(x["done_us"] for x in inf) - min(x["submit_us"] for x in inf)) / 1e6
+        cap = float(sizes[:W].sum()) / span
+        lam = 0.7 * cap / float(sizes[W:].mean())
+        log(f"[serve] warm-up: {int(sizes[:W].sum()):,} rows in {span * 1e3:.0f} ms over "
+            f"{len({x['batch'] for x in inf})} batches -> capacity {cap:,.0f} rows/s; "
+            f"offered {lam:.1f} requests/s")
+        gaps = synth.rng(5006).exponential(1.0 / lam, size=R)
+        arrive = np.cumsum(gaps)
+        q = queue.Queue()
+
+        def submitter():
+            t0 = time.perf_counter()
+            for j in range(R):
+                i = W + j
+                delay = arrive[j] - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+                q.put((i, srv.submit(dR[offs[i]:offs[i + 1]])))
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        infos = []
+        for j in range(R):
+            i, ticket = q.get()
+            infos.append(srv.wait(ticket, int(sizes[i]))[2])
+            if (j + 1) % 250 == 0:
+                log(f"[serve] {j + 1}/{R} requests done")
+        th.join()
+        lat = np.array([x["done_us"] - x["submit_us"] for x in infos]) / 1e3
+        wall = (max(x["done_us"] for x in infos) - min(x["submit_us"] for x in infos)) / 1e6
+        rows_meas = float(sizes[W:].sum())
+        batches = sorted({x["batch"] for x in infos})
+        si, _ = srv.snapshot()
+        ids = si.cpu().numpy()
+    finally:
+        srv.close()
+    X = np.concatenate([base, req])
+    sample = synth.rng(5007).choice(np.arange(nb + offs[W], nb + offs[-1]), 1000, replace=False)
+    rec = recall_at10(ids, X, sample, dev)
+    out = {
+        "workload": (f"J-Merge server: resident base {nb:,} x d128 (same byte-valued "
+                     f"mixture, exact k=20 graph), {R} requests of 1-20,000 rows "
+                     f"(log-uniform) in Poisson arrivals at 0.7x measured capacity, "
+                     f"continuous batching (balanced append), {precision}"),
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+        "inserted_points_per_s": rows_meas / wall, "capacity_rows_per_s": cap,
+        "offered_requests_per_s": lam, "requests": R, "rows": int(rows_meas),
+        "batches": len(batches), "mean_batch_rows": rows_meas / max(len(batches), 1),
+        "recall@10_inserted": rec, "resident_rows_end": int(nb + offs[-1]),
+    }
+    log(f"[serve] p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "
+        f"{out['inserted_points_per_s']:,.0f} rows/s over {len(batches)} batches, "
+        f"recall@10 of inserted rows {rec:.4f}")
+    return out
+
+
+def tree_bench(args, dev):
+    """Merge tree: 8 blocks, exact l1 block graphs, 3 levels of S-Merge."""
+    import torch
+    import synth
+    from paper_1908_00814_amd import knng
+    k = 16
+    blocks = synth.gmm_blocks()
+    starts = np.concatenate([[0], np.cumsum([len(b) for b in blocks])]).astype(np.int64)
+    X = np.concatenate(blocks)
+    dX = torch.from_numpy(X).to(dev)
+    t = time.perf_counter()
+    graphs = [knng.exact_graph(dX[starts[b]:starts[b + 1]], k, "l1") for b in range(len(blocks))]
+    torch.cuda.synchronize()
+    t_blocks = time.perf_counter() - t
+    kw = dict(sample=args.sample, delta=args.delta, seed=args.seed + 4)
+    knng.merge_tree(dX, starts, graphs, k, "l1", **kw)   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ids, _, st = knng.merge_tree(dX, starts, graphs, k, "l1", **kw)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t
+    rows = synth.rng(4007).choice(len(X), 1000, replace=False)
+    rec = recall_at10(ids.cpu().numpy(), X, rows, dev, metric="l1")
+    out = {"workload": "merge tree: 8 x 125,000 x d100 Gaussian mixture (50 components), "
+                       "exact k=16 l1 block graphs, pairwise S-Merge in 3 levels",
+           "points_per_s": len(X) / secs, "seconds": secs, "level_ms": st["level_ms"],
+           "level_rounds": st["level_rounds"], "recall@10": rec,
+           "block_graphs_s": t_blocks,
+           "scanning_rate": st["evals"] / (len(X) * (len(X) - 1) / 2.0)}
+    log(f"[tree] 1,000,000 rows in {secs * 1e3:.0f} ms (levels {st['level_ms']} ms), "
+        f"recall@10 {rec:.4f}; block graphs {t_blocks:.1f}s")
+    return out
 
 
 def cpu_baseline(n_per, k, s, delta, seed):
@@ -116,6 +241,12 @@ def main():
                     help="time one path only (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (scales PMC byte counters)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-base", type=int, default=2_000_000)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-max-batch", type=int, default=262_144)
+    ap.add_argument("--no-tree", action="store_true", help="skip the merge-tree workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -221,6 +352,16 @@ def main():
                            if len(paths) == 2 else None),
         "paths_identical": same,
     }
+    del dS1, dS2, dG1, dG2, ws, out
+    torch.cuda.empty_cache()
+    if not args.no_tree:
+        line["tree"] = tree_bench(args, dev)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        line["serving"] = serve_bench(args, dev, best)
+        line["p50_insert_latency_ms"] = line["serving"]["p50_ms"]
+        line["p99_insert_latency_ms"] = line["serving"]["p99_ms"]
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log(f"[bench] timing the CPU oracle on 2 x {args.cpu_n} points ...")
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, k, args.sample, args.delta, args.seed)

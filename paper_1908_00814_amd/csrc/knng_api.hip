@@ -5,6 +5,8 @@
 // k-NN Graph", Sections 3.1-3.2): Divide/Append (or Initialize), then the
 // repeat loop -- per round: sampling, Reverse(G), local join -- until the
 // number of surviving insertions c drops to delta*n*k, then Merge and Sort.
+#include <chrono>
+
 #include "knng_host.h"
 
 using namespace knng;
@@ -413,6 +415,7 @@ extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
     int level = 0;
     while (segs.size() > 1) {
         const bool last = segs.size() == 2;
+        const auto t_level = std::chrono::steady_clock::now();
         int32_t *li = last ? out->ids : ids[level & 1];
         float *ld = last ? out->dist : dist[level & 1];
         std::vector<Seg> nxt;
@@ -462,6 +465,11 @@ extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
                                      hipMemcpyDeviceToDevice, st));
             nxt.push_back({r.a, r.c, li + r.a * k, ld + r.a * k, k});
         }
+        HIP_TRY(hipStreamSynchronize(st));
+        if (level < KNNG_STATS_ROUNDS)
+            total.gathered[level] = (int64_t)std::chrono::duration<double, std::micro>(
+                                        std::chrono::steady_clock::now() - t_level)
+                                        .count();
         segs.swap(nxt);
         level++;
     }

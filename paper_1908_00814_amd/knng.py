@@ -321,6 +321,7 @@ def merge_tree(X, starts, graphs, k, metric="l2", stream=None, workspace=None, *
     levels = [lvl for lvl in range(STATS_ROUNDS) if st.pairs[lvl]]
     d["level_evals"] = [st.updates[lvl] for lvl in levels]
     d["level_rounds"] = [st.pairs[lvl] for lvl in levels]
+    d["level_ms"] = [st.gathered[lvl] / 1e3 for lvl in levels]
     return ids, dist, d
 
 
