@@ -94,6 +94,7 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     a.rold = w.rold;
     a.dtag = w.dtag;
     a.atag = w.atag;
+    a.rfill = w.rfill;
     a.ctr = w.ctr;
     a.n = n;
     a.n1 = n1;

@@ -66,7 +66,7 @@ struct Layout {
     float *x, *norm, *sq, *eb;
     uint16_t *xb;
     uint64_t *gin, *L, *worst, *rnew, *rold;
-    int32_t *new_f, *old_f, *cnt_f, *dtag, *atag;
+    int32_t *new_f, *old_f, *cnt_f, *dtag, *atag, *rfill;
     int dp, db, gstride;
 };
 
@@ -98,6 +98,7 @@ inline void carve_merge(Carve &c, Layout &w, int64_t n, int64_t n_list, int d, i
     w.rold = c.take<uint64_t>((size_t)n * s);
     w.dtag = c.take<int32_t>((size_t)n);
     w.atag = c.take<int32_t>((size_t)n);
+    w.rfill = c.take<int32_t>((size_t)n * 2);
 }
 
 inline bool is_device_ptr(const void *p)

@@ -29,6 +29,7 @@ struct RoundArgs {
     int32_t *cnt_f;     // n x 2: (#new_f, #old_f)
     uint64_t *rnew;     // n x s reverse NEW reservoirs
     uint64_t *rold;     // n x s reverse OLD reservoirs
+    int32_t *rfill;     // n x 2 offers made to each reservoir (NEW, OLD) this round
     // Row tags (rounds are numbered from 0; -1 = never):
     //   dtag[u] = t: u holds NEW entries to sample in round t (set by Divide/
     //            Append/Initialize for t = 0, by an insert during round t-1,

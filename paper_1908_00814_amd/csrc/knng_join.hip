@@ -51,8 +51,8 @@ namespace {
 
 constexpr int JOIN_WAVES = 4;
 constexpr int CH = 16;                  // coordinates per staged chunk
-constexpr int OLD_CAP = MAX_K + MAX_S;  // OLD candidates per neighbourhood
-constexpr int QCAP = 256;               // insert-queue entries per wave
+constexpr int QCAP = 256;               // BF16 path: rescore-queue words per wave
+constexpr int QF = 192;                 // FP32 path: insert-queue entries per wave
 constexpr int TMAX = 4;                 // MFMA tiles held per batch
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -70,24 +70,25 @@ struct Regions {
 struct WaveLds {
     float *vecT;     // CH x GS staged coordinates, transposed
     uint64_t *gw;    // GS worst bound of each member's list
-    uint64_t *q64;   // QCAP queue words
+    uint64_t *q64;   // QCAP queue words (FP32 path: the QF queued keys)
     int32_t *grp;    // GS member ids (-1 = padding)
     float *gnorm;    // GS canonical norms (cosine)
     float *gsq;      // GS squared norms of bf16 rows (BF16 path)
     float *gerr;     // GS bf16 rounding-error norms (BF16 path)
-    int32_t *tnew;   // 2 MAX_S NEW members, first set then second
-    int32_t *told;   // OLD_CAP raw OLD candidates
-    int32_t *toldA;  // OLD_CAP accepted OLD members of the first set
-    int32_t *toldB;  // OLD_CAP accepted OLD members of the second set
+    int32_t *tnew;   // 2 s NEW members, first set then second
+    int32_t *told;   // k + s raw OLD candidates
+    int32_t *toldA;  // k + s accepted OLD members of the first set
+    int32_t *toldB;  // k + s accepted OLD members of the second set
+    int32_t *qdst;   // FP32 path: target rows of the QF queued keys
 };
 
-__host__ __device__ inline int wave_lds_bytes(int GS)
+__host__ __device__ inline int wave_lds_bytes(int GS, int s, int k)
 {
-    int b = CH * GS * 4 + GS * 8 + QCAP * 8 + 4 * GS * 4 + (2 * MAX_S + 3 * OLD_CAP) * 4;
+    int b = CH * GS * 4 + GS * 8 + QCAP * 8 + 4 * GS * 4 + (2 * s + 3 * (k + s) + QF) * 4;
     return (b + 15) / 16 * 16;
 }
 
-__device__ inline WaveLds carve_lds(unsigned char *base, int GS)
+__device__ inline WaveLds carve_lds(unsigned char *base, int GS, int s, int k)
 {
     WaveLds L;
     L.vecT = reinterpret_cast<float *>(base);
@@ -98,9 +99,10 @@ __device__ inline WaveLds carve_lds(unsigned char *base, int GS)
     L.gsq = L.gnorm + GS;
     L.gerr = L.gsq + GS;
     L.tnew = reinterpret_cast<int32_t *>(L.gerr + GS);
-    L.told = L.tnew + 2 * MAX_S;
-    L.toldA = L.told + OLD_CAP;
-    L.toldB = L.toldA + OLD_CAP;
+    L.told = L.tnew + 2 * s;
+    L.toldA = L.told + (k + s);
+    L.toldB = L.toldA + (k + s);
+    L.qdst = L.toldB + (k + s);
     return L;
 }
 
@@ -331,9 +333,12 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join(Rows R, RoundArgs a,
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     const int lane = lane_id();
-    const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS);
+    const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS, a.s, a.k);
+    // the insert queue lives across tiles and rows: it is drained in whole
+    // 64-entry steps when it runs full, and once more at the end
     uint64_t *qkey = L.q64;
-    int32_t *qdst = L.told;  // the OLD candidate lists are consumed before the queue fills
+    int32_t *qdst = L.qdst;
+    int qn = 0;
     const uint64_t below = (1ull << lane) - 1ull;
     uint64_t n_pairs = 0, n_gather = 0, n_attempt = 0;
     int maxg = 0;
@@ -388,7 +393,6 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join(Rows R, RoundArgs a,
             }
             // screen; survivors go through the wave's insert queue, drained by
             // all lanes together (UpdateNN in both directions)
-            int qn = 0;
 #pragma unroll
             for (int x = 0; x < 2; x++) {
                 const int r = tr0 + x;
@@ -422,20 +426,21 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join(Rows R, RoundArgs a,
                         qdst[pos] = q;
                     }
                     qn += __popcll(mq);
-                    if (qn > QCAP - 2 * WAVE) {
+                    if (qn > QF - 2 * WAVE) {
+                        // drain the top whole steps, keep the rest (< 64)
+                        const int keep = qn & (WAVE - 1);
                         __builtin_amdgcn_wave_barrier();
-                        n_attempt += drain_keys<KB>(qkey, qdst, qn, a);
-                        qn = 0;
+                        n_attempt += drain_keys<KB>(qkey + keep, qdst + keep, qn - keep, a);
+                        qn = keep;
                         __builtin_amdgcn_wave_barrier();
                     }
                 }
             }
-            __builtin_amdgcn_wave_barrier();
-            n_attempt += drain_keys<KB>(qkey, qdst, qn, a);
-            __builtin_amdgcn_wave_barrier();
         }
         }
     }
+    __builtin_amdgcn_wave_barrier();
+    n_attempt += drain_keys<KB>(qkey, qdst, qn, a);
     flush_counters(a, n_pairs, n_gather, n_attempt, 0, 0, maxg);
 }
 
@@ -512,7 +517,7 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     const int lane = lane_id();
-    const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS);
+    const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS, a.s, a.k);
     // queue word: slot r | slot c << 8 | (p gets q) << 16 | (q gets p) << 17 in
     // the low half, the screening distance's bits in the high half
     uint64_t *qw = L.q64;
@@ -684,7 +689,7 @@ hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, 
     // the BF16 tiles read 16 slots past a region start (+16); +4 spreads banks
     const int g_max = 3 * a.s + a.k;
     const int GS = r4(g_max) + 12 + 16 + 4;
-    const int wave_bytes = wave_lds_bytes(GS);
+    const int wave_bytes = wave_lds_bytes(GS, a.s, a.k);
     const size_t shmem = (size_t)wave_bytes * JOIN_WAVES;
     const int units = GS * (CH / 4);
     if (units > 12 * WAVE)

@@ -48,10 +48,12 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
             uint64_t h = hash5(a.seed, TAG_FWD, (uint64_t)a.round, (uint64_t)u, (uint64_t)id);
             pk = ((h >> 32) << 32) | id;
         }
+        // rank among the NEW entries (ties, which a well-formed list never
+        // has, go by slot so that the sample slots stay a permutation)
         int rank = 0, nnew = 0;
         for (int j = 0; j < a.k; j++) {
             uint64_t o = __shfl(pk, j, WAVE);
-            rank += o < pk;
+            rank += o < pk || (o == pk && j < lane);
             nnew += o != ~0ull;
         }
         const bool sampled = isnew && rank < a.s;
@@ -96,6 +98,8 @@ __global__ __launch_bounds__(256) void k_prep_active(RoundArgs a)
             a.rnew[u * a.s + lane] = empty_key(lane);
             a.rold[u * a.s + lane] = empty_key(lane);
         }
+        if (lane < 2)
+            a.rfill[2 * u + lane] = 0;
         if (a.dtag[u] < a.round) {
             const uint64_t v = lane < a.k ? a.L[u * a.k + lane] : ~0ull;
             const bool has = lane < a.k && !key_empty(v);
@@ -128,12 +132,14 @@ __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
         int32_t v;
         uint32_t tag;
         uint64_t *res;
+        int kind;
         if (j < a.s) {
             if (!sampled || j >= a.cnt_f[2 * u])
                 continue;
             v = a.new_f[u * a.s + j];
             tag = TAG_RNEW;
             res = a.rnew;
+            kind = 0;
         } else {
             j -= a.s;
             if (sampled) {
@@ -150,10 +156,18 @@ __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
                 continue;
             tag = TAG_ROLD;
             res = a.rold;
+            kind = 1;
         }
         uint64_t h = hash5(a.seed, tag, (uint64_t)a.round, (uint64_t)v, (uint64_t)u);
         uint64_t key = ((h >> 32) << 32) | (uint64_t)u;
-        bounded_insert<MAX_S>(res + (int64_t)v * a.s, a.s, key, false, nullptr, a.ctr + C_ERR);
+        uint64_t *slots = res + (int64_t)v * a.s;
+        // the first s offers take a slot of their own (every slot change is a
+        // compare-and-swap to a smaller word, as in bounded_insert, so a slot
+        // that a competing insert has taken sends this offer the long way)
+        const int pos = atomicAdd(a.rfill + 2 * (int64_t)v + kind, 1);
+        if (pos < a.s && cas64(slots + pos, empty_key(pos), key))
+            continue;
+        bounded_insert<MAX_S>(slots, a.s, key, false, nullptr, a.ctr + C_ERR);
     }
 }
 
