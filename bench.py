@@ -63,6 +63,28 @@ def recall_at10(ids, X, rows, device, metric="l2"):
     return hits / (len(rows) * 10)
 
 
+JOIN_SOURCES = ["paper_1908_00814_amd/csrc/knng_join.hip", "paper_1908_00814_amd/csrc/knng_common.h",
+                "paper_1908_00814_amd/csrc/knng_internal.h"]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per join launch from the committed PMC record (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy of known size), or None when there is no
+    record for this kernel or its sources changed after the counters were
+    taken."""
+    import hashlib
+    p = os.path.join(ROOT, "profiles", "k_join_traffic.json")
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p))
+    h = hashlib.sha256()
+    for f in JOIN_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec.get("kernel") != kernel or rec.get("sources_sha256") != h.hexdigest():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def join_roofline(st, n, d, k, s, prec="fp32"):
     """Algorithmic bytes of the local-join launches of one merge and the
     achieved rate over their summed duration."""
@@ -76,9 +98,10 @@ def join_roofline(st, n, d, k, s, prec="fp32"):
     launches = max(st["join_launches"], 1)
     secs = st["ms"]["join"] / 1e3
     achieved = traffic / secs if secs > 0 else 0.0
+    kernel = "k_join<0, 32, 8>" if prec == "fp32" else "k_join_bf16<0, 32>"
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK, "traffic": None,
-            "kernel": "k_join<M_L2>" if prec == "fp32" else "k_join_bf16<M_L2>",
+            "frac": achieved / HBM_PEAK, "traffic": measured_traffic(kernel),
+            "kernel": kernel,
             "launches": launches,
             "algorithmic_bytes_per_launch": traffic / launches,
             "avg_launch_ms": st["ms"]["join"] / launches}
@@ -205,17 +228,32 @@ def tree_bench(args, dev):
     return out
 
 
-def cpu_baseline(n_per, k, s, delta, seed):
+def cpu_baseline(n_per, k, s, delta, seed, dev, precision):
+    """The oracle timed on a bounded sample of the headline workload; the GPU
+    merges the same sample and the two graphs are compared."""
+    import torch
     import oracle
     import synth
     from synth.graphs import approximate_graph
+    from paper_1908_00814_amd import knng
     S1, S2 = synth.byte_cluster_sets(n_per, n_per, workload=2)
     G1 = approximate_graph(S1, k, 0.9, device="cpu", stream=6)
     G2 = approximate_graph(S2, k, 0.9, device="cpu", stream=7)
     t0 = time.perf_counter()
-    oracle.smerge(S1, G1, S2, G2, k, "l2", sample=s, delta=delta, seed=seed)
+    oi, od, _ = oracle.smerge(S1, G1, S2, G2, k, "l2", sample=s, delta=delta, seed=seed)
     dt = time.perf_counter() - t0
+    d = lambda a: torch.from_numpy(a).to(dev)
+    gi, gd, _ = knng.merge(d(S1), (d(G1[0]), d(G1[1])), d(S2), (d(G2[0]), d(G2[1])), k, "l2",
+                           sample=s, delta=delta, seed=seed, precision=precision)
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    X = np.concatenate([S1, S2])
+    rows = synth.rng(2009).choice(len(X), 300, replace=False)
+    parity = {"identical": bool(np.array_equal(gi, oi) and
+                                np.array_equal(gd.view(np.uint32), od.view(np.uint32))),
+              "recall@10_oracle": oracle.recall_at(oi, X, rows, 10)[0],
+              "recall@10_gpu": oracle.recall_at(gi, X, rows, 10)[0], "rows": 300}
     return {"value": 2 * n_per / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "parity_with_gpu": parity,
             "sample": (f"S-Merge of 2 x {n_per:,} points drawn from the same byte-valued "
                        f"cluster law (d=128, k=20, s={s}, delta={delta}), approximate "
                        f"input graphs built the same way; single-threaded C oracle, "
@@ -364,8 +402,10 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log(f"[bench] timing the CPU oracle on 2 x {args.cpu_n} points ...")
-        line["cpu_baseline"] = cpu_baseline(args.cpu_n, k, args.sample, args.delta, args.seed)
-        log(f"[bench] oracle: {line['cpu_baseline']['value']:.0f} points/s")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_n, k, args.sample, args.delta, args.seed,
+                                            dev, best)
+        log(f"[bench] oracle: {line['cpu_baseline']['value']:.0f} points/s; GPU graph on the "
+            f"same sample identical: {line['cpu_baseline']['parity_with_gpu']['identical']}")
     print(json.dumps(line), flush=True)
 
 
