@@ -13,7 +13,8 @@ is points merged per second.  After the timed steps the script
   - serving: a J-Merge server over a resident base of 2,000,000 rows of the
     same mixture (exact k=20 graph) takes 1,000 requests of 1-20,000 rows
     (log-uniform sizes) arriving as a Poisson stream at 0.7x the capacity
-    measured on a warm-up burst; p50/p99 of submit-to-result latency,
+    measured on a warm-up burst, several requests on the device at once;
+    p50/p99 of submit-to-result latency,
   - merge tree: 8 blocks of 125,000 x d100 Gaussian-mixture rows with exact
     k=16 l1 block graphs merged pairwise in 3 levels to 1,000,000 rows,
   - times the CPU oracle on a bounded sample of the headline workload.
@@ -129,20 +130,20 @@ def serve_bench(args, dev, precision):
     gi, gd = knng.exact_graph(dB, k, "l2")
     torch.cuda.synchronize()
     log(f"[serve] exact k={k} base graph in {time.perf_counter() - t:.1f}s")
-    srv = knng.Server(dB, (gi, gd), k, "l2", capacity=nb + int(offs[-1]),
-                      max_batch=args.serve_max_batch, sample=args.sample, delta=args.delta,
-                      seed=args.seed + 5, precision=precision)
+    budget = args.serve_budget_gib << 30
+    srv = knng.Server(dB, (gi, gd), k, "l2", capacity=nb + int(offs[-1]), max_request=20_000,
+                      hbm_budget=budget, slots=args.serve_slots, sample=args.sample,
+                      delta=args.delta, seed=args.seed + 5, precision=precision)
     del gi, gd
     try:
-        # warm-up burst: every request queued at once, the device saturated
-        tk = [srv.submit(dR[offs[i]:offs[i + 1]]) for i in range(W)]
+        # warm-up burst: every request queued at once, all slots busy
+        tk = [srv.submit(dR[offs[i]:offs[i + 1]], i) for i in range(W)]
         inf = [srv.wait(tk[i], int(sizes[i]))[2] for i in range(W)]
         span = (max(x["done_us"] for x in inf) - min(x["submit_us"] for x in inf)) / 1e6
         cap = float(sizes[:W].sum()) / span
         lam = 0.7 * cap / float(sizes[W:].mean())
-        log(f"[serve] warm-up: {int(sizes[:W].sum()):,} rows in {span * 1e3:.0f} ms over "
-            f"{len({x['batch'] for x in inf})} batches -> capacity {cap:,.0f} rows/s; "
-            f"offered {lam:.1f} requests/s")
+        log(f"[serve] {srv.slots} slots; warm-up: {int(sizes[:W].sum()):,} rows in "
+            f"{span * 1e3:.0f} ms -> capacity {cap:,.0f} rows/s; offered {lam:.1f} requests/s")
         gaps = synth.rng(5006).exponential(1.0 / lam, size=R)
         arrive = np.cumsum(gaps)
         q = queue.Queue()
@@ -154,44 +155,73 @@ def serve_bench(args, dev, precision):
                 delay = arrive[j] - (time.perf_counter() - t0)
                 if delay > 0:
                     time.sleep(delay)
-                q.put((i, srv.submit(dR[offs[i]:offs[i + 1]])))
+                q.put((i, srv.submit(dR[offs[i]:offs[i + 1]], i)))
 
         th = threading.Thread(target=submitter)
         th.start()
-        infos = []
+        infos, results = [], {}
         for j in range(R):
             i, ticket = q.get()
-            infos.append(srv.wait(ticket, int(sizes[i]))[2])
+            ids, _, info = srv.wait(ticket, int(sizes[i]))
+            infos.append(info)
+            results[i] = ids.numpy()
             if (j + 1) % 250 == 0:
                 log(f"[serve] {j + 1}/{R} requests done")
         th.join()
         lat = np.array([x["done_us"] - x["submit_us"] for x in infos]) / 1e3
         wall = (max(x["done_us"] for x in infos) - min(x["submit_us"] for x in infos)) / 1e6
         rows_meas = float(sizes[W:].sum())
-        batches = sorted({x["batch"] for x in infos})
-        si, _ = srv.snapshot()
-        ids = si.cpu().numpy()
     finally:
         srv.close()
-    X = np.concatenate([base, req])
-    sample = synth.rng(5007).choice(np.arange(nb + offs[W], nb + offs[-1]), 1000, replace=False)
-    rec = recall_at10(ids, X, sample, dev)
+    rec = serve_recall(base, req, offs, sizes, results, W, dev)
     out = {
         "workload": (f"J-Merge server: resident base {nb:,} x d128 (same byte-valued "
                      f"mixture, exact k=20 graph), {R} requests of 1-20,000 rows "
-                     f"(log-uniform) in Poisson arrivals at 0.7x measured capacity, "
-                     f"continuous batching (balanced append), {precision}"),
+                     f"(log-uniform) in Poisson arrivals at 0.7x the capacity measured on a "
+                     f"warm-up burst; each request merged with the base on its own "
+                     f"(balanced append), {srv.slots} slots, {precision}"),
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
         "inserted_points_per_s": rows_meas / wall, "capacity_rows_per_s": cap,
         "offered_requests_per_s": lam, "requests": R, "rows": int(rows_meas),
-        "batches": len(batches), "mean_batch_rows": rows_meas / max(len(batches), 1),
+        "slots": srv.slots, "hbm_budget_bytes": budget,
         "recall@10_inserted": rec, "resident_rows_end": int(nb + offs[-1]),
     }
     log(f"[serve] p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "
-        f"{out['inserted_points_per_s']:,.0f} rows/s over {len(batches)} batches, "
-        f"recall@10 of inserted rows {rec:.4f}")
+        f"{out['inserted_points_per_s']:,.0f} rows/s, recall@10 of inserted rows "
+        f"(against base + own request) {rec:.4f}")
     return out
+
+
+def serve_recall(base, req, offs, sizes, results, W, dev, n_rows=1000):
+    """recall@10 of inserted rows against their exact neighbours among the
+    base and their own request's rows (the set their merge covers)."""
+    import torch
+    import synth
+    g = synth.rng(5007)
+    Xb = torch.from_numpy(base).to(device=dev, dtype=torch.float64)
+    sqb = (Xb * Xb).sum(1)
+    nb = base.shape[0]
+    picked = g.choice(np.arange(W, len(sizes)), 100, replace=False)
+    hits = total = 0
+    for i in picked:
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        Xr = torch.from_numpy(req[lo:hi]).to(device=dev, dtype=torch.float64)
+        rows = g.choice(hi - lo, min(10, hi - lo), replace=False)
+        q = Xr[rows]
+        Db = (q * q).sum(1)[:, None] + sqb[None, :] - 2.0 * (q @ Xb.T)
+        Dr = (q * q).sum(1)[:, None] + (Xr * Xr).sum(1)[None, :] - 2.0 * (q @ Xr.T)
+        Dr[torch.arange(len(rows), device=dev), torch.from_numpy(rows).to(dev)] = float("inf")
+        D = torch.cat([Db, Dr], 1)                      # columns: base rows, then own rows
+        kth = torch.topk(D, 10, dim=1, largest=False)[0][:, 9]
+        ids = results[i][rows, :10].astype(np.int64)
+        first = nb + lo
+        col = np.where(ids < nb, ids, nb + (ids - first))
+        ok = (ids >= 0) & ((ids < nb) | ((ids >= first) & (ids < first + (hi - lo))))
+        got = torch.gather(D, 1, torch.from_numpy(np.where(ok, col, 0)).to(dev))
+        hits += int(((got <= kth[:, None]) & torch.from_numpy(ok).to(dev)).sum().item())
+        total += 10 * len(rows)
+    return hits / total
 
 
 def tree_bench(args, dev):
@@ -283,7 +313,8 @@ def main():
     ap.add_argument("--serve-base", type=int, default=2_000_000)
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=50)
-    ap.add_argument("--serve-max-batch", type=int, default=262_144)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--no-tree", action="store_true", help="skip the merge-tree workload")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -250,62 +250,68 @@ size_t knng_exact_graph_workspace_size(int64_t n, int32_t d, int32_t k, knng_met
 /*
  * ---------------------------------------------------------------- serving
  * J-Merge as a service (Section 3.2: a built graph absorbs raw data without
- * a rebuild).  A server holds a resident set -- the base rows and every row
- * merged since -- with its k-NN graph in device memory it owns.  Requests of
- * raw rows are queued; whenever the device is free, all waiting requests
- * (in submission order, up to max_batch rows; a request is never split) form
- * one batch, and the batch is one knng_expand of the resident set and graph
- * with the batch's rows as the raw set, under KNNG_FLAG_BALANCED_APPEND, with
- * seed opts->seed + batch index.  Afterwards the resident set includes the
- * batch rows and the resident graph is that merge's output.
+ * a rebuild).  A server holds, in device memory it owns, a base -- rows and
+ * their k-NN lists, frozen between rebases -- and the resident graph: the
+ * base rows, every accepted request's rows, and their lists.
  *
- * Row ids: base rows 0..n_base-1, then the rows of each accepted request in
- * submission order (knng_request_info.first_id).  A request's result is its
- * rows' lists as they stood when its batch finished; later batches keep
- * improving the resident graph (knng_server_snapshot).
+ * A request of raw rows is one knng_expand of the base with the request's
+ * rows as the raw set, under KNNG_FLAG_BALANCED_APPEND, with seed
+ * SM(opts->seed ^ SM(req_id)) (SM = the SplitMix64 output function of
+ * state + 0x9E3779B97F4A7C15).  Its result therefore depends only on the
+ * base, its rows and req_id, never on other requests: the same request gives
+ * the same result alone and in any mix.  Row ids: base rows 0..m-1, then each
+ * accepted request's rows in submission order (knng_request_info.first_id).
  *
- * Given the same batches, results are deterministic; which requests share a
- * batch depends on timing unless the server is created with manual = 1,
- * where batches run only inside knng_server_step.
+ * When a request finishes, its rows' lists enter the resident graph and the
+ * new entries of base rows are offered to the resident lists with the
+ * set-form UpdateNN (top k of the union, ties by id), so the resident graph
+ * does not depend on the order in which requests finish.  Requests merge with
+ * the base only; knng_server_rebase makes the whole resident graph the base,
+ * so later requests also meet earlier requests' rows.
  *
- * Threads: submit, wait, step, snapshot and status may be called from any
- * threads concurrently; destroy must not overlap any other call on the same
- * server.  Work runs on the device that was current at creation, on streams
- * the server owns.
+ * Requests run in slots: each slot is a stream, a host thread and a merge
+ * workspace sized for the capacity.  Several requests are on the device at
+ * once; a queued request starts as soon as a slot frees up.  The number of
+ * slots is cfg->slots, lowered to what cfg->hbm_budget holds (slots = 0: no
+ * thread, requests run inside knng_server_step).
+ *
+ * Threads: submit, wait, step, snapshot, rebase and status may be called from
+ * any threads concurrently; destroy must not overlap any other call on the
+ * same server.  Work runs on the device that was current at creation.
  */
 typedef struct knng_server knng_server;
 
 typedef struct {
-    int64_t capacity;   /* rows the server can ever hold: base + every request row */
-    int64_t max_batch;  /* most raw rows merged in one batch (also the largest request) */
+    int64_t capacity;    /* rows the server can ever hold: base + every request row */
+    int64_t max_request; /* most rows in one request */
     uint64_t hbm_budget; /* device bytes the server may allocate; 0 = no limit */
-    int32_t manual;     /* 1: no worker thread; batches run in knng_server_step */
+    int32_t slots;       /* requests on the device at once; 0 = run in knng_server_step */
     int32_t reserved;
 } knng_server_config;
 
 typedef struct {
     int64_t first_id;   /* id of the request's first row */
-    int64_t batch;      /* index of the batch that merged it (-1: none) */
-    int64_t batch_rows; /* raw rows in that batch */
-    int64_t evals;      /* distance evaluations of that batch */
-    int32_t rounds;     /* rounds of that batch's repeat loop */
-    int32_t reserved;
+    int64_t rows;       /* rows of the request */
+    int64_t evals;      /* distance evaluations of its merge */
+    int32_t rounds;     /* rounds of its repeat loop */
+    int32_t slot;       /* slot that ran it (-1: none) */
     /* host steady clock, microseconds since the server was created */
     double submit_us;   /* knng_server_submit entered */
-    double start_us;    /* its batch started */
-    double done_us;     /* its batch finished (results on the host) */
+    double start_us;    /* its merge started */
+    double done_us;     /* its result is on the host and committed */
 } knng_request_info;
 
-/* Device bytes a server of this shape allocates (kin: columns of the base
- * graph). */
-size_t knng_server_bytes(int64_t capacity, int64_t max_batch, int32_t d, int32_t k, int32_t kin,
-                         knng_metric metric, const knng_opts *opts);
+/* Device bytes of a server of this shape with `slots` slots (kin: columns of
+ * the base graph). */
+size_t knng_server_bytes(int64_t capacity, int64_t max_request, int32_t d, int32_t k, int32_t kin,
+                         knng_metric metric, const knng_opts *opts, int32_t slots);
 
 /*
  * Copies base (n_base x d, device) and its graph G (as for knng_expand: local
- * ids, sorted with distances or dist NULL, G->k >= k1) into server memory,
- * allocated once with hipMalloc (KNNG_ENOMEM beyond cfg->hbm_budget).
- * Inputs are not kept.  *srv receives the server (NULL on error).
+ * ids, rows sorted with distances or dist NULL, G->k >= k1) into server
+ * memory, allocated once with hipMalloc.  KNNG_ENOMEM when cfg->hbm_budget
+ * holds no slot.  Inputs are not kept.  *srv receives the server (NULL on
+ * error).
  */
 knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_t k,
                                knng_metric metric, const knng_opts *opts,
@@ -313,16 +319,17 @@ knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_
 
 /*
  * Queues n_raw rows (n_raw x d fp32, host or device memory; read before
- * return, so the buffer may be reused at once).  Rows are validated
- * (KNNG_EINVAL: non-finite values, zero rows under cosine); KNNG_ENOMEM when
- * the capacity would be exceeded, KNNG_EINVAL when n_raw > max_batch.
- * *ticket identifies the request for knng_server_wait.
+ * return, so the buffer may be reused at once) under the caller's request id
+ * req_id (which seeds its merge).  Rows are validated (KNNG_EINVAL:
+ * non-finite values, zero rows under cosine; nothing is reserved then);
+ * KNNG_ENOMEM when the capacity would be exceeded, KNNG_EINVAL when
+ * n_raw > max_request.  *ticket identifies the request for knng_server_wait.
  */
-knng_status knng_server_submit(knng_server *srv, const float *raw, int64_t n_raw,
+knng_status knng_server_submit(knng_server *srv, const float *raw, int64_t n_raw, uint64_t req_id,
                                uint64_t *ticket);
 
-/* manual servers: runs one batch of the waiting requests (*ran = 0 when none
- * was waiting) */
+/* servers without slots: runs the oldest queued request (*ran = 0 when none
+ * was queued) */
 knng_status knng_server_step(knng_server *srv, int32_t *ran);
 
 /*
@@ -330,21 +337,29 @@ knng_status knng_server_step(knng_server *srv, int32_t *ran);
  * has not finished.  On success ids / dist (n_raw x k, host or device; either
  * may be NULL) receive its rows' lists with global ids, and the ticket is
  * released (a second wait gives KNNG_EINVAL).  info (may be NULL) is filled
- * also when the batch failed.
+ * also when the request failed.
  */
 knng_status knng_server_wait(knng_server *srv, uint64_t ticket, int64_t timeout_us,
                              int32_t *ids, float *dist, knng_request_info *info);
 
-/* The resident graph (waits for a running batch): *n_rows receives the row
- * count; out (device, out->n >= rows, out->k = k) receives the lists when
- * not NULL. */
+/* Waits until no request is queued or running, then writes the resident
+ * graph (rows sorted by (distance, id)) to out (device, out->n >= rows,
+ * out->k = k) when not NULL; *n_rows receives the row count.  KNNG_EBUSY on
+ * a server without slots while requests are queued. */
 knng_status knng_server_snapshot(knng_server *srv, knng_graph *out, int64_t *n_rows);
 
-/* rows merged, rows accepted but not merged yet, batches started */
-knng_status knng_server_status(knng_server *srv, int64_t *resident_rows, int64_t *pending_rows,
-                               int64_t *batches);
+/* Waits like knng_server_snapshot, then makes the resident graph the base. */
+knng_status knng_server_rebase(knng_server *srv);
 
-/* Finishes a running batch, then frees everything.  Requests still queued
+/* rows of the base, request rows committed since the last rebase, request
+ * rows accepted but not committed */
+knng_status knng_server_status(knng_server *srv, int64_t *base_rows, int64_t *committed_rows,
+                               int64_t *pending_rows);
+
+/* slots the server runs (after the budget) */
+int32_t knng_server_slots(const knng_server *srv);
+
+/* Lets the requests in slots finish, then frees everything; queued requests
  * are dropped. */
 void knng_server_destroy(knng_server *srv);
 

@@ -62,7 +62,7 @@ knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
 knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool bf16,
                       const knng_opts *o, int64_t n, int64_t n1, int k, int k1, int joint,
                       int64_t rows_with_rear, knng_graph *out, hipStream_t st, knng_stats *stats,
-                      Prof &prof, uint64_t *out_keys)
+                      Prof &prof, uint64_t *out_keys, bool touched_only)
 {
     const int balanced = joint && (o->flags & KNNG_FLAG_BALANCED_APPEND) ? 1 : 0;
     InitArgs ia;
@@ -156,6 +156,7 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     fa.out_ids = out ? out->ids : nullptr;
     fa.out_dist = out ? out->dist : nullptr;
     fa.out_keys = out_keys;
+    fa.touched = touched_only ? w.dtag : nullptr;
     HIP_TRY(launch_final(fa, st));
     prof.end();
     knng_status s = read_ctr(w.ctr, h, st);

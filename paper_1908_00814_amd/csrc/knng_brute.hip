@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_brute(Rows R, int64_t a_lo, int64_t a_h
 #pragma unroll
     for (int i = 0; i < 4; i++) {
         int64_t a = a0 + 4 * ty + i;
-        na[i] = (METRIC == M_COS && a < a_hi) ? R.norm[a] : 0.0f;
+        na[i] = (METRIC == M_COS && a < a_hi) ? R.norm[R.phys(a)] : 0.0f;
     }
     for (int64_t b0 = b_lo; b0 < b_hi; b0 += TN) {
         float acc[4][4];
@@ -80,9 +80,9 @@ __global__ __launch_bounds__(256) void k_brute(Rows R, int64_t a_lo, int64_t a_h
                 int64_t a = a0 + r, b = b0 + r;
                 float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
                 if (a < a_hi)
-                    va = *reinterpret_cast<const float4 *>(R.x + a * R.dp + t0 + 4 * q);
+                    va = *reinterpret_cast<const float4 *>(R.x + R.phys(a) * R.dp + t0 + 4 * q);
                 if (b < b_hi)
-                    vb = *reinterpret_cast<const float4 *>(R.x + b * R.dp + t0 + 4 * q);
+                    vb = *reinterpret_cast<const float4 *>(R.x + R.phys(b) * R.dp + t0 + 4 * q);
                 As[4 * q + 0][r] = va.x;
                 As[4 * q + 1][r] = va.y;
                 As[4 * q + 2][r] = va.z;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_brute(Rows R, int64_t a_lo, int64_t a_h
                 const int64_t b = b0 + 4 * tx + j;
                 if (a >= a_hi || b >= b_hi || (exclude_self && a == b))
                     continue;
-                float nbv = METRIC == M_COS ? R.norm[b] : 0.0f;
+                float nbv = METRIC == M_COS ? R.norm[R.phys(b)] : 0.0f;
                 float dv = canon_finish<METRIC>(acc[i][j], na[i], nbv);
                 uint64_t key = make_key(dv, (uint32_t)(b - id_base), 0);
                 if (key < thr[r]) {

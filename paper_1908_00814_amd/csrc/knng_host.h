@@ -285,7 +285,7 @@ knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
 knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool bf16,
                       const knng_opts *o, int64_t n, int64_t n1, int k, int k1, int joint,
                       int64_t rows_with_rear, knng_graph *out, hipStream_t st, knng_stats *stats,
-                      Prof &prof, uint64_t *out_keys = nullptr);
+                      Prof &prof, uint64_t *out_keys = nullptr, bool touched_only = false);
 
 inline int keep_count(const knng_opts *o, int k) { return (int)floorf(o->keep_ratio * (float)k); }
 

@@ -9,14 +9,19 @@ namespace knng {
 
 // Device view of the rows of a merge: the two input sets concatenated into one
 // padded fp32 array (rows of the first set first), plus per-row canonical norms.
+// Row i of the merge is stored at row phys(i) of the arrays: rows below
+// `split` in place, the others `off2` rows further on (a server keeps each
+// request's rows apart from the base rows they are merged with).
 struct Rows {
-    const float *x;  // n x dp fp32, zero-padded
-    const float *norm;  // n canonical norms (cosine) or nullptr
-    const uint16_t *xb; // BF16 path: n x db bf16 copy (round to nearest even), or nullptr
+    const float *x;  // rows x dp fp32, zero-padded
+    const float *norm;  // canonical norms (cosine) or nullptr
+    const uint16_t *xb; // BF16 path: bf16 copy (round to nearest even, stride db), or nullptr
     const float *sq;    // BF16 path: squared norms of the bf16-rounded rows, or nullptr
     const float *eb;    // BF16 path: upper bounds of |x - bf16(x)| per row, or nullptr
     int64_t n;
     int d, dp, db;  // db: bf16 row stride, d rounded up to 32
+    int64_t split = INT64_MAX, off2 = 0;
+    __host__ __device__ int64_t phys(int64_t i) const { return i < split ? i : i + off2; }
 };
 
 // Parameters of one iteration of the merge loop.
@@ -90,11 +95,32 @@ struct FinalArgs {
     int32_t *out_ids;    // n x k, or nullptr
     float *out_dist;     // n x k, or nullptr
     uint64_t *out_keys;  // n x kin sorted keys (may be gin itself), or nullptr
+    const int32_t *touched;  // when set, rows below rows_with_rear with touched[i] < 0
+                             // (never held a NEW entry) are left out
 };
 hipError_t launch_final(const FinalArgs &a, hipStream_t st);
-// sorted keys (stride kin) -> ids / distances (n x k); empty slots give -1 / +inf
-hipError_t launch_keys_to_graph(const uint64_t *keys, int kin, int64_t n, int k,
-                                int32_t *ids, float *dist, hipStream_t st);
+
+// ---- serving (knng_prep.hip)
+// Folds one request's merge into the resident graph: for base rows that held
+// a NEW entry, its entries of request rows (local ids >= m_base, renumbered
+// to first + id - m_base) are offered to the resident list (UpdateNN, set
+// form, so commits of different requests commute); the request's own rows
+// are copied, renumbered, to resident rows first .. first + n_req - 1.
+struct CommitArgs {
+    const uint64_t *out;     // (m_base + n_req) x gs final keys of the request
+    int gs, k;
+    const int32_t *touched;  // dtag of the request's merge
+    int64_t m_base, n_req, first;
+    uint64_t *res;           // resident lists, k per row
+    uint64_t *ctr;
+};
+hipError_t launch_commit(const CommitArgs &a, hipStream_t st);
+// rows of keys (stride src_stride, k used) sorted by (distance, id), empty
+// slots last; written as keys (dst, stride dst_stride, padded with empty
+// slots) and/or as ids / distances (n x k, -1 / +inf for empty slots)
+hipError_t launch_sort_rows(const uint64_t *src, int src_stride, int64_t n, int k,
+                            uint64_t *dst, int dst_stride, int32_t *ids, float *dist,
+                            hipStream_t st);
 hipError_t launch_zero_counters(uint64_t *ctr, int words, hipStream_t st);
 
 // ---- knng_round.hip

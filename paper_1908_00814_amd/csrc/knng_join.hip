@@ -195,10 +195,10 @@ __device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a,
         L.grp[slot] = id;
         L.gw[slot] = id >= 0 ? a.worst[id] : 0ull;
         if (METRIC == M_COS)
-            L.gnorm[slot] = id >= 0 ? R.norm[id] : 1.0f;
+            L.gnorm[slot] = id >= 0 ? R.norm[R.phys(id)] : 1.0f;
         if (BF) {
-            L.gsq[slot] = id >= 0 ? R.sq[id] : 0.0f;
-            L.gerr[slot] = id >= 0 ? R.eb[id] : 0.0f;
+            L.gsq[slot] = id >= 0 ? R.sq[R.phys(id)] : 0.0f;
+            L.gerr[slot] = id >= 0 ? R.eb[R.phys(id)] : 0.0f;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -222,7 +222,7 @@ __device__ inline void stage_chunk(const Rows &R, const WaveLds &L, int GP, int 
             const int m = e / q4, q = e - m * q4;
             const int32_t id = L.grp[m];
             if (id >= 0 && c0 + 4 * q < R.dp)
-                pre[j] = *reinterpret_cast<const float4 *>(R.x + (int64_t)id * R.dp + c0 + 4 * q);
+                pre[j] = *reinterpret_cast<const float4 *>(R.x + R.phys(id) * R.dp + c0 + 4 * q);
         }
     }
 #pragma unroll
@@ -564,9 +564,9 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
                 const int32_t ir = rs < g.GP ? L.grp[rs] : -1;
                 const int32_t ic = cs < g.GP ? L.grp[cs] : -1;
                 const bf16x8 *pa =
-                    reinterpret_cast<const bf16x8 *>(R.xb + (int64_t)(ir < 0 ? 0 : ir) * R.db + koff);
+                    reinterpret_cast<const bf16x8 *>(R.xb + R.phys(ir < 0 ? 0 : ir) * R.db + koff);
                 const bf16x8 *pb =
-                    reinterpret_cast<const bf16x8 *>(R.xb + (int64_t)(ic < 0 ? 0 : ic) * R.db + koff);
+                    reinterpret_cast<const bf16x8 *>(R.xb + R.phys(ic < 0 ? 0 : ic) * R.db + koff);
                 const bf16x8 zero = {};
 #pragma unroll 4
                 for (int ks = 0; ks < ksteps; ks++) {
@@ -647,8 +647,8 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
                         const float db = __uint_as_float((uint32_t)(w >> 32));
                         float D = db;
                         if (!(signbit(L.gerr[sr]) && signbit(L.gerr[sc]))) {
-                            D = canon_dist<M_L2>(R.x + (int64_t)pp * R.dp,
-                                                 R.x + (int64_t)qq * R.dp, R.dp, 0.0f, 0.0f);
+                            D = canon_dist<M_L2>(R.x + R.phys(pp) * R.dp,
+                                                 R.x + R.phys(qq) * R.dp, R.dp, 0.0f, 0.0f);
                             n_rescore++;
                             // the margin also bounds |d~ - d| at d itself
                             const float sp = L.gsq[sr], sq2 = L.gsq[sc];

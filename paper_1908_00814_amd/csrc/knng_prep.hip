@@ -134,8 +134,9 @@ __global__ __launch_bounds__(256) void k_prep_input(Rows R, int64_t row0, int64_
                 if (!(dv >= 0.0f) || isinf(dv))
                     err |= ERR_BAD_DIST;
             } else {
-                const float *a = R.x + r * R.dp, *b = R.x + g * R.dp;
-                float na = R.norm ? R.norm[r] : 0.0f, nb = R.norm ? R.norm[g] : 0.0f;
+                const float *a = R.x + R.phys(r) * R.dp, *b = R.x + R.phys(g) * R.dp;
+                float na = R.norm ? R.norm[R.phys(r)] : 0.0f;
+                float nb = R.norm ? R.norm[R.phys(g)] : 0.0f;
                 dv = canon_dist<METRIC>(a, b, R.dp, na, nb);
             }
         }
@@ -269,8 +270,9 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
             key = key_empty(key) ? empty_key(lane) : key_strip(key);
         } else if (lane < first + m) {
             int64_t g = picked[lane - first] + cand_off;
-            float na = R.norm ? R.norm[i] : 0.0f, nb = R.norm ? R.norm[g] : 0.0f;
-            float dv = canon_dist<METRIC>(R.x + i * R.dp, R.x + g * R.dp, R.dp, na, nb);
+            float na = R.norm ? R.norm[R.phys(i)] : 0.0f, nb = R.norm ? R.norm[R.phys(g)] : 0.0f;
+            float dv = canon_dist<METRIC>(R.x + R.phys(i) * R.dp, R.x + R.phys(g) * R.dp, R.dp,
+                                          na, nb);
             key = make_key(dv, (uint32_t)g, F_NEW);
         } else {
             key = empty_key(lane);
@@ -314,6 +316,8 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
     uint64_t *kept = kept_all[w];
     const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
     if (i >= n)
+        return;
+    if (a.touched && i < a.rows_with_rear && a.touched[i] < 0)
         return;
     int rear0 = a.k1;
     if (!selected_base_row(a.seed, a.balanced, i, a.rows_with_rear, a.n_raw))
@@ -372,20 +376,57 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
     }
 }
 
-// one thread per entry
-__global__ __launch_bounds__(256) void k_keys_to_graph(const uint64_t *__restrict__ keys,
-                                                       int kin, int64_t n, int k,
-                                                       int32_t *__restrict__ ids,
-                                                       float *__restrict__ dist)
+// one wave per row: commit of one request into the resident lists
+template <int KB>
+__global__ __launch_bounds__(256) void k_commit(CommitArgs a)
 {
-    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= n * k)
+    const int lane = lane_id();
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    if (i >= a.m_base + a.n_req)
         return;
-    const int64_t i = e / k;
-    const uint64_t v = keys[i * kin + (e - i * k)];
-    const bool empty = key_empty(v);
-    ids[e] = empty ? -1 : (int32_t)key_id(v);
-    dist[e] = empty ? __uint_as_float(0x7F800000u) : key_dist(v);
+    const uint64_t e = lane < a.k ? a.out[i * a.gs + lane] : ~0ull;
+    const bool real = lane < a.k && !key_empty(e);
+    const uint32_t id = key_id(e);
+    const uint32_t gid = id < a.m_base ? id : (uint32_t)(a.first + (id - a.m_base));
+    const uint64_t ge = make_key(key_dist(e), gid, 0);
+    if (i < a.m_base) {
+        if (a.touched[i] < 0 || !real || id < a.m_base)
+            return;
+        bounded_insert<KB>(a.res + i * a.k, a.k, ge, true, nullptr, a.ctr + C_ERR);
+    } else if (lane < a.k) {
+        a.res[(a.first + (i - a.m_base)) * a.k + lane] = real ? ge : empty_key(lane);
+    }
+}
+
+// one wave per row: sort k keys by value (empties last)
+__global__ __launch_bounds__(256) void k_sort_rows(const uint64_t *__restrict__ src, int sst,
+                                                   int64_t n, int k, uint64_t *dst, int dstst,
+                                                   int32_t *ids, float *dist)
+{
+    const int lane = lane_id();
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    if (i >= n)
+        return;
+    uint64_t v = lane < k ? src[i * sst + lane] : ~0ull;
+    if (lane < k && key_empty(v))
+        v = ~0ull;
+    v = v == ~0ull ? v : key_strip(v);
+    int rank = 0;
+    for (int j = 0; j < k; j++) {
+        const uint64_t o = __shfl(v, j, WAVE);
+        rank += o < v || (o == v && j < lane);
+    }
+    if (lane < k) {
+        const bool empty = v == ~0ull;
+        if (dst)
+            dst[i * dstst + rank] = empty ? empty_key(rank) : v;
+        if (ids) {
+            ids[i * k + rank] = empty ? -1 : (int32_t)key_id(v);
+            dist[i * k + rank] = empty ? __uint_as_float(0x7F800000u) : key_dist(v);
+        }
+    }
+    if (dst && lane >= k && lane < dstst)
+        dst[i * dstst + lane] = empty_key(lane);
 }
 
 __global__ void k_zero(uint64_t *p, int words)
@@ -462,13 +503,28 @@ hipError_t launch_final(const FinalArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_keys_to_graph(const uint64_t *keys, int kin, int64_t n, int k, int32_t *ids,
-                                float *dist, hipStream_t st)
+hipError_t launch_commit(const CommitArgs &a, hipStream_t st)
+{
+    const int64_t rows = a.m_base + a.n_req;
+    if (rows <= 0)
+        return hipSuccess;
+    dim3 grid(grid_for(rows, 4)), block(256);
+    if (a.k <= 16)
+        hipLaunchKernelGGL(k_commit<16>, grid, block, 0, st, a);
+    else if (a.k <= 32)
+        hipLaunchKernelGGL(k_commit<32>, grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL(k_commit<64>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_rows(const uint64_t *src, int src_stride, int64_t n, int k, uint64_t *dst,
+                            int dst_stride, int32_t *ids, float *dist, hipStream_t st)
 {
     if (n <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_keys_to_graph, dim3(grid_for(n * k, 256)), dim3(256), 0, st, keys, kin,
-                       n, k, ids, dist);
+    hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n, 4)), dim3(256), 0, st, src, src_stride, n, k,
+                       dst, dst_stride, ids, dist);
     return hipGetLastError();
 }
 

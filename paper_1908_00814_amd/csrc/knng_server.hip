@@ -1,20 +1,27 @@
 // knng_server.hip -- J-Merge serving: a resident point set with its k-NN
 // graph absorbs requests of raw rows (Section 3.2: a built graph takes in
-// raw data without being rebuilt).  Requests are merged in batches: every
-// request waiting when the device turns free joins the next batch
-// (continuous batching), and a batch is one joint merge of the resident rows
-// with the batch's rows under balanced append.
+// raw data without being rebuilt).
 //
-// Device memory is allocated once at creation (the merge state for the full
-// capacity, the resident graph as sorted keys, a staging buffer) and rows
-// are never moved: request rows are packed at submission into their final
-// place, so a batch reads them where they are and its Merge and Sort writes
-// the new resident graph in place.
+// Every request is one balanced-append J-Merge of the current base (rows and
+// lists frozen until the next rebase) with the request's rows, seeded from
+// the request's own id, so its result does not depend on which requests run
+// beside it.  Requests run in slots -- a stream, a host thread and a merge
+// workspace each -- so several are on the device at once and a waiting
+// request starts as soon as a slot frees up.  When a request finishes, its
+// new entries are folded into the resident graph with the lock-free set-form
+// insert; the commits of different requests commute.
+//
+// Device memory is allocated once at creation: the row store for the full
+// capacity (request rows are packed at submission into their final place and
+// never move), the base lists, the resident lists, and one workspace per
+// slot.  A request's merge sees base rows [0, m) and its own rows, which the
+// row view maps onto their place in the store.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
 #include <mutex>
+#include <shared_mutex>
 #include <thread>
 
 #include "knng_host.h"
@@ -28,10 +35,11 @@ enum ReqState { Q_PENDING = 0, Q_RUNNING = 1, Q_DONE = 2 };
 
 struct Request {
     int64_t first = 0, n = 0;
+    uint64_t seed = 0;
     int state = Q_PENDING;
     knng_status rc = KNNG_OK;
     std::string err;
-    std::vector<uint64_t> keys;  // n x k result keys, filled at batch end
+    std::vector<uint64_t> keys;  // n x k result keys (global ids), filled at the end
     knng_request_info info{};
 };
 
@@ -41,6 +49,22 @@ double now_us(std::chrono::steady_clock::time_point t0)
         .count();
 }
 
+uint64_t sm64_host(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct Slot {
+    int idx = 0;
+    hipStream_t st = nullptr;
+    Layout w{};               // per-request merge state; row arrays point at the store
+    uint64_t *out = nullptr;  // capacity x gstride final keys of the request
+    std::thread th;
+};
+
 } // namespace
 
 struct knng_server {
@@ -48,190 +72,261 @@ struct knng_server {
     int d = 0, k = 0, gstride = 0;
     knng_metric metric = KNNG_L2;
     knng_opts opts{};
-    bool bf16 = false;
-    int64_t capacity = 0, max_batch = 0;
+    bool bf16 = false, manual = false;
+    int64_t capacity = 0, max_request = 0;
     void *mem = nullptr;
-    Layout w{};
-    float *stage = nullptr;     // max_batch x d: host rows on their way in
+    Layout store{};           // x, norm, xb, sq, eb for all rows; gin = base lists
+    uint64_t *res = nullptr;  // capacity x k resident lists
+    float *stage = nullptr;   // max_request x d: host rows on their way in
     uint64_t *sub_ctr = nullptr;
-    hipStream_t run_st = nullptr, sub_st = nullptr;
+    hipStream_t sub_st = nullptr;
+    std::vector<Slot> slots;
     std::chrono::steady_clock::time_point t0;
 
-    std::mutex mu;        // everything below
-    std::mutex run_mu;    // held while a batch runs or the graph is read out
-    std::mutex sub_mu;    // one submission at a time
+    std::shared_mutex state_mu;  // shared: a request in a slot; exclusive: snapshot, rebase
+    std::mutex mu;               // queue, counters and records below
+    std::mutex sub_mu;           // one submission at a time
     std::condition_variable cv_work, cv_done;
-    int64_t resident = 0;  // rows merged (base + finished batches)
-    int64_t reserved = 0;  // rows taken by accepted submissions
+    int64_t m_base = 0;     // rows of the base the requests merge with
+    int64_t reserved = 0;   // rows taken by accepted submissions
+    int64_t committed = 0;  // request rows folded into the resident graph since the rebase
+    int64_t running = 0;
     uint64_t next_ticket = 1;
-    int64_t batches = 0;
     std::deque<uint64_t> pending;
     std::map<uint64_t, Request> reqs;
-    bool stop = false, manual = false, failed = false;
+    bool stop = false, failed = false;
     std::string fail_text;
-    std::thread worker;
 };
 
 namespace {
 
-// the device layout of a server; with base == nullptr it only measures
-void carve_server(Carve &c, knng_server &s, int s_sample)
+// device layout shared by the requests; with base == nullptr it only measures
+void carve_store(Carve &c, knng_server &s)
 {
-    carve_merge(c, s.w, s.capacity, s.capacity, s.d, s.k, s.gstride, s_sample, s.metric,
-                s.bf16);
-    s.stage = c.take<float>((size_t)s.max_batch * s.d);
+    Layout &w = s.store;
+    w.dp = pad4(s.d);
+    w.db = (s.d + 31) / 32 * 32;
+    w.gstride = s.gstride;
+    w.x = c.take<float>((size_t)s.capacity * w.dp);
+    w.norm = s.metric == KNNG_COSINE ? c.take<float>(s.capacity) : nullptr;
+    w.xb = s.bf16 ? c.take<uint16_t>((size_t)s.capacity * w.db) : nullptr;
+    w.sq = s.bf16 ? c.take<float>(s.capacity) : nullptr;
+    w.eb = s.bf16 ? c.take<float>(s.capacity) : nullptr;
+    w.gin = c.take<uint64_t>((size_t)s.capacity * s.gstride);
+    w.ctr = c.take<uint64_t>(C_WORDS);
+    s.res = c.take<uint64_t>((size_t)s.capacity * s.k);
+    s.stage = c.take<float>((size_t)s.max_request * s.d);
     s.sub_ctr = c.take<uint64_t>(C_WORDS);
 }
 
-Rows rows_of(const knng_server &s, int64_t n)
+// one slot's merge state for a problem of up to `capacity` rows
+void carve_slot(Carve &c, const knng_server &s, Slot &sl)
 {
-    Rows R;
-    R.x = s.w.x;
-    R.norm = s.w.norm;
-    R.xb = s.w.xb;
-    R.sq = s.w.sq;
-    R.eb = s.w.eb;
-    R.n = n;
-    R.d = s.d;
-    R.dp = s.w.dp;
-    R.db = s.w.db;
-    return R;
+    const int64_t n = s.capacity;
+    const int k = s.k, sm = s.opts.sample;
+    Layout &w = sl.w;
+    w = s.store;  // row arrays and base lists are shared
+    w.ctr = c.take<uint64_t>(C_WORDS);
+    w.L = c.take<uint64_t>((size_t)n * k);
+    w.worst = c.take<uint64_t>(n);
+    w.new_f = c.take<int32_t>((size_t)n * sm);
+    w.old_f = c.take<int32_t>((size_t)n * k);
+    w.cnt_f = c.take<int32_t>((size_t)n * 2);
+    w.rnew = c.take<uint64_t>((size_t)n * sm);
+    w.rold = c.take<uint64_t>((size_t)n * sm);
+    w.dtag = c.take<int32_t>(n);
+    w.atag = c.take<int32_t>(n);
+    w.rfill = c.take<int32_t>((size_t)n * 2);
+    sl.out = c.take<uint64_t>((size_t)n * s.gstride);
 }
 
-// One batch: every pending request that fits in max_batch rows (at least
-// one), merged into the resident graph.  Caller holds no lock.
-knng_status run_batch(knng_server *s, bool *ran)
+size_t store_bytes(knng_server &s)
 {
-    std::lock_guard<std::mutex> run_lock(s->run_mu);
-    std::vector<uint64_t> tickets;
-    int64_t rows = 0, m = 0, batch = 0;
+    Carve c(nullptr);
+    carve_store(c, s);
+    return c.off + 256;
+}
+
+size_t slot_bytes(const knng_server &s)
+{
+    Carve c(nullptr);
+    Slot sl;
+    carve_slot(c, s, sl);
+    return c.off + 256;
+}
+
+// One request in one slot (the caller holds the state lock shared).
+knng_status run_request(knng_server *s, Slot &sl, uint64_t ticket)
+{
+    int64_t m, first, nr;
+    uint64_t seed;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (s->failed)
-            return fail(KNNG_EDEVICE, "server failed earlier: %s", s->fail_text.c_str());
-        while (!s->pending.empty()) {
-            Request &r = s->reqs[s->pending.front()];
-            if (rows > 0 && rows + r.n > s->max_batch)
-                break;
-            rows += r.n;
-            tickets.push_back(s->pending.front());
-            s->pending.pop_front();
-            r.state = Q_RUNNING;
-            r.info.start_us = now_us(s->t0);
-        }
-        m = s->resident;
-        if (!tickets.empty())
-            batch = s->batches++;
+        Request &r = s->reqs[ticket];
+        m = s->m_base;
+        first = r.first;
+        nr = r.n;
+        seed = r.seed;
+        r.state = Q_RUNNING;
+        r.info.start_us = now_us(s->t0);
+        r.info.slot = sl.idx;
     }
-    *ran = !tickets.empty();
-    if (tickets.empty())
-        return ok();
     knng_opts o = s->opts;
     o.flags |= KNNG_FLAG_BALANCED_APPEND;
-    o.seed = s->opts.seed + (uint64_t)batch;
-    const int64_t n = m + rows;
+    o.seed = seed;
     knng_stats st;
     memset(&st, 0, sizeof st);
-    Prof prof{(o.flags & KNNG_FLAG_PROFILE) != 0, s->run_st};
-    std::vector<uint64_t> keys((size_t)rows * s->gstride);
-    knng_status rc = [&]() -> knng_status {
-        HIP_TRY(launch_zero_counters(s->w.ctr, C_WORDS, s->run_st));
-        const Rows R = rows_of(*s, n);
-        knng_status r = run_merge(R, s->w, s->metric, s->bf16, &o, n, m, s->k,
-                                  keep_count(&o, s->k), 1, m, nullptr, s->run_st, &st, prof,
-                                  s->w.gin);
+    Prof prof{(o.flags & KNNG_FLAG_PROFILE) != 0, sl.st};
+    std::vector<uint64_t> keys((size_t)nr * s->gstride);
+    const knng_status rc = [&]() -> knng_status {
+        Rows R;
+        R.x = sl.w.x;
+        R.norm = sl.w.norm;
+        R.xb = sl.w.xb;
+        R.sq = sl.w.sq;
+        R.eb = sl.w.eb;
+        R.n = m + nr;
+        R.d = s->d;
+        R.dp = sl.w.dp;
+        R.db = sl.w.db;
+        R.split = m;  // the request's rows m .. m+nr-1 are stored at first ..
+        R.off2 = first - m;
+        HIP_TRY(launch_zero_counters(sl.w.ctr, C_WORDS, sl.st));
+        knng_status r = run_merge(R, sl.w, s->metric, s->bf16, &o, m + nr, m, s->k,
+                                  keep_count(&o, s->k), 1, m, nullptr, sl.st, &st, prof, sl.out,
+                                  true);
         if (r != KNNG_OK)
             return r;
-        HIP_TRY(hipMemcpyAsync(keys.data(), s->w.gin + m * s->gstride,
-                               keys.size() * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                               s->run_st));
-        HIP_TRY(hipStreamSynchronize(s->run_st));
+        CommitArgs ca;
+        ca.out = sl.out;
+        ca.gs = s->gstride;
+        ca.k = s->k;
+        ca.touched = sl.w.dtag;
+        ca.m_base = m;
+        ca.n_req = nr;
+        ca.first = first;
+        ca.res = s->res;
+        ca.ctr = sl.w.ctr;
+        HIP_TRY(launch_commit(ca, sl.st));
+        HIP_TRY(hipMemcpyAsync(keys.data(), sl.out + m * s->gstride,
+                               keys.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, sl.st));
+        uint64_t h[C_WORDS];
+        r = read_ctr(sl.w.ctr, h, sl.st);
+        if (r != KNNG_OK)
+            return r;
+        if (h[C_ERR])
+            return fail(KNNG_EDEVICE, "%s", err_text(h[C_ERR]));
         return KNNG_OK;
     }();
     const std::string err = rc == KNNG_OK ? std::string() : g_err;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        const double t = now_us(s->t0);
+        Request &r = s->reqs[ticket];
+        r.state = Q_DONE;
+        r.rc = rc;
+        r.err = err;
+        r.info.done_us = now_us(s->t0);
+        r.info.rounds = st.rounds;
+        r.info.evals = st.evals;
         if (rc == KNNG_OK) {
-            s->resident = n;
+            s->committed += nr;
+            // the request's own rows are renumbered to their global ids
+            r.keys.resize((size_t)nr * s->k);
+            for (int64_t i = 0; i < nr; i++)
+                for (int j = 0; j < s->k; j++) {
+                    uint64_t v = keys[(size_t)i * s->gstride + j];
+                    const uint32_t id = (uint32_t)v >> 2;
+                    if ((uint32_t)(v >> 32) != 0xFFFFFFFFu && id >= (uint64_t)m)
+                        v = (v & 0xFFFFFFFF00000003ull) | ((uint64_t)(first + (id - m)) << 2);
+                    r.keys[(size_t)i * s->k + j] = v;
+                }
         } else {
-            // the resident graph may be half written: nothing more runs
+            // the resident graph may hold part of this commit: stop serving
             s->failed = true;
             s->fail_text = err;
-        }
-        for (uint64_t tk : tickets) {
-            Request &r = s->reqs[tk];
-            r.state = Q_DONE;
-            r.rc = rc;
-            r.err = err;
-            r.info.done_us = t;
-            r.info.batch = batch;
-            r.info.batch_rows = rows;
-            r.info.rounds = st.rounds;
-            r.info.evals = st.evals;
-            if (rc == KNNG_OK) {
-                r.keys.resize((size_t)r.n * s->k);
-                for (int64_t i = 0; i < r.n; i++)
-                    for (int j = 0; j < s->k; j++)
-                        r.keys[i * s->k + j] = keys[(r.first - m + i) * s->gstride + j];
-            }
-        }
-        if (s->failed) {
-            // requests still queued cannot run any more
-            for (uint64_t tk : s->pending) {
-                Request &r = s->reqs[tk];
-                r.state = Q_DONE;
-                r.rc = KNNG_EDEVICE;
-                r.err = "server failed: " + err;
-                r.info.done_us = t;
-            }
-            s->pending.clear();
         }
     }
     s->cv_done.notify_all();
     return rc;
 }
 
-void worker_main(knng_server *s)
+// pops the next request (waiting for one when asked); false when the server
+// stops, has failed, or (without waiting) nothing is queued
+bool next_request(knng_server *s, std::unique_lock<std::mutex> &lk, bool wait, uint64_t *t)
+{
+    if (wait)
+        s->cv_work.wait(lk, [&] { return s->stop || s->failed || !s->pending.empty(); });
+    if (s->stop || s->failed || s->pending.empty())
+        return false;
+    *t = s->pending.front();
+    s->pending.pop_front();
+    s->running++;
+    return true;
+}
+
+void finish_request(knng_server *s)
+{
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->running--;
+    }
+    s->cv_done.notify_all();
+}
+
+void slot_main(knng_server *s, Slot *sl)
 {
     (void)hipSetDevice(s->device);
-    std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        s->cv_work.wait(lk, [&] { return s->stop || (!s->pending.empty() && !s->failed); });
-        if (s->stop)
-            return;
-        lk.unlock();
-        bool ran = false;
-        (void)run_batch(s, &ran);
-        lk.lock();
+        uint64_t t;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (!next_request(s, lk, true, &t)) {
+                if (s->stop)
+                    return;
+                // failed: leave the queue to the waiters below
+                s->cv_done.notify_all();
+                return;
+            }
+        }
+        {
+            std::shared_lock<std::shared_mutex> state(s->state_mu);
+            (void)run_request(s, *sl, t);
+        }
+        finish_request(s);
     }
 }
 
-size_t server_bytes(knng_server &probe, int sample)
+// waits until no request is queued or running (caller holds no lock)
+knng_status drain(knng_server *s)
 {
-    Carve c(nullptr);
-    carve_server(c, probe, sample);
-    return c.off + 256;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->manual)
+        return s->pending.empty() ? KNNG_OK
+                                  : fail(KNNG_EBUSY, "manual server: run the queued requests "
+                                                     "with knng_server_step first");
+    s->cv_done.wait(lk, [&] { return s->failed || (s->pending.empty() && s->running == 0); });
+    return s->failed ? fail(KNNG_EDEVICE, "server failed: %s", s->fail_text.c_str()) : KNNG_OK;
 }
 
 } // namespace
 
 extern "C" {
 
-size_t knng_server_bytes(int64_t capacity, int64_t max_batch, int32_t d, int32_t k, int32_t kin,
-                         knng_metric metric, const knng_opts *opts)
+size_t knng_server_bytes(int64_t capacity, int64_t max_request, int32_t d, int32_t k, int32_t kin,
+                         knng_metric metric, const knng_opts *opts, int32_t slots)
 {
-    if (capacity < 2 || max_batch < 1 || d < 1 || k < 1 || !opts)
+    if (capacity < 2 || max_request < 1 || d < 1 || k < 1 || !opts || slots < 1)
         return 0;
     knng_server probe;
     probe.capacity = capacity;
-    probe.max_batch = max_batch;
+    probe.max_request = max_request;
     probe.d = d;
     probe.k = k;
     probe.gstride = kin > k ? kin : k;
     probe.metric = metric;
+    probe.opts = *opts;
     probe.bf16 = uses_bf16(metric, opts);
-    return server_bytes(probe, opts->sample);
+    return store_bytes(probe) + (size_t)slots * slot_bytes(probe);
 }
 
 knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_t k,
@@ -254,10 +349,13 @@ knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_
     if ((rc = check_graph_in(G, m, "G", k1)))
         return rc;
     if (cfg->capacity < m || cfg->capacity >= (1ll << 30) - 64)
-        return fail(KNNG_EINVAL, "capacity %lld must hold the base (%lld rows) and stay below 2^30",
+        return fail(KNNG_EINVAL,
+                    "capacity %lld must hold the base (%lld rows) and stay below 2^30",
                     (long long)cfg->capacity, (long long)m);
-    if (cfg->max_batch < 1)
-        return fail(KNNG_EINVAL, "max_batch must be >= 1");
+    if (cfg->max_request < 1)
+        return fail(KNNG_EINVAL, "max_request must be >= 1");
+    if (cfg->slots < 0 || cfg->slots > 64)
+        return fail(KNNG_EINVAL, "slots %d not in [0, 64]", cfg->slots);
     knng_server *s = new knng_server();
     s->d = base->d;
     s->k = k;
@@ -266,37 +364,52 @@ knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_
     s->opts = *opts;
     s->bf16 = uses_bf16(metric, opts);
     s->capacity = cfg->capacity;
-    s->max_batch = cfg->max_batch < cfg->capacity - m ? cfg->max_batch : cfg->capacity - m;
-    if (s->max_batch < 1)
-        s->max_batch = 1;
-    s->manual = cfg->manual != 0;
-    const size_t bytes = server_bytes(*s, opts->sample);
-    if (cfg->hbm_budget && bytes > cfg->hbm_budget) {
-        delete s;
-        return fail(KNNG_ENOMEM, "server needs %zu device bytes, budget %zu", bytes,
-                    (size_t)cfg->hbm_budget);
+    s->max_request = cfg->max_request;
+    s->manual = cfg->slots == 0;
+    const size_t gbytes = store_bytes(*s), sbytes = slot_bytes(*s);
+    int nslots = s->manual ? 1 : cfg->slots;
+    if (cfg->hbm_budget) {
+        // as many of the asked-for slots as the budget holds, at least one
+        const int64_t fit = cfg->hbm_budget > gbytes
+                                ? (int64_t)((cfg->hbm_budget - gbytes) / sbytes)
+                                : 0;
+        if (fit < 1) {
+            delete s;
+            return fail(KNNG_ENOMEM, "budget %llu bytes holds no slot (store %zu + slot %zu)",
+                        (unsigned long long)cfg->hbm_budget, gbytes, sbytes);
+        }
+        nslots = fit < nslots ? (int)fit : nslots;
     }
+    s->slots.resize(nslots);
     rc = [&]() -> knng_status {
         HIP_TRY(hipGetDevice(&s->device));
-        HIP_TRY(hipMalloc(&s->mem, bytes));
-        HIP_TRY(hipStreamCreateWithFlags(&s->run_st, hipStreamNonBlocking));
+        HIP_TRY(hipMalloc(&s->mem, gbytes + (size_t)nslots * sbytes));
         HIP_TRY(hipStreamCreateWithFlags(&s->sub_st, hipStreamNonBlocking));
         Carve c(s->mem);
-        carve_server(c, *s, opts->sample);
-        HIP_TRY(launch_zero_counters(s->sub_ctr, C_WORDS, s->run_st));
-        // base rows and their lists (validated, sorted keys) into the layout
+        carve_store(c, *s);
+        for (int i = 0; i < nslots; i++) {
+            s->slots[i].idx = i;
+            HIP_TRY(hipStreamCreateWithFlags(&s->slots[i].st, hipStreamNonBlocking));
+            carve_slot(c, *s, s->slots[i]);
+        }
+        // base rows and lists into the store (validated, sorted keys); the
+        // resident lists start as the base lists
         knng_set none{0, base->d, nullptr};
         Rows R;
-        knng_status r = prepare(base, G, &none, nullptr, metric, s->bf16, s->w, m, m, s->run_st, R);
+        knng_status r =
+            prepare(base, G, &none, nullptr, metric, s->bf16, s->store, m, m, s->sub_st, R);
         if (r != KNNG_OK)
             return r;
-        HIP_TRY(hipStreamSynchronize(s->run_st));
+        HIP_TRY(launch_sort_rows(s->store.gin, s->gstride, m, k, s->res, k, nullptr, nullptr,
+                                 s->sub_st));
+        HIP_TRY(hipStreamSynchronize(s->sub_st));
         return KNNG_OK;
     }();
     if (rc != KNNG_OK) {
         const std::string e = g_err;
-        if (s->run_st)
-            (void)hipStreamDestroy(s->run_st);
+        for (Slot &sl : s->slots)
+            if (sl.st)
+                (void)hipStreamDestroy(sl.st);
         if (s->sub_st)
             (void)hipStreamDestroy(s->sub_st);
         if (s->mem)
@@ -304,15 +417,16 @@ knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_
         delete s;
         return fail(rc, "%s", e.c_str());
     }
-    s->resident = s->reserved = m;
+    s->m_base = s->reserved = m;
     s->t0 = std::chrono::steady_clock::now();
     if (!s->manual)
-        s->worker = std::thread(worker_main, s);
+        for (Slot &sl : s->slots)
+            sl.th = std::thread(slot_main, s, &sl);
     *out = s;
     return ok();
 }
 
-knng_status knng_server_submit(knng_server *s, const float *raw, int64_t n_raw,
+knng_status knng_server_submit(knng_server *s, const float *raw, int64_t n_raw, uint64_t req_id,
                                uint64_t *ticket)
 {
     if (!s || !ticket)
@@ -326,17 +440,18 @@ knng_status knng_server_submit(knng_server *s, const float *raw, int64_t n_raw,
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->failed)
             return fail(KNNG_EDEVICE, "server failed earlier: %s", s->fail_text.c_str());
-        if (n_raw > s->max_batch)
-            return fail(KNNG_EINVAL, "request of %lld rows exceeds max_batch %lld",
-                        (long long)n_raw, (long long)s->max_batch);
+        if (n_raw > s->max_request)
+            return fail(KNNG_EINVAL, "request of %lld rows exceeds max_request %lld",
+                        (long long)n_raw, (long long)s->max_request);
         if (s->reserved + n_raw > s->capacity)
             return fail(KNNG_ENOMEM, "capacity %lld rows reached", (long long)s->capacity);
         row = s->reserved;
     }
-    // pack the rows into their final place (disjoint from every row a running
-    // batch reads), validate them, and compute their norms
+    // pack the rows into their place in the store (no running request reads
+    // it), validate them and compute their norms
     const bool on_device = is_device_ptr(raw);
     const knng_status rc = [&]() -> knng_status {
+        const Layout &w = s->store;
         const float *src = raw;
         if (!on_device) {
             HIP_TRY(hipMemcpyAsync(s->stage, raw, (size_t)n_raw * s->d * sizeof(float),
@@ -344,15 +459,13 @@ knng_status knng_server_submit(knng_server *s, const float *raw, int64_t n_raw,
             src = s->stage;
         }
         HIP_TRY(launch_zero_counters(s->sub_ctr, C_WORDS, s->sub_st));
-        HIP_TRY(launch_pack(nullptr, 0, src, n_raw, s->d, s->w.dp, s->w.x + row * s->w.dp,
-                            s->bf16 ? s->w.db : 0, s->bf16 ? s->w.xb + row * s->w.db : nullptr,
+        HIP_TRY(launch_pack(nullptr, 0, src, n_raw, s->d, w.dp, w.x + row * w.dp,
+                            s->bf16 ? w.db : 0, s->bf16 ? w.xb + row * w.db : nullptr,
                             s->sub_ctr, s->sub_st));
-        if (s->w.norm || s->w.sq)
-            HIP_TRY(launch_norms(s->w.x + row * s->w.dp, n_raw, s->w.dp,
-                                 s->w.norm ? s->w.norm + row : nullptr,
-                                 s->w.sq ? s->w.sq + row : nullptr,
-                                 s->w.eb ? s->w.eb + row : nullptr, s->metric == KNNG_COSINE,
-                                 s->sub_ctr, s->sub_st));
+        if (w.norm || w.sq)
+            HIP_TRY(launch_norms(w.x + row * w.dp, n_raw, w.dp, w.norm ? w.norm + row : nullptr,
+                                 w.sq ? w.sq + row : nullptr, w.eb ? w.eb + row : nullptr,
+                                 s->metric == KNNG_COSINE, s->sub_ctr, s->sub_st));
         uint64_t h[C_WORDS];
         knng_status r = read_ctr(s->sub_ctr, h, s->sub_st);
         if (r != KNNG_OK)
@@ -369,9 +482,11 @@ knng_status knng_server_submit(knng_server *s, const float *raw, int64_t n_raw,
         Request &r = s->reqs[t];
         r.first = row;
         r.n = n_raw;
+        r.seed = sm64_host(s->opts.seed ^ sm64_host(req_id));
         r.info.first_id = row;
+        r.info.rows = n_raw;
         r.info.submit_us = t_submit;
-        r.info.batch = -1;
+        r.info.slot = -1;
         s->reserved += n_raw;
         s->pending.push_back(t);
         *ticket = t;
@@ -385,12 +500,26 @@ knng_status knng_server_step(knng_server *s, int32_t *ran)
     if (!s)
         return fail(KNNG_EINVAL, "server is NULL");
     if (!s->manual)
-        return fail(KNNG_EINVAL, "knng_server_step needs a server created with manual = 1");
-    bool r = false;
-    const knng_status rc = run_batch(s, &r);
+        return fail(KNNG_EINVAL, "knng_server_step needs a server created with slots = 0");
+    uint64_t t;
+    bool got;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->failed)
+            return fail(KNNG_EDEVICE, "server failed earlier: %s", s->fail_text.c_str());
+        got = next_request(s, lk, false, &t);
+    }
     if (ran)
-        *ran = r ? 1 : 0;
-    return rc;
+        *ran = got ? 1 : 0;
+    if (!got)
+        return ok();
+    knng_status rc;
+    {
+        std::shared_lock<std::shared_mutex> state(s->state_mu);
+        rc = run_request(s, s->slots[0], t);
+    }
+    finish_request(s);
+    return rc == KNNG_OK ? ok() : rc;
 }
 
 knng_status knng_server_wait(knng_server *s, uint64_t ticket, int64_t timeout_us, int32_t *ids,
@@ -403,11 +532,21 @@ knng_status knng_server_wait(knng_server *s, uint64_t ticket, int64_t timeout_us
     if (it == s->reqs.end())
         return fail(KNNG_EINVAL, "unknown or already collected ticket %llu",
                     (unsigned long long)ticket);
-    auto done = [&] { return it->second.state == Q_DONE; };
+    auto done = [&] { return it->second.state == Q_DONE || (s->failed && it->second.state ==
+                                                                          Q_PENDING); };
     if (timeout_us < 0)
         s->cv_done.wait(lk, done);
     else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done))
         return fail(KNNG_EBUSY, "request %llu not finished yet", (unsigned long long)ticket);
+    if (it->second.state == Q_PENDING) {
+        // the server failed before this request ran
+        knng_request_info inf = it->second.info;
+        s->reqs.erase(it);
+        if (info)
+            *info = inf;
+        return fail(KNNG_EDEVICE, "server failed before the request ran: %s",
+                    s->fail_text.c_str());
+    }
     Request r = std::move(it->second);
     s->reqs.erase(it);
     lk.unlock();
@@ -438,11 +577,16 @@ knng_status knng_server_snapshot(knng_server *s, knng_graph *out, int64_t *n_row
 {
     if (!s)
         return fail(KNNG_EINVAL, "server is NULL");
-    std::lock_guard<std::mutex> run_lock(s->run_mu);
+    knng_status rc = drain(s);
+    if (rc != KNNG_OK)
+        return rc;
+    std::unique_lock<std::shared_mutex> state(s->state_mu);  // no request in a slot
     int64_t n;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        n = s->resident;
+        if (s->m_base + s->committed != s->reserved)
+            return fail(KNNG_EBUSY, "requests were submitted during the snapshot");
+        n = s->reserved;
     }
     if (n_rows)
         *n_rows = n;
@@ -453,25 +597,54 @@ knng_status knng_server_snapshot(knng_server *s, knng_graph *out, int64_t *n_row
                     (long long)out->n, out->k, (long long)n, s->k);
     if (!is_device_ptr(out->ids) || !is_device_ptr(out->dist))
         return fail(KNNG_EINVAL, "out->ids / out->dist must be device memory");
-    HIP_TRY(launch_keys_to_graph(s->w.gin, s->gstride, n, s->k, out->ids, out->dist, s->run_st));
-    HIP_TRY(hipStreamSynchronize(s->run_st));
+    HIP_TRY(launch_sort_rows(s->res, s->k, n, s->k, nullptr, 0, out->ids, out->dist, s->sub_st));
+    HIP_TRY(hipStreamSynchronize(s->sub_st));
     return ok();
 }
 
-knng_status knng_server_status(knng_server *s, int64_t *resident_rows, int64_t *pending_rows,
-                               int64_t *batches)
+knng_status knng_server_rebase(knng_server *s)
+{
+    if (!s)
+        return fail(KNNG_EINVAL, "server is NULL");
+    knng_status rc = drain(s);
+    if (rc != KNNG_OK)
+        return rc;
+    std::unique_lock<std::shared_mutex> state(s->state_mu);
+    int64_t n;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->m_base + s->committed != s->reserved)
+            return fail(KNNG_EBUSY, "requests were submitted during the rebase");
+        n = s->reserved;
+    }
+    // the resident graph, sorted, becomes the base lists
+    HIP_TRY(launch_sort_rows(s->res, s->k, n, s->k, s->store.gin, s->gstride, nullptr, nullptr,
+                             s->sub_st));
+    HIP_TRY(hipStreamSynchronize(s->sub_st));
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->m_base = n;
+        s->committed = 0;
+    }
+    return ok();
+}
+
+knng_status knng_server_status(knng_server *s, int64_t *base_rows, int64_t *committed_rows,
+                               int64_t *pending_rows)
 {
     if (!s)
         return fail(KNNG_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    if (resident_rows)
-        *resident_rows = s->resident;
+    if (base_rows)
+        *base_rows = s->m_base;
+    if (committed_rows)
+        *committed_rows = s->committed;
     if (pending_rows)
-        *pending_rows = s->reserved - s->resident;
-    if (batches)
-        *batches = s->batches;
+        *pending_rows = s->reserved - s->m_base - s->committed;
     return s->failed ? fail(KNNG_EDEVICE, "server failed: %s", s->fail_text.c_str()) : ok();
 }
+
+int32_t knng_server_slots(const knng_server *s) { return s ? (int32_t)s->slots.size() : 0; }
 
 void knng_server_destroy(knng_server *s)
 {
@@ -482,11 +655,14 @@ void knng_server_destroy(knng_server *s)
         s->stop = true;
     }
     s->cv_work.notify_all();
-    if (s->worker.joinable())
-        s->worker.join();  // a batch in flight finishes first
-    (void)hipStreamSynchronize(s->run_st);
+    for (Slot &sl : s->slots)
+        if (sl.th.joinable())
+            sl.th.join();  // a request in a slot finishes first
+    for (Slot &sl : s->slots) {
+        (void)hipStreamSynchronize(sl.st);
+        (void)hipStreamDestroy(sl.st);
+    }
     (void)hipStreamSynchronize(s->sub_st);
-    (void)hipStreamDestroy(s->run_st);
     (void)hipStreamDestroy(s->sub_st);
     (void)hipFree(s->mem);
     delete s;

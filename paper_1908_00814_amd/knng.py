@@ -28,8 +28,8 @@ ENTRY_POINTS = ["knng_opts_default", "knng_merge", "knng_merge_workspace_size", 
                 "knng_exact_graph_workspace_size", "knng_last_error", "knng_version",
                 "knng_merge_tree", "knng_merge_tree_workspace_size", "knng_server_bytes",
                 "knng_server_create", "knng_server_submit", "knng_server_step",
-                "knng_server_wait", "knng_server_snapshot", "knng_server_status",
-                "knng_server_destroy"]
+                "knng_server_wait", "knng_server_snapshot", "knng_server_rebase",
+                "knng_server_status", "knng_server_slots", "knng_server_destroy"]
 
 
 class Opts(ctypes.Structure):
@@ -74,20 +74,19 @@ class Stats(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("capacity", ctypes.c_int64), ("max_batch", ctypes.c_int64),
-                ("hbm_budget", ctypes.c_uint64), ("manual", ctypes.c_int32),
+    _fields_ = [("capacity", ctypes.c_int64), ("max_request", ctypes.c_int64),
+                ("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
-    _fields_ = [("first_id", ctypes.c_int64), ("batch", ctypes.c_int64),
-                ("batch_rows", ctypes.c_int64), ("evals", ctypes.c_int64),
-                ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("first_id", ctypes.c_int64), ("rows", ctypes.c_int64),
+                ("evals", ctypes.c_int64), ("rounds", ctypes.c_int32), ("slot", ctypes.c_int32),
                 ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double),
                 ("done_us", ctypes.c_double)]
 
     def to_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class KnngError(RuntimeError):
@@ -133,18 +132,22 @@ def load():
     lib.knng_merge_tree_workspace_size.restype = SZ
     lib.knng_merge_tree_workspace_size.argtypes = [I64, I32, I32, P, I32, I32, ctypes.c_int, pO]
     lib.knng_server_bytes.restype = SZ
-    lib.knng_server_bytes.argtypes = [I64, I64, I32, I32, I32, ctypes.c_int, pO]
+    lib.knng_server_bytes.argtypes = [I64, I64, I32, I32, I32, ctypes.c_int, pO, I32]
     lib.knng_server_create.restype = ctypes.c_int
     lib.knng_server_create.argtypes = [pS, pG, I32, ctypes.c_int, pO,
                                        ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
     lib.knng_server_submit.restype = ctypes.c_int
-    lib.knng_server_submit.argtypes = [P, P, I64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.knng_server_submit.argtypes = [P, P, I64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     lib.knng_server_step.restype = ctypes.c_int
     lib.knng_server_step.argtypes = [P, ctypes.POINTER(I32)]
     lib.knng_server_wait.restype = ctypes.c_int
     lib.knng_server_wait.argtypes = [P, ctypes.c_uint64, I64, P, P, ctypes.POINTER(RequestInfo)]
     lib.knng_server_snapshot.restype = ctypes.c_int
     lib.knng_server_snapshot.argtypes = [P, pG, ctypes.POINTER(I64)]
+    lib.knng_server_rebase.restype = ctypes.c_int
+    lib.knng_server_rebase.argtypes = [P]
+    lib.knng_server_slots.restype = I32
+    lib.knng_server_slots.argtypes = [P]
     lib.knng_server_status.restype = ctypes.c_int
     lib.knng_server_status.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64),
                                        ctypes.POINTER(I64)]
@@ -330,37 +333,41 @@ def version():
 
 
 class Server:
-    """J-Merge serving (knng_server_*): a resident base that absorbs requests
-    of raw rows, merged in batches.  base: device (n, d) fp32; G = (ids, dist
-    or None) of the base, local ids."""
+    """J-Merge serving (knng_server_*): a resident graph that absorbs requests
+    of raw rows, each merged with the base independently, several at a time.
+    base: device (n, d) fp32; G = (ids, dist or None) of the base, local ids.
+    slots = 0 runs requests only inside step()."""
 
-    def __init__(self, base, G, k, metric="l2", capacity=None, max_batch=None, hbm_budget=0,
-                 manual=False, **kw):
+    def __init__(self, base, G, k, metric="l2", capacity=None, max_request=None, hbm_budget=0,
+                 slots=4, **kw):
         lib = load()
         o = opts(**kw)
         cfg = ServerConfig(int(capacity if capacity is not None else 2 * base.shape[0]),
-                           int(max_batch if max_batch is not None else base.shape[0]),
-                           int(hbm_budget), int(bool(manual)), 0)
+                           int(max_request if max_request is not None else base.shape[0]),
+                           int(hbm_budget), int(slots), 0)
         h = ctypes.c_void_p()
         _check(lib.knng_server_create(ctypes.byref(_set(base)), ctypes.byref(_graph(*G)), k,
                                       _metric(metric), ctypes.byref(o), ctypes.byref(cfg),
                                       ctypes.byref(h)))
         self._h, self.k, self.d, self.device = h, k, base.shape[1], base.device
+        self.slots = lib.knng_server_slots(h)
 
-    def submit(self, raw):
+    def submit(self, raw, req_id):
         """Queues the rows of raw ((n, d) fp32, device tensor or host
-        tensor/array; copied before return).  Returns the ticket."""
+        tensor/array; copied before return) as request req_id.  Returns the
+        ticket."""
         if not isinstance(raw, torch.Tensor):
             raw = torch.from_numpy(raw)
         assert raw.dtype == torch.float32 and raw.dim() == 2 and raw.shape[1] == self.d
         raw = raw.contiguous()
         t = ctypes.c_uint64()
         _check(load().knng_server_submit(self._h, ctypes.c_void_p(raw.data_ptr()), raw.shape[0],
-                                         ctypes.byref(t)))
+                                         int(req_id) & (2 ** 64 - 1), ctypes.byref(t)))
         return t.value
 
     def step(self):
-        """Manual servers: runs one batch; False when nothing was waiting."""
+        """Servers without slots: runs the oldest queued request; False when
+        none was queued."""
         ran = ctypes.c_int32()
         _check(load().knng_server_step(self._h, ctypes.byref(ran)))
         return bool(ran.value)
@@ -376,7 +383,7 @@ class Server:
         return ids, dist, info.to_dict()
 
     def snapshot(self):
-        """The resident graph as device tensors (ids, dist)."""
+        """The resident graph as device tensors (ids, dist), rows sorted."""
         n = ctypes.c_int64()
         _check(load().knng_server_snapshot(self._h, None, ctypes.byref(n)))
         ids, dist = _out(n.value, self.k, self.device)
@@ -384,11 +391,14 @@ class Server:
         _check(load().knng_server_snapshot(self._h, ctypes.byref(g), ctypes.byref(n)))
         return ids[:n.value], dist[:n.value]
 
+    def rebase(self):
+        _check(load().knng_server_rebase(self._h))
+
     def status(self):
-        r, p, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        _check(load().knng_server_status(self._h, ctypes.byref(r), ctypes.byref(p),
-                                         ctypes.byref(b)))
-        return {"resident": r.value, "pending": p.value, "batches": b.value}
+        b, c, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().knng_server_status(self._h, ctypes.byref(b), ctypes.byref(c),
+                                         ctypes.byref(p)))
+        return {"base": b.value, "committed": c.value, "pending": p.value}
 
     def close(self):
         if self._h:
@@ -402,7 +412,7 @@ class Server:
             pass
 
 
-def server_bytes(capacity, max_batch, d, k, kin, metric="l2", **kw):
+def server_bytes(capacity, max_request, d, k, kin, metric="l2", slots=1, **kw):
     o = opts(**kw)
-    return load().knng_server_bytes(capacity, max_batch, d, k, kin, _metric(metric),
-                                    ctypes.byref(o))
+    return load().knng_server_bytes(capacity, max_request, d, k, kin, _metric(metric),
+                                    ctypes.byref(o), slots)

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "knng_merge.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:knng_status|size_t|void|int|const char \*)\s*\*?\s*(knng_\w+)\s*\(",
+    names = re.findall(r"^\s*(?:knng_status|size_t|void|int32_t|int|const char \*)\s*\*?\s*(knng_\w+)\s*\(",
                        text, flags=re.M)
     return sorted(set(names))
 

@@ -1,7 +1,7 @@
-"""J-Merge server (knng_server_*): batches of requests against a resident
-graph.  Each batch must equal one balanced-append J-Merge of the resident set
-with the batch's rows (the oracle's, id for id), and the resident graph must
-equal the chain of those merges."""
+"""J-Merge server (knng_server_*).  Every request must equal one
+balanced-append J-Merge of the base with its rows (the oracle's, id for id)
+whatever runs beside it, and the resident graph must equal the base lists
+with every request's new entries folded in (top k of the union)."""
 import threading
 
 import numpy as np
@@ -13,12 +13,47 @@ from test_gpu_parity import assert_same_graph, dev, host
 
 pytestmark = pytest.mark.gpu
 
+M64 = 2 ** 64 - 1
 
-def _sets(nb, sizes, d, seed, metric="l2"):
+
+def _sets(nb, sizes, d, seed):
     g = synth.rng(seed)
     base = g.standard_normal((nb, d)).astype(np.float32)
     reqs = [(g.standard_normal((m, d)) + 0.3).astype(np.float32) for m in sizes]
     return base, reqs
+
+
+def _seed(seed, req_id):
+    return oracle.splitmix64((seed ^ oracle.splitmix64(req_id)) & M64)
+
+
+def _alone(X, G, raw, k, metric, first, s, seed, req_id):
+    """The oracle's J-Merge of the base with one request, ids renumbered to
+    the server's (request rows from `first`)."""
+    m = X.shape[0]
+    oi, od, ost = oracle.jmerge(X, G, raw, k, metric, sample=s, seed=_seed(seed, req_id),
+                                balanced=True)
+    oi = np.where(oi >= m, oi - m + first, oi)
+    return oi, od, ost
+
+
+def _fold(G, results, m, k):
+    """Base lists with every request's entries of request rows folded in,
+    followed by the requests' own rows (in id order)."""
+    ids, dist = [], []
+    for u in range(m):
+        cand = {int(a): float(b) for a, b in zip(G[0][u], G[1][u])}
+        for oi, od, _, first, n in results:
+            for a, b in zip(oi[u], od[u]):
+                if a >= m:
+                    cand[int(a)] = float(b)
+        best = sorted(cand.items(), key=lambda e: (np.float32(e[1]), e[0]))[:k]
+        ids.append([a for a, _ in best])
+        dist.append([b for _, b in best])
+    for oi, od, _, first, n in sorted(results, key=lambda r: r[3]):
+        ids.extend(oi[m:m + n].tolist())
+        dist.extend(od[m:m + n].tolist())
+    return np.array(ids, np.int32), np.array(dist, np.float32)
 
 
 def _server(hip, base, G, k, metric, **kw):
@@ -26,54 +61,53 @@ def _server(hip, base, G, k, metric, **kw):
 
 
 @pytest.mark.parametrize("metric", ["l2", "cos"])
-def test_manual_batches_equal_the_oracle_chain(hip, metric):
+def test_each_request_is_the_oracles_merge_with_the_base(hip, metric):
     k, s, seed = 8, 6, 31
-    base, reqs = _sets(1200, [37, 5, 60, 22, 9], 11, 120)
+    base, reqs = _sets(1200, [37, 5, 60], 11, 120)
+    m = base.shape[0]
     G = oracle.exact_graph(base, k, metric)
-    srv = _server(hip, base, G, k, metric, capacity=1400, max_batch=120, manual=True,
-                  sample=s, seed=seed)
+    srv = _server(hip, base, G, k, metric, capacity=1400, max_request=100, slots=0, sample=s,
+                  seed=seed)
     try:
-        # batch 0: the first three requests (102 rows); batch 1: the other two
-        X, GX = base, G
-        for b, group in enumerate(([0, 1, 2], [3, 4])):
-            tickets = [srv.submit(dev(reqs[i]) if i % 2 else reqs[i]) for i in group]
-            assert srv.step() and not srv.step()
-            raw = np.concatenate([reqs[i] for i in group])
-            oi, od, ost = oracle.jmerge(X, GX, raw, k, metric, sample=s, seed=seed + b,
-                                        balanced=True)
-            first = X.shape[0]
-            for t, i in zip(tickets, group):
-                ids, dist, info = srv.wait(t, len(reqs[i]))
-                assert info["first_id"] == first and info["batch"] == b
-                assert info["batch_rows"] == len(raw) and info["rounds"] == ost["rounds"]
-                assert info["evals"] == ost["evals"]
-                rows = slice(first, first + len(reqs[i]))
-                assert_same_graph(ids.numpy(), dist.numpy(), oi[rows], od[rows],
-                                  f"batch {b} request {i}")
-                first += len(reqs[i])
-            si, sd = srv.snapshot()
-            assert_same_graph(host(si), host(sd), oi, od, f"snapshot after batch {b}")
-            X, GX = np.concatenate([X, raw]), (oi, od)
-        assert srv.status() == {"resident": X.shape[0], "pending": 0, "batches": 2}
+        rids = [101, 202, 303]
+        tickets = [srv.submit(dev(r) if i % 2 else r, rid)
+                   for i, (r, rid) in enumerate(zip(reqs, rids))]
+        assert srv.step() and srv.step() and srv.step() and not srv.step()
+        first, results = m, []
+        for t, raw, rid in zip(tickets, reqs, rids):
+            ids, dist, info = srv.wait(t, len(raw))
+            oi, od, ost = _alone(base, G, raw, k, metric, first, s, seed, rid)
+            assert info["first_id"] == first and info["rows"] == len(raw)
+            assert info["rounds"] == ost["rounds"] and info["evals"] == ost["evals"]
+            assert_same_graph(ids.numpy(), dist.numpy(), oi[m:], od[m:], f"request {rid}")
+            results.append((oi, od, ost, first, len(raw)))
+            first += len(raw)
+        si, sd = srv.snapshot()
+        ei, ed = _fold(G, results, m, k)
+        assert_same_graph(host(si), host(sd), ei, ed, "resident graph")
+        assert srv.status() == {"base": m, "committed": first - m, "pending": 0}
     finally:
         srv.close()
 
 
-def test_worker_batches_replay_as_expand_chain(hip):
-    # requests submitted from two threads while the worker merges: whatever
-    # batches formed, the resident graph is the chain of balanced J-Merges of
-    # those batches, replayed here with knng_expand
+def test_results_are_the_same_in_a_mix(hip):
+    # ten requests from two threads on three slots: each result equals the
+    # request merged alone, and the resident graph does not depend on the
+    # order in which they finished
     k, s, seed = 10, 6, 5
-    base, reqs = _sets(3000, [int(v) for v in synth.rng(9).integers(1, 90, 24)], 16, 121)
+    sizes = [int(v) for v in synth.rng(9).integers(1, 70, 10)]
+    base, reqs = _sets(1500, sizes, 16, 121)
+    m = base.shape[0]
     G = oracle.exact_graph(base, k)
-    srv = _server(hip, base, G, k, "l2", capacity=3000 + sum(map(len, reqs)), max_batch=200,
+    srv = _server(hip, base, G, k, "l2", capacity=m + sum(sizes), max_request=80, slots=3,
                   sample=s, seed=seed)
+    assert srv.slots == 3
     tickets = {}
     lock = threading.Lock()
 
     def submitter(part):
         for i in part:
-            t = srv.submit(dev(reqs[i]))
+            t = srv.submit(dev(reqs[i]), 1000 + i)
             with lock:
                 tickets[i] = t
 
@@ -82,39 +116,42 @@ def test_worker_batches_replay_as_expand_chain(hip):
         t.start()
     for t in th:
         t.join()
-    infos = {}
-    res = {}
-    for i, t in tickets.items():
-        ids, dist, info = srv.wait(t, len(reqs[i]))
-        infos[i], res[i] = info, (ids.numpy(), dist.numpy())
+    got = {i: srv.wait(t, len(reqs[i])) for i, t in tickets.items()}
     si, sd = (host(a) for a in srv.snapshot())
     srv.close()
-    # rows in id order, grouped by batch
-    order = sorted(infos, key=lambda i: infos[i]["first_id"])
-    X = base
-    Gi, Gd = dev(G[0]), dev(G[1])
-    b_prev = -1
-    groups = []
-    for i in order:
-        if infos[i]["batch"] != b_prev:
-            groups.append([])
-            b_prev = infos[i]["batch"]
-        groups[-1].append(i)
-    assert [infos[g[0]]["batch"] for g in groups] == list(range(len(groups)))
-    for b, grp in enumerate(groups):
-        raw = np.concatenate([reqs[i] for i in grp])
-        assert all(infos[i]["batch_rows"] == len(raw) for i in grp)
-        gi, gd, _ = hip.expand(dev(X), (Gi, Gd), dev(raw), k, "l2", sample=s, seed=seed + b,
-                               balanced=True)
-        for i in grp:
-            lo = infos[i]["first_id"]
-            np.testing.assert_array_equal(res[i][0], host(gi)[lo:lo + len(reqs[i])])
-        X = np.concatenate([X, raw])
-        Gi, Gd = gi, gd
-    assert_same_graph(si, sd, host(Gi), host(Gd), "resident graph")
-    # every request waited no longer than its batch ran after it arrived
-    for i in infos:
-        assert infos[i]["submit_us"] <= infos[i]["start_us"] <= infos[i]["done_us"]
+    results = []
+    for i, (ids, dist, info) in got.items():
+        oi, od, ost = _alone(base, G, reqs[i], k, "l2", info["first_id"], s, seed, 1000 + i)
+        assert_same_graph(ids.numpy(), dist.numpy(), oi[m:], od[m:], f"request {i} in the mix")
+        assert info["submit_us"] <= info["start_us"] <= info["done_us"]
+        assert 0 <= info["slot"] < 3
+        results.append((oi, od, ost, info["first_id"], len(reqs[i])))
+    ei, ed = _fold(G, results, m, k)
+    assert_same_graph(si, sd, ei, ed, "resident graph after the mix")
+
+
+def test_rebase_lets_later_requests_meet_earlier_rows(hip):
+    k, s, seed = 8, 5, 77
+    base, reqs = _sets(900, [40, 30], 9, 123)
+    m = base.shape[0]
+    G = oracle.exact_graph(base, k)
+    srv = _server(hip, base, G, k, "l2", capacity=1000, max_request=64, slots=0, sample=s,
+                  seed=seed)
+    try:
+        t0 = srv.submit(reqs[0], 7)
+        assert srv.step()
+        srv.wait(t0, 40)
+        srv.rebase()
+        si, sd = (host(a) for a in srv.snapshot())
+        assert srv.status() == {"base": m + 40, "committed": 0, "pending": 0}
+        t1 = srv.submit(reqs[1], 8)
+        assert srv.step()
+        ids, dist, info = srv.wait(t1, 30)
+        X1 = np.concatenate([base, reqs[0]])
+        oi, od, _ = _alone(X1, (si, sd), reqs[1], k, "l2", m + 40, s, seed, 8)
+        assert_same_graph(ids.numpy(), dist.numpy(), oi[m + 40:], od[m + 40:], "after rebase")
+    finally:
+        srv.close()
 
 
 def test_server_errors(hip):
@@ -122,30 +159,33 @@ def test_server_errors(hip):
     k = 6
     base, reqs = _sets(300, [10, 50], 5, 122)
     G = oracle.exact_graph(base, k)
-    need = hip.server_bytes(400, 40, 5, k, k, "l2", sample=4)
+    need = hip.server_bytes(400, 40, 5, k, k, "l2", slots=1, sample=4)
     with pytest.raises(KnngError, match="ENOMEM"):
-        _server(hip, base, G, k, "l2", capacity=400, max_batch=40, hbm_budget=need - 1,
+        _server(hip, base, G, k, "l2", capacity=400, max_request=40, hbm_budget=need // 2,
                 sample=4)
-    srv = _server(hip, base, G, k, "l2", capacity=330, max_batch=40, hbm_budget=need,
-                  manual=True, sample=4)
+    srv = _server(hip, base, G, k, "l2", capacity=330, max_request=40, hbm_budget=10 * need,
+                  slots=0, sample=4)
     try:
         with pytest.raises(KnngError, match="EINVAL"):
-            srv.submit(reqs[1])                       # more rows than max_batch
+            srv.submit(reqs[1], 1)                    # more rows than max_request
         bad = reqs[0].copy()
         bad[3, 2] = np.nan
         with pytest.raises(KnngError, match="EINVAL"):
-            srv.submit(bad)                           # rejected, nothing reserved
-        t = srv.submit(reqs[0])
+            srv.submit(bad, 2)                        # rejected, nothing reserved
+        t = srv.submit(reqs[0], 3)
         with pytest.raises(KnngError, match="EBUSY"):
-            srv.wait(t, 10, timeout_us=0)             # manual server: not run yet
-        t2 = srv.submit(reqs[0][:5])
-        t3 = srv.submit(reqs[0][:10])
+            srv.wait(t, 10, timeout_us=0)             # no slots: not run yet
+        with pytest.raises(KnngError, match="EBUSY"):
+            srv.snapshot()                            # queued work on a server without slots
+        t2 = srv.submit(reqs[0][:5], 4)
+        t3 = srv.submit(reqs[0][:10], 5)
         with pytest.raises(KnngError, match="ENOMEM"):
-            srv.submit(reqs[0][:10])                  # 300 + 25 + 10 > 330
+            srv.submit(reqs[0][:10], 6)               # 300 + 25 + 10 > 330
         assert srv.status()["pending"] == 25
-        assert srv.step()
+        while srv.step():
+            pass
         ids, _, info = srv.wait(t, 10)
-        assert info["first_id"] == 300 and info["batch_rows"] == 25
+        assert info["first_id"] == 300 and info["rows"] == 10
         assert (ids.numpy() >= 0).all() and (ids.numpy() < 325).all()
         srv.wait(t2, 5)
         srv.wait(t3, 10)
