@@ -54,7 +54,9 @@ def recall_at10(ids, X, rows, device, metric="l2"):
         if metric == "l2":
             D = sq[r, None] + sq[None, :] - 2.0 * (Xd[r] @ Xd.T)
         else:
-            D = torch.cdist(Xd[r], Xd, p=1.0)
+            D = torch.empty((len(r), Xd.shape[0]), dtype=torch.float64, device=device)
+            for a in range(len(r)):        # explicit sum of |x - y| per query row
+                D[a] = (Xd - Xd[r[a]]).abs_().sum(1)
         D[torch.arange(len(r), device=device), r] = float("inf")
         kth = torch.topk(D, 10, dim=1, largest=False, sorted=True)[0][:, 9]
         got = torch.from_numpy(ids[rows[lo:lo + 100], :10].astype(np.int64)).to(device)
@@ -109,9 +111,8 @@ def join_roofline(st, n, d, k, s, prec="fp32"):
 
 
 def serve_bench(args, dev, precision):
-    """Serving workload: J-Merge server over a resident base, Poisson arrivals."""
-    import queue
-    import threading
+    """Serving workload: J-Merge server over a resident base, Poisson arrivals,
+    once with independent requests and once with batching."""
     import torch
     import synth
     from paper_1908_00814_amd import knng
@@ -131,10 +132,29 @@ def serve_bench(args, dev, precision):
     torch.cuda.synchronize()
     log(f"[serve] exact k={k} base graph in {time.perf_counter() - t:.1f}s")
     budget = args.serve_budget_gib << 30
-    srv = knng.Server(dB, (gi, gd), k, "l2", capacity=nb + int(offs[-1]), max_request=20_000,
-                      hbm_budget=budget, slots=args.serve_slots, sample=args.sample,
-                      delta=args.delta, seed=args.seed + 5, precision=precision)
+    modes = {}
+    for mode, slots, batching in (("independent", args.serve_slots, False),
+                                  ("batched", args.serve_batched_slots, True)):
+        modes[mode] = serve_run(args, dB, (gi, gd), dR, base, req, offs, sizes, k, nb, budget,
+                                slots, batching, precision, dev)
     del gi, gd
+    out = dict(modes["independent"])
+    out["batched"] = modes["batched"]
+    return out
+
+
+def serve_run(args, dB, G, dR, base, req, offs, sizes, k, nb, budget, slots, batching,
+              precision, dev):
+    """One serving run: warm-up burst, then Poisson arrivals at 0.7x capacity."""
+    import queue
+    import threading
+    import synth
+    from paper_1908_00814_amd import knng
+    W, R = args.serve_warmup, args.serve_requests
+    mode = "batched" if batching else "independent"
+    srv = knng.Server(dB, G, k, "l2", capacity=nb + int(offs[-1]), max_request=20_000,
+                      hbm_budget=budget, slots=slots, batching=batching, sample=args.sample,
+                      delta=args.delta, seed=args.seed + 5, precision=precision)
     try:
         # warm-up burst: every request queued at once, all slots busy
         tk = [srv.submit(dR[offs[i]:offs[i + 1]], i) for i in range(W)]
@@ -142,7 +162,7 @@ def serve_bench(args, dev, precision):
         span = (max(x["done_us"] for x in inf) - min(x["submit_us"] for x in inf)) / 1e6
         cap = float(sizes[:W].sum()) / span
         lam = 0.7 * cap / float(sizes[W:].mean())
-        log(f"[serve] {srv.slots} slots; warm-up: {int(sizes[:W].sum()):,} rows in "
+        log(f"[serve] {mode}, {srv.slots} slots; warm-up: {int(sizes[:W].sum()):,} rows in "
             f"{span * 1e3:.0f} ms -> capacity {cap:,.0f} rows/s; offered {lam:.1f} requests/s")
         gaps = synth.rng(5006).exponential(1.0 / lam, size=R)
         arrive = np.cumsum(gaps)
@@ -159,12 +179,13 @@ def serve_bench(args, dev, precision):
 
         th = threading.Thread(target=submitter)
         th.start()
-        infos, results = [], {}
+        infos, results, by_req = [], {}, {}
         for j in range(R):
             i, ticket = q.get()
             ids, _, info = srv.wait(ticket, int(sizes[i]))
             infos.append(info)
             results[i] = ids.numpy()
+            by_req[i] = info
             if (j + 1) % 250 == 0:
                 log(f"[serve] {j + 1}/{R} requests done")
         th.join()
@@ -173,29 +194,36 @@ def serve_bench(args, dev, precision):
         rows_meas = float(sizes[W:].sum())
     finally:
         srv.close()
-    rec = serve_recall(base, req, offs, sizes, results, W, dev)
+    rec = serve_recall(base, req, offs, sizes, results, W, dev, by_req)
+    how = ("queued requests merged together as one raw set when a slot frees up"
+           if batching else "each request merged with the base on its own")
     out = {
         "workload": (f"J-Merge server: resident base {nb:,} x d128 (same byte-valued "
                      f"mixture, exact k=20 graph), {R} requests of 1-20,000 rows "
                      f"(log-uniform) in Poisson arrivals at 0.7x the capacity measured on a "
-                     f"warm-up burst; each request merged with the base on its own "
-                     f"(balanced append), {srv.slots} slots, {precision}"),
+                     f"warm-up burst; {how} (balanced append), {srv.slots} slots, "
+                     f"{precision}"),
+        "mode": mode,
+        "mean_merged_rows": float(np.mean([x["merged_rows"] for x in infos])),
+        "mean_rounds": float(np.mean([x["rounds"] for x in infos])),
+        "mean_service_ms": float(np.mean([x["done_us"] - x["start_us"] for x in infos]) / 1e3),
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
         "inserted_points_per_s": rows_meas / wall, "capacity_rows_per_s": cap,
         "offered_requests_per_s": lam, "requests": R, "rows": int(rows_meas),
-        "slots": srv.slots, "hbm_budget_bytes": budget,
+        "slots": slots, "hbm_budget_bytes": budget,
         "recall@10_inserted": rec, "resident_rows_end": int(nb + offs[-1]),
     }
-    log(f"[serve] p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "
-        f"{out['inserted_points_per_s']:,.0f} rows/s, recall@10 of inserted rows "
-        f"(against base + own request) {rec:.4f}")
+    log(f"[serve] {mode}: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "
+        f"{out['inserted_points_per_s']:,.0f} rows/s, mean merged rows "
+        f"{out['mean_merged_rows']:,.0f}, recall@10 of inserted rows {rec:.4f}")
     return out
 
 
-def serve_recall(base, req, offs, sizes, results, W, dev, n_rows=1000):
+def serve_recall(base, req, offs, sizes, results, W, dev, infos):
     """recall@10 of inserted rows against their exact neighbours among the
-    base and their own request's rows (the set their merge covers)."""
+    base and the rows their merge covered (their own request's, or with
+    batching the whole batch's)."""
     import torch
     import synth
     g = synth.rng(5007)
@@ -206,18 +234,21 @@ def serve_recall(base, req, offs, sizes, results, W, dev, n_rows=1000):
     hits = total = 0
     for i in picked:
         lo, hi = int(offs[i]), int(offs[i + 1])
-        Xr = torch.from_numpy(req[lo:hi]).to(device=dev, dtype=torch.float64)
-        rows = g.choice(hi - lo, min(10, hi - lo), replace=False)
+        # the raw rows of the merge that ran request i (its own, or its batch)
+        mlo = int(infos[i]["merged_first"]) - nb
+        mhi = mlo + int(infos[i]["merged_rows"])
+        Xr = torch.from_numpy(req[mlo:mhi]).to(device=dev, dtype=torch.float64)
+        rows = g.choice(hi - lo, min(10, hi - lo), replace=False) + (lo - mlo)
         q = Xr[rows]
         Db = (q * q).sum(1)[:, None] + sqb[None, :] - 2.0 * (q @ Xb.T)
         Dr = (q * q).sum(1)[:, None] + (Xr * Xr).sum(1)[None, :] - 2.0 * (q @ Xr.T)
         Dr[torch.arange(len(rows), device=dev), torch.from_numpy(rows).to(dev)] = float("inf")
-        D = torch.cat([Db, Dr], 1)                      # columns: base rows, then own rows
+        D = torch.cat([Db, Dr], 1)                      # columns: base rows, then merged rows
         kth = torch.topk(D, 10, dim=1, largest=False)[0][:, 9]
-        ids = results[i][rows, :10].astype(np.int64)
-        first = nb + lo
+        ids = results[i][rows - (lo - mlo), :10].astype(np.int64)
+        first = nb + mlo
         col = np.where(ids < nb, ids, nb + (ids - first))
-        ok = (ids >= 0) & ((ids < nb) | ((ids >= first) & (ids < first + (hi - lo))))
+        ok = (ids >= 0) & ((ids < nb) | ((ids >= first) & (ids < first + (mhi - mlo))))
         got = torch.gather(D, 1, torch.from_numpy(np.where(ok, col, 0)).to(dev))
         hits += int(((got <= kth[:, None]) & torch.from_numpy(ok).to(dev)).sum().item())
         total += 10 * len(rows)
@@ -314,6 +345,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-batched-slots", type=int, default=2)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--no-tree", action="store_true", help="skip the merge-tree workload")
     args = ap.parse_args()

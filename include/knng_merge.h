@@ -83,8 +83,9 @@ typedef enum {
  * list, all OLD, and receive no samples.  Every raw row then meets about
  * k - k1 base rows through Append, as in the balanced case.  With
  * n_raw >= n_base every row is selected and the call is Algorithm 2 as
- * printed.  The work of a round then scales with the rows touched, not with
- * n_base (see knng_server_*). */
+ * printed.  Rows that never hold a NEW entry are skipped by the rounds'
+ * sampling and local join (they join nothing), so small raw sets cost little
+ * beyond one pass over the lists per round. */
 #define KNNG_FLAG_BALANCED_APPEND 2u
 
 /*
@@ -275,6 +276,12 @@ size_t knng_exact_graph_workspace_size(int64_t n, int32_t d, int32_t k, knng_met
  * slots is cfg->slots, lowered to what cfg->hbm_budget holds (slots = 0: no
  * thread, requests run inside knng_server_step).
  *
+ * cfg->batching = 1 trades that independence for quality under load: a slot
+ * that frees up takes every queued request that fits in max_request rows and
+ * merges them as ONE raw set (seed from the first request's id), so requests
+ * meet each other's rows; a request's result then depends on what it was
+ * batched with (knng_request_info.merged_rows).
+ *
  * Threads: submit, wait, step, snapshot, rebase and status may be called from
  * any threads concurrently; destroy must not overlap any other call on the
  * same server.  Work runs on the device that was current at creation.
@@ -286,12 +293,14 @@ typedef struct {
     int64_t max_request; /* most rows in one request */
     uint64_t hbm_budget; /* device bytes the server may allocate; 0 = no limit */
     int32_t slots;       /* requests on the device at once; 0 = run in knng_server_step */
-    int32_t reserved;
+    int32_t batching;    /* 1: a slot merges all queued requests that fit as one raw set */
 } knng_server_config;
 
 typedef struct {
     int64_t first_id;   /* id of the request's first row */
     int64_t rows;       /* rows of the request */
+    int64_t merged_first; /* id of the first raw row of the merge that ran it */
+    int64_t merged_rows; /* raw rows of that merge (> rows when batched) */
     int64_t evals;      /* distance evaluations of its merge */
     int32_t rounds;     /* rounds of its repeat loop */
     int32_t slot;       /* slot that ran it (-1: none) */

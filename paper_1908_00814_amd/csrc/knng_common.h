@@ -27,7 +27,19 @@ enum : uint32_t {
     ERR_BAD_DIST = 1u << 6,
     ERR_SPIN = 1u << 7,  // an insert exceeded its retry budget
     ERR_GROUP = 1u << 8, // neighbourhood larger than the kernel bound
+    // internal consistency: a row id read from a list, sample or queue fell
+    // outside [0, n); the access is skipped and the call fails
+    ERR_ROW_INSERT = 1u << 9,
+    ERR_ROW_REVERSE = 1u << 10,
+    ERR_ROW_GROUP = 1u << 11,
+    ERR_ROW_SAMPLE = 1u << 12,
+    ERR_ROW_COMMIT = 1u << 13,
 };
+
+__device__ __forceinline__ void raise_err(uint64_t *err_word, uint32_t bit)
+{
+    atomicOr((unsigned long long *)err_word, (unsigned long long)bit);
+}
 
 // counters block (uint64 words)
 enum : int {

@@ -201,6 +201,16 @@ inline const char *err_text(uint64_t bits)
         return "input graph distance negative or not finite";
     if (bits & ERR_SPIN)
         return "internal: list insert exceeded its retry budget";
+    if (bits & ERR_ROW_INSERT)
+        return "internal: a queued insert names a row out of range";
+    if (bits & ERR_ROW_REVERSE)
+        return "internal: a sampled edge names a row out of range";
+    if (bits & ERR_ROW_GROUP)
+        return "internal: a neighbourhood member is out of range";
+    if (bits & ERR_ROW_SAMPLE)
+        return "internal: a list entry names a row out of range";
+    if (bits & ERR_ROW_COMMIT)
+        return "internal: a committed entry names a row out of range";
     if (bits & ERR_GROUP)
         return "internal: neighbourhood exceeded the kernel bound";
     return "unknown device error";

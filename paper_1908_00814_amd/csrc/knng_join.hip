@@ -126,6 +126,10 @@ __device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a,
         if (!res_empty(wv))
             cid = (int32_t)(uint32_t)wv;
     }
+    if (cid >= a.n) {
+        raise_err(a.ctr + C_ERR, ERR_ROW_GROUP);
+        cid = -1;
+    }
     bool keep = cid >= 0;
     for (int j = 0; j < 2 * s; j++) {
         int32_t o = __shfl(cid, j, WAVE);
@@ -153,6 +157,10 @@ __device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a,
             uint64_t wv = a.rold[u * s + (c - k)];
             if (!res_empty(wv))
                 oc = (int32_t)(uint32_t)wv;
+        }
+        if (oc >= a.n) {
+            raise_err(a.ctr + C_ERR, ERR_ROW_GROUP);
+            oc = -1;
         }
         if (c < nco)
             L.told[c] = oc;
@@ -277,6 +285,10 @@ __device__ __forceinline__ bool tile_of(int t, const Regions &g, int joint, int 
 template <int KB>
 __device__ __forceinline__ void insert_into(const RoundArgs &a, int64_t dst, uint64_t key)
 {
+    if (dst < 0 || dst >= a.n || key_id(key) >= (uint64_t)a.n) {
+        raise_err(a.ctr + C_ERR, ERR_ROW_INSERT);
+        return;
+    }
     if (bounded_insert<KB>(a.L + dst * a.k, a.k, key, true, a.worst + dst, a.ctr + C_ERR))
         a.dtag[dst] = a.round + 1;
 }

@@ -389,6 +389,10 @@ __global__ __launch_bounds__(256) void k_commit(CommitArgs a)
     const uint32_t id = key_id(e);
     const uint32_t gid = id < a.m_base ? id : (uint32_t)(a.first + (id - a.m_base));
     const uint64_t ge = make_key(key_dist(e), gid, 0);
+    if (real && id >= a.m_base + a.n_req) {
+        raise_err(a.ctr + C_ERR, ERR_ROW_COMMIT);
+        return;
+    }
     if (i < a.m_base) {
         if (a.touched[i] < 0 || !real || id < a.m_base)
             return;

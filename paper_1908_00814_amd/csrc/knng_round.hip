@@ -59,7 +59,10 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
         const bool sampled = isnew && rank < a.s;
         if (sampled) {
             a.new_f[u * a.s + rank] = (int32_t)id;
-            a.atag[id] = a.round;
+            if (id < a.n)
+                a.atag[id] = a.round;
+            else
+                raise_err(a.ctr + C_ERR, ERR_ROW_SAMPLE);
         }
         uint64_t nv = v & ~(uint64_t)F_FRESH;
         if (sampled)
@@ -137,6 +140,10 @@ __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
             if (!sampled || j >= a.cnt_f[2 * u])
                 continue;
             v = a.new_f[u * a.s + j];
+            if (v < 0 || v >= a.n) {
+                raise_err(a.ctr + C_ERR, ERR_ROW_REVERSE);
+                continue;
+            }
             tag = TAG_RNEW;
             res = a.rnew;
             kind = 0;
@@ -151,6 +158,10 @@ __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
                 if (key_empty(w))
                     continue;
                 v = (int32_t)key_id(w);
+            }
+            if (v < 0 || v >= a.n) {
+                raise_err(a.ctr + C_ERR, ERR_ROW_REVERSE);
+                continue;
             }
             if (a.atag[v] != a.round)
                 continue;

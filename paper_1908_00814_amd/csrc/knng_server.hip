@@ -9,7 +9,10 @@
 // workspace each -- so several are on the device at once and a waiting
 // request starts as soon as a slot frees up.  When a request finishes, its
 // new entries are folded into the resident graph with the lock-free set-form
-// insert; the commits of different requests commute.
+// insert; the commits of different requests commute.  With batching on, a
+// slot that frees up merges all queued requests (up to max_request rows) as
+// one raw set instead: better bridges into the base for small requests, at
+// the price of results that depend on the batch.
 //
 // Device memory is allocated once at creation: the row store for the full
 // capacity (request rows are packed at submission into their final place and
@@ -72,7 +75,7 @@ struct knng_server {
     int d = 0, k = 0, gstride = 0;
     knng_metric metric = KNNG_L2;
     knng_opts opts{};
-    bool bf16 = false, manual = false;
+    bool bf16 = false, manual = false, batching = false;
     int64_t capacity = 0, max_request = 0;
     void *mem = nullptr;
     Layout store{};           // x, norm, xb, sq, eb for all rows; gin = base lists
@@ -155,21 +158,27 @@ size_t slot_bytes(const knng_server &s)
     return c.off + 256;
 }
 
-// One request in one slot (the caller holds the state lock shared).
-knng_status run_request(knng_server *s, Slot &sl, uint64_t ticket)
+// One merge in one slot: a single request, or (batching) several queued
+// requests whose rows are consecutive (the caller holds the state lock shared).
+knng_status run_request(knng_server *s, Slot &sl, const std::vector<uint64_t> &tickets)
 {
-    int64_t m, first, nr;
-    uint64_t seed;
+    int64_t m, first = 0, nr = 0;
+    uint64_t seed = 0;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        Request &r = s->reqs[ticket];
         m = s->m_base;
-        first = r.first;
-        nr = r.n;
-        seed = r.seed;
-        r.state = Q_RUNNING;
-        r.info.start_us = now_us(s->t0);
-        r.info.slot = sl.idx;
+        for (size_t i = 0; i < tickets.size(); i++) {
+            Request &r = s->reqs[tickets[i]];
+            if (i == 0) {
+                first = r.first;
+                seed = r.seed;
+            }
+            nr += r.n;
+            r.state = Q_RUNNING;
+            r.info.start_us = now_us(s->t0);
+            r.info.slot = sl.idx;
+            r.info.merged_rows = 0;
+        }
     }
     knng_opts o = s->opts;
     o.flags |= KNNG_FLAG_BALANCED_APPEND;
@@ -221,25 +230,33 @@ knng_status run_request(knng_server *s, Slot &sl, uint64_t ticket)
     const std::string err = rc == KNNG_OK ? std::string() : g_err;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        Request &r = s->reqs[ticket];
-        r.state = Q_DONE;
-        r.rc = rc;
-        r.err = err;
-        r.info.done_us = now_us(s->t0);
-        r.info.rounds = st.rounds;
-        r.info.evals = st.evals;
-        if (rc == KNNG_OK) {
-            s->committed += nr;
-            // the request's own rows are renumbered to their global ids
-            r.keys.resize((size_t)nr * s->k);
-            for (int64_t i = 0; i < nr; i++)
+        const double t_done = now_us(s->t0);
+        for (uint64_t ticket : tickets) {
+            Request &r = s->reqs[ticket];
+            r.state = Q_DONE;
+            r.rc = rc;
+            r.err = err;
+            r.info.done_us = t_done;
+            r.info.rounds = st.rounds;
+            r.info.evals = st.evals;
+            r.info.merged_rows = nr;
+            r.info.merged_first = first;
+            if (rc != KNNG_OK)
+                continue;
+            // the request's rows, renumbered to their global ids
+            const int64_t lo = r.first - first;
+            r.keys.resize((size_t)r.n * s->k);
+            for (int64_t i = 0; i < r.n; i++)
                 for (int j = 0; j < s->k; j++) {
-                    uint64_t v = keys[(size_t)i * s->gstride + j];
+                    uint64_t v = keys[(size_t)(lo + i) * s->gstride + j];
                     const uint32_t id = (uint32_t)v >> 2;
                     if ((uint32_t)(v >> 32) != 0xFFFFFFFFu && id >= (uint64_t)m)
                         v = (v & 0xFFFFFFFF00000003ull) | ((uint64_t)(first + (id - m)) << 2);
                     r.keys[(size_t)i * s->k + j] = v;
                 }
+        }
+        if (rc == KNNG_OK) {
+            s->committed += nr;
         } else {
             // the resident graph may hold part of this commit: stop serving
             s->failed = true;
@@ -250,16 +267,26 @@ knng_status run_request(knng_server *s, Slot &sl, uint64_t ticket)
     return rc;
 }
 
-// pops the next request (waiting for one when asked); false when the server
-// stops, has failed, or (without waiting) nothing is queued
-bool next_request(knng_server *s, std::unique_lock<std::mutex> &lk, bool wait, uint64_t *t)
+// pops the next request -- with batching, every queued request that fits in
+// max_request rows (at least one) -- waiting for one when asked; false when
+// the server stops, has failed, or (without waiting) nothing is queued
+bool next_request(knng_server *s, std::unique_lock<std::mutex> &lk, bool wait,
+                  std::vector<uint64_t> *t)
 {
     if (wait)
         s->cv_work.wait(lk, [&] { return s->stop || s->failed || !s->pending.empty(); });
     if (s->stop || s->failed || s->pending.empty())
         return false;
-    *t = s->pending.front();
-    s->pending.pop_front();
+    t->clear();
+    int64_t rows = 0;
+    while (!s->pending.empty()) {
+        const Request &r = s->reqs[s->pending.front()];
+        if (!t->empty() && (!s->batching || rows + r.n > s->max_request))
+            break;
+        rows += r.n;
+        t->push_back(s->pending.front());
+        s->pending.pop_front();
+    }
     s->running++;
     return true;
 }
@@ -277,7 +304,7 @@ void slot_main(knng_server *s, Slot *sl)
 {
     (void)hipSetDevice(s->device);
     for (;;) {
-        uint64_t t;
+        std::vector<uint64_t> t;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             if (!next_request(s, lk, true, &t)) {
@@ -366,6 +393,7 @@ knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_
     s->capacity = cfg->capacity;
     s->max_request = cfg->max_request;
     s->manual = cfg->slots == 0;
+    s->batching = cfg->batching != 0;
     const size_t gbytes = store_bytes(*s), sbytes = slot_bytes(*s);
     int nslots = s->manual ? 1 : cfg->slots;
     if (cfg->hbm_budget) {
@@ -501,7 +529,7 @@ knng_status knng_server_step(knng_server *s, int32_t *ran)
         return fail(KNNG_EINVAL, "server is NULL");
     if (!s->manual)
         return fail(KNNG_EINVAL, "knng_server_step needs a server created with slots = 0");
-    uint64_t t;
+    std::vector<uint64_t> t;
     bool got;
     {
         std::unique_lock<std::mutex> lk(s->mu);

@@ -76,11 +76,12 @@ class Stats(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("max_request", ctypes.c_int64),
                 ("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("batching", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
     _fields_ = [("first_id", ctypes.c_int64), ("rows", ctypes.c_int64),
+                ("merged_first", ctypes.c_int64), ("merged_rows", ctypes.c_int64),
                 ("evals", ctypes.c_int64), ("rounds", ctypes.c_int32), ("slot", ctypes.c_int32),
                 ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double),
                 ("done_us", ctypes.c_double)]
@@ -339,12 +340,12 @@ class Server:
     slots = 0 runs requests only inside step()."""
 
     def __init__(self, base, G, k, metric="l2", capacity=None, max_request=None, hbm_budget=0,
-                 slots=4, **kw):
+                 slots=4, batching=False, **kw):
         lib = load()
         o = opts(**kw)
         cfg = ServerConfig(int(capacity if capacity is not None else 2 * base.shape[0]),
                            int(max_request if max_request is not None else base.shape[0]),
-                           int(hbm_budget), int(slots), 0)
+                           int(hbm_budget), int(slots), int(bool(batching)))
         h = ctypes.c_void_p()
         _check(lib.knng_server_create(ctypes.byref(_set(base)), ctypes.byref(_graph(*G)), k,
                                       _metric(metric), ctypes.byref(o), ctypes.byref(cfg),

@@ -130,6 +130,34 @@ def test_results_are_the_same_in_a_mix(hip):
     assert_same_graph(si, sd, ei, ed, "resident graph after the mix")
 
 
+def test_batching_merges_queued_requests_as_one_raw_set(hip):
+    k, s, seed = 8, 6, 11
+    base, reqs = _sets(1000, [20, 7, 33], 10, 124)
+    m = base.shape[0]
+    G = oracle.exact_graph(base, k)
+    srv = _server(hip, base, G, k, "l2", capacity=1100, max_request=64, slots=0,
+                  batching=True, sample=s, seed=seed)
+    try:
+        tickets = [srv.submit(r, 50 + i) for i, r in enumerate(reqs)]
+        assert srv.step() and not srv.step()   # 60 rows fit in one merge of at most 64
+        raw = np.concatenate(reqs)
+        oi, od, ost = _alone(base, G, raw, k, "l2", m, s, seed, 50)
+        first = m
+        for t, r in zip(tickets, reqs):
+            ids, dist, info = srv.wait(t, len(r))
+            assert info["merged_first"] == m and info["merged_rows"] == len(raw)
+            assert info["rounds"] == ost["rounds"]
+            lo = first - m
+            assert_same_graph(ids.numpy(), dist.numpy(), oi[m + lo:m + lo + len(r)],
+                              od[m + lo:m + lo + len(r)], "batched request")
+            first += len(r)
+        si, sd = srv.snapshot()
+        ei, ed = _fold(G, [(oi, od, ost, m, len(raw))], m, k)
+        assert_same_graph(host(si), host(sd), ei, ed, "resident graph after a batch")
+    finally:
+        srv.close()
+
+
 def test_rebase_lets_later_requests_meet_earlier_rows(hip):
     k, s, seed = 8, 5, 77
     base, reqs = _sets(900, [40, 30], 9, 123)
