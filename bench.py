@@ -289,6 +289,73 @@ def tree_bench(args, dev):
     return out
 
 
+def cosine_bench(args, dev):
+    """High-dimensional cosine workload: S-Merge of 2 x 250,000 x d960, both
+    precisions, with the stored distances' error against FP64."""
+    import torch
+    import oracle
+    import synth
+    from synth.graphs import approximate_graph
+    from paper_1908_00814_amd import knng
+    k = 20
+    t = time.perf_counter()
+    S1, S2 = synth.cosine_sets()
+    G1 = approximate_graph(S1, k, 0.9, device=dev, workload=3, stream=6)[0]
+    G2 = approximate_graph(S2, k, 0.9, device=dev, workload=3, stream=7)[0]
+    log(f"[cosine] 2 x 250,000 x d960 and approximate k=20 inputs in "
+        f"{time.perf_counter() - t:.1f}s")
+    d = lambda a: torch.from_numpy(a).to(dev)
+    dS1, dS2, g1, g2 = d(S1), d(S2), (d(G1), None), (d(G2), None)
+    X = np.concatenate([S1, S2])
+    n = len(X)
+    rows = synth.rng(3008).choice(n, 500, replace=False)
+    out = {"workload": "symmetric merge, 2 x 250,000 x d960 nonnegative rows (|N(0,1)| plus "
+                       "one of 200 offsets), L2-normalised, approximate k=20 inputs without "
+                       "distances, merged to k=20 under cosine"}
+    graphs = {}
+    for prec in ("fp32", "bf16"):
+        kw = dict(sample=args.sample, delta=args.delta, seed=args.seed + 3, precision=prec)
+        knng.merge(dS1, g1, dS2, g2, k, "cos", **kw)            # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ids, dist, st = knng.merge(dS1, g1, dS2, g2, k, "cos", **kw)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t
+        graphs[prec] = (ids.cpu().numpy(), dist.cpu().numpy())
+        out[prec] = {"points_per_s": n / secs, "ms": secs * 1e3, "rounds": st["rounds"],
+                     "rescored": st["rescored"], "screen_violations": st["screen_violations"]}
+        log(f"[cosine] {prec}: {secs * 1e3:.0f} ms, {n / secs / 1e6:.2f} M points/s, "
+            f"{st['rounds']} rounds")
+    ids, dist = graphs["fp32"]
+    out["paths_identical"] = bool(np.array_equal(ids, graphs["bf16"][0]) and np.array_equal(
+        dist.view(np.uint32), graphs["bf16"][1].view(np.uint32)))
+    # FP64 error of every stored distance of the sampled rows (relative above
+    # 1e-3, absolute below)
+    rel, ab = [], []
+    for i in rows:
+        for j in range(k):
+            e = oracle.dist64("cos", X[i], X[ids[i, j]])
+            (rel if e >= 1e-3 else ab).append(abs(float(dist[i, j]) - e) / (e if e >= 1e-3 else 1))
+    out["fp64_error"] = {"max_rel": float(max(rel)) if rel else 0.0,
+                         "p999_rel": float(np.percentile(rel, 99.9)) if rel else 0.0,
+                         "max_abs_below_1e-3": float(max(ab)) if ab else 0.0,
+                         "entries": len(rel) + len(ab)}
+    Xd = torch.from_numpy(X).to(device=dev, dtype=torch.float64)
+    nrm = Xd.norm(dim=1)
+    hits = 0
+    for lo in range(0, len(rows), 100):
+        r = torch.from_numpy(rows[lo:lo + 100]).to(dev)
+        D = 1.0 - (Xd[r] @ Xd.T) / (nrm[r, None] * nrm[None, :])
+        D[torch.arange(len(r), device=dev), r] = float("inf")
+        kth = torch.topk(D, 10, dim=1, largest=False)[0][:, 9]
+        got = torch.from_numpy(ids[rows[lo:lo + 100], :10].astype(np.int64)).to(dev)
+        hits += (torch.gather(D, 1, got) <= kth[:, None] * (1 + 1e-12)).sum().item()
+    out["recall@10"] = hits / (len(rows) * 10)
+    log(f"[cosine] identical paths {out['paths_identical']}, recall@10 {out['recall@10']:.4f}, "
+        f"FP64 max rel err {out['fp64_error']['max_rel']:.2e}")
+    return out
+
+
 def cpu_baseline(n_per, k, s, delta, seed, dev, precision):
     """The oracle timed on a bounded sample of the headline workload; the GPU
     merges the same sample and the two graphs are compared."""
@@ -348,6 +415,7 @@ def main():
     ap.add_argument("--serve-batched-slots", type=int, default=2)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--no-tree", action="store_true", help="skip the merge-tree workload")
+    ap.add_argument("--no-cosine", action="store_true", help="skip the d960 cosine workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -457,6 +525,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_tree:
         line["tree"] = tree_bench(args, dev)
+        torch.cuda.empty_cache()
+    if not args.no_cosine:
+        line["cosine"] = cosine_bench(args, dev)
         torch.cuda.empty_cache()
     if not args.no_serve:
         line["serving"] = serve_bench(args, dev, best)

@@ -29,7 +29,6 @@ enum : uint32_t {
     ERR_GROUP = 1u << 8, // neighbourhood larger than the kernel bound
     // internal consistency: a row id read from a list, sample or queue fell
     // outside [0, n); the access is skipped and the call fails
-    ERR_ROW_INSERT = 1u << 9,
     ERR_ROW_REVERSE = 1u << 10,
     ERR_ROW_GROUP = 1u << 11,
     ERR_ROW_SAMPLE = 1u << 12,

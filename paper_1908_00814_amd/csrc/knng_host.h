@@ -201,8 +201,6 @@ inline const char *err_text(uint64_t bits)
         return "input graph distance negative or not finite";
     if (bits & ERR_SPIN)
         return "internal: list insert exceeded its retry budget";
-    if (bits & ERR_ROW_INSERT)
-        return "internal: a queued insert names a row out of range";
     if (bits & ERR_ROW_REVERSE)
         return "internal: a sampled edge names a row out of range";
     if (bits & ERR_ROW_GROUP)

@@ -285,10 +285,8 @@ __device__ __forceinline__ bool tile_of(int t, const Regions &g, int joint, int 
 template <int KB>
 __device__ __forceinline__ void insert_into(const RoundArgs &a, int64_t dst, uint64_t key)
 {
-    if (dst < 0 || dst >= a.n || key_id(key) >= (uint64_t)a.n) {
-        raise_err(a.ctr + C_ERR, ERR_ROW_INSERT);
-        return;
-    }
+    // dst and the key's id are neighbourhood members, range-checked when the
+    // neighbourhood was formed
     if (bounded_insert<KB>(a.L + dst * a.k, a.k, key, true, a.worst + dst, a.ctr + C_ERR))
         a.dtag[dst] = a.round + 1;
 }
@@ -340,7 +338,7 @@ __device__ inline void flush_counters(const RoundArgs &a, uint64_t pairs_lane, u
 
 // ============================================================ FP32 path
 template <int METRIC, int KB, int MU>
-__global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join(Rows R, RoundArgs a, int GS,
+__global__ __launch_bounds__(JOIN_WAVES * WAVE, MU == 8 ? 3 : 2) void k_join(Rows R, RoundArgs a, int GS,
                                                             int wave_bytes)
 {
     extern __shared__ __align__(16) unsigned char dyn[];

@@ -389,12 +389,16 @@ __global__ __launch_bounds__(256) void k_commit(CommitArgs a)
     const uint32_t id = key_id(e);
     const uint32_t gid = id < a.m_base ? id : (uint32_t)(a.first + (id - a.m_base));
     const uint64_t ge = make_key(key_dist(e), gid, 0);
+    // rows of the base that never held a NEW entry were not written by the
+    // merge's Merge and Sort and are skipped before their entries are read
+    if (i < a.m_base && a.touched[i] < 0)
+        return;
     if (real && id >= a.m_base + a.n_req) {
         raise_err(a.ctr + C_ERR, ERR_ROW_COMMIT);
         return;
     }
     if (i < a.m_base) {
-        if (a.touched[i] < 0 || !real || id < a.m_base)
+        if (!real || id < a.m_base)
             return;
         bounded_insert<KB>(a.res + i * a.k, a.k, ge, true, nullptr, a.ctr + C_ERR);
     } else if (lane < a.k) {

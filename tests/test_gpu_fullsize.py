@@ -1,5 +1,6 @@
-"""The benchmark workload at full size (2 x 500,000 x d128 byte-valued
-clusters, approximate k=20 inputs, merged to k=20, s=20, delta=0.001) in the
+"""The benchmark workloads at full size: 2 x 500,000 x d128 byte-valued
+clusters (l2) and 2 x 250,000 x d960 normalised rows (cosine), approximate k=20
+inputs, merged to k=20, s=20, delta=0.001, in the
 launch configuration bench.py times.  The oracle cannot run it whole, so the
 checks are per-row values it computes one by one (canonical distances of
 sampled rows, FP64 errors) and properties that hold at any size."""
@@ -103,3 +104,53 @@ def test_recall_at_10(w2):
         hits += (torch.gather(D, 1, got) <= kth[:, None]).sum().item()
     assert hits / (len(rows) * 10) >= 0.95
     assert st["rounds"] < 30
+
+
+# ---------------------------------------------------------------- cosine, d960
+
+@pytest.fixture(scope="module")
+def w3(hip):
+    # 2 x 250,000 x d960 L2-normalised nonnegative rows, approximate k=20
+    # inputs given without distances (the library computes them)
+    import torch
+    from synth.graphs import approximate_graph
+    S1, S2 = synth.cosine_sets()
+    G1 = approximate_graph(S1, K, 0.9, device="cuda", workload=3, stream=6)[0]
+    G2 = approximate_graph(S2, K, 0.9, device="cuda", workload=3, stream=7)[0]
+    d = lambda a: torch.from_numpy(a).cuda()
+    args = (d(S1), (d(G1), None), d(S2), (d(G2), None), K, "cos")
+    out = {}
+    for prec in ("fp32", "bf16"):
+        ids, dist, st = hip.merge(*args, sample=20, delta=0.001, seed=2007, precision=prec)
+        out[prec] = (ids.cpu().numpy(), dist.cpu().numpy(), st)
+    return np.concatenate([S1, S2]), out
+
+
+def test_cosine_d960_valid_canonical_and_close_to_fp64(w3):
+    X, out = w3
+    ids, dist, _ = out["fp32"]
+    n = X.shape[0]
+    assert (ids >= 0).all() and (ids < n).all()
+    assert not (ids == np.arange(n)[:, None]).any()
+    s = np.sort(ids, axis=1)
+    assert not (s[:, 1:] == s[:, :-1]).any()
+    assert (np.diff(dist, axis=1) >= 0).all()
+    rows = synth.rng(33).choice(n, 100, replace=False)
+    rel = []
+    for i in rows:
+        for j in range(K):
+            c = oracle.dist32("cos", X[i], X[ids[i, j]])
+            assert np.float32(c).view(np.uint32) == dist[i, j].view(np.uint32), (i, j)
+            e = oracle.dist64("cos", X[i], X[ids[i, j]])
+            rel.append(abs(float(dist[i, j]) - e) / max(e, 1e-3))
+    # canonical FP32 against FP64: relative above 1e-3, absolute (scaled by
+    # 1e-3) below; the sequential sum of 960 terms stays well inside 1e-5
+    assert max(rel) <= 1e-5
+
+
+def test_cosine_d960_bf16_screen_gives_the_fp32_graph(w3):
+    _, out = w3
+    assert np.array_equal(out["fp32"][0], out["bf16"][0])
+    assert np.array_equal(out["fp32"][1].view(np.uint32), out["bf16"][1].view(np.uint32))
+    assert out["bf16"][2]["screen_violations"] == 0
+    assert out["bf16"][2]["rescored"] > 0
