@@ -332,12 +332,19 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
     cand[lane] = c0;
     cand[WAVE + lane] = c1;
     __builtin_amdgcn_wave_barrier();
-    // keep the first occurrence of each entry
+    // keep the first occurrence of each entry (only slots [0, k) and
+    // [WAVE, WAVE + nrear) hold candidates; the rest hold ~0, which matches
+    // and outranks nothing)
     bool v0 = c0 != ~0ull, v1 = c1 != ~0ull;
-    for (int j = 0; j < 2 * WAVE; j++) {
-        uint64_t o = cand[j];
+    for (int j = 0; j < k; j++) {
+        const uint64_t o = cand[j];
         if (o == c0 && j < lane)
             v0 = false;
+        if (o == c1)
+            v1 = false;
+    }
+    for (int j = WAVE; j < WAVE + nrear; j++) {
+        const uint64_t o = cand[j];
         if (o == c1 && j < WAVE + lane)
             v1 = false;
     }
@@ -345,8 +352,13 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
     kept[WAVE + lane] = v1 ? c1 : ~0ull;
     __builtin_amdgcn_wave_barrier();
     int r0 = 0, r1 = 0;
-    for (int j = 0; j < 2 * WAVE; j++) {
-        uint64_t o = kept[j];
+    for (int j = 0; j < k; j++) {
+        const uint64_t o = kept[j];
+        r0 += o < c0;
+        r1 += o < c1;
+    }
+    for (int j = WAVE; j < WAVE + nrear; j++) {
+        const uint64_t o = kept[j];
         r0 += o < c0;
         r1 += o < c1;
     }
