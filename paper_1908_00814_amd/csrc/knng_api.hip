@@ -80,6 +80,8 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     ia.joint = joint;
     ia.seed = o->seed;
     ia.ctr = w.ctr;
+    ia.tag0 = w.tag0;
+    ia.incremental = w.incremental ? 1 : 0;
     prof.begin(PH_INIT);
     HIP_TRY(launch_init(R, (int)metric, ia, st));
     prof.end();
@@ -96,6 +98,10 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     a.atag = w.atag;
     a.rfill = w.rfill;
     a.ctr = w.ctr;
+    a.rev_off = w.rev_off;
+    a.rev_src = w.rev_src;
+    a.rev_m = w.rev_m;
+    a.tag0 = w.tag0;
     a.n = n;
     a.n1 = n1;
     a.k = k;
@@ -135,7 +141,10 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
         HIP_TRY(launch_zero_counters(w.ctr, C_ROUND_WORDS, st));
         prof.begin(PH_REVERSE);
         HIP_TRY(launch_prep_active(a, st));
-        HIP_TRY(launch_reverse(a, st));
+        if (a.rev_off)
+            HIP_TRY(launch_reverse_indexed(a, st));
+        else
+            HIP_TRY(launch_reverse(a, st));
         prof.end();
         prof.begin(PH_JOIN);
         HIP_TRY(launch_join(R, (int)metric, bf16 ? 1 : 0, a, st));
@@ -157,6 +166,7 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     fa.out_dist = out ? out->dist : nullptr;
     fa.out_keys = out_keys;
     fa.touched = touched_only ? w.dtag : nullptr;
+    fa.tag0 = w.tag0;
     HIP_TRY(launch_final(fa, st));
     prof.end();
     knng_status s = read_ctr(w.ctr, h, st);

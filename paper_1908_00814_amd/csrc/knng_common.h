@@ -276,4 +276,31 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
     return v;
 }
 
+// ---------------------------------------------------------------- row walks
+// Rows are visited wave-strided (row u by wave u mod W), 64 candidate rows at
+// a time: one tag load per lane and a ballot pick the rows to work on.
+#define FOR_TAGGED_ROWS(u, n, tagarr, want)                                                   \
+    const int64_t nwaves_ = (int64_t)gridDim.x * (blockDim.x / WAVE);                        \
+    const int64_t wave0_ = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;          \
+    for (int64_t b_ = wave0_; b_ < (n); b_ += nwaves_ * WAVE)                                 \
+        for (uint64_t todo_ = __ballot(b_ + (int64_t)lane_id() * nwaves_ < (n) &&            \
+                                       (tagarr)[b_ + (int64_t)lane_id() * nwaves_] == (want)); \
+             todo_; todo_ &= todo_ - 1)                                                       \
+            if (const int64_t u = b_ + (int64_t)__builtin_ctzll(todo_) * nwaves_; true)
+
+// The same walk over the rows r < n for which pred(r) holds.
+template <class P>
+__device__ inline uint64_t ballot_rows(int64_t b, int64_t stride, int64_t n, P pred)
+{
+    const int64_t r = b + (int64_t)lane_id() * stride;
+    return __ballot(r < n && pred(r));
+}
+
+#define FOR_ROWS_IF(u, n, pred)                                                               \
+    const int64_t nwaves_ = (int64_t)gridDim.x * (blockDim.x / WAVE);                        \
+    const int64_t wave0_ = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;          \
+    for (int64_t b_ = wave0_; b_ < (n); b_ += nwaves_ * WAVE)                                 \
+        for (uint64_t todo_ = ballot_rows(b_, nwaves_, (n), pred); todo_; todo_ &= todo_ - 1) \
+            if (const int64_t u = b_ + (int64_t)__builtin_ctzll(todo_) * nwaves_; true)
+
 } // namespace knng

@@ -68,6 +68,14 @@ struct Layout {
     uint64_t *gin, *L, *worst, *rnew, *rold;
     int32_t *new_f, *old_f, *cnt_f, *dtag, *atag, *rfill;
     int dp, db, gstride;
+    // reverse index of the base lists (server only; see RoundArgs)
+    const int64_t *rev_off = nullptr;
+    const int32_t *rev_src = nullptr;
+    int64_t rev_m = 0;
+    // tag of the merge's round 0, and whether the state already holds the
+    // initial lists of unselected base rows (server slots; see RoundArgs)
+    int32_t tag0 = 0;
+    bool incremental = false;
 };
 
 inline bool uses_bf16(knng_metric m, const knng_opts *o)

@@ -35,19 +35,31 @@ struct RoundArgs {
     uint64_t *rnew;     // n x s reverse NEW reservoirs
     uint64_t *rold;     // n x s reverse OLD reservoirs
     int32_t *rfill;     // n x 2 offers made to each reservoir (NEW, OLD) this round
-    // Row tags (rounds are numbered from 0; -1 = never):
-    //   dtag[u] = t: u holds NEW entries to sample in round t (set by Divide/
-    //            Append/Initialize for t = 0, by an insert during round t-1,
-    //            or by round t-1's sampling when more than s NEW entries were
-    //            left).  Before round t's join, u is sampled in round t iff
-    //            dtag[u] >= t.
-    //   atag[u] = t: u's round-t neighbourhood has a NEW member (u sampled
+    // Row tags.  Round t of this merge has tag T(t) = tag0 + t (tag0 = 0 for
+    // a merge on fresh state; a server slot starts each merge above every tag
+    // its previous merges wrote, so old tags read as "never"):
+    //   dtag[u] = T(t): u holds NEW entries to sample in round t (set by
+    //            Divide/Append/Initialize for t = 0, by an insert during round
+    //            t-1, or by round t-1's sampling when more than s NEW entries
+    //            were left).  Before round t's join, u is sampled in round t
+    //            iff dtag[u] >= T(t); dtag[u] < tag0 iff u still holds the list
+    //            it started the merge with.
+    //   atag[u] = T(t): u's round-t neighbourhood has a NEW member (u sampled
     //            NEW entries, or a row sampled u as a NEW entry).
     // Rows outside both sets hold only OLD entries: their neighbourhood has no
     // NEW member and joins nothing, and their whole list is their OLD sample.
     int32_t *dtag;
     int32_t *atag;
+    int32_t tag0;
     uint64_t *ctr;      // counter words
+    // Reverse index of the initial lists of rows 0 .. rev_m-1 (or rev_off ==
+    // nullptr): the rows u whose initial list holds v are
+    // rev_src[rev_off[v] .. rev_off[v+1]).  With it, Reverse(G) reads the
+    // lists only of rows with dtag >= 0; every other row still holds its
+    // initial list, all OLD.
+    const int64_t *rev_off;
+    const int32_t *rev_src;
+    int64_t rev_m;
     int64_t n;
     int64_t n1;         // first row of the second set
     int k, s;
@@ -79,8 +91,16 @@ struct InitArgs {
     int balanced;       // J-Merge: balanced append (base rows selected by hash)
     uint64_t seed;
     uint64_t *ctr;
+    int32_t tag0;       // dtag = tag0 for rows holding NEW entries, tag0 - 1 otherwise
+    int incremental;    // only rows >= n1 and selected base rows are written; the
+                        // others already hold their initial state with tags < tag0
 };
 hipError_t launch_init(const Rows &R, int metric, const InitArgs &a, hipStream_t st);
+// Rows u < m with dtag[u] >= since (changed by an earlier merge) get back their
+// initial state as an unselected base row: the first min(kin, k) entries of
+// gin as OLD, the list maximum in worst; their tags stay (below the next tag0).
+hipError_t launch_restore(uint64_t *L, uint64_t *worst, const int32_t *dtag, const uint64_t *gin,
+                          int kin, int k, int64_t m, int32_t since, hipStream_t st);
 // Merge and Sort: list + set-aside rear part -> output rows.  Rows below
 // rows_with_rear have a rear part: gin entries from k1 on (or, for base rows
 // that balanced append leaves unselected, from min(kin, k) on).
@@ -95,8 +115,9 @@ struct FinalArgs {
     int32_t *out_ids;    // n x k, or nullptr
     float *out_dist;     // n x k, or nullptr
     uint64_t *out_keys;  // n x kin sorted keys (may be gin itself), or nullptr
-    const int32_t *touched;  // when set, rows below rows_with_rear with touched[i] < 0
+    const int32_t *touched;  // when set, rows below rows_with_rear with touched[i] < tag0
                              // (never held a NEW entry) are left out
+    int32_t tag0;
 };
 hipError_t launch_final(const FinalArgs &a, hipStream_t st);
 
@@ -109,7 +130,8 @@ hipError_t launch_final(const FinalArgs &a, hipStream_t st);
 struct CommitArgs {
     const uint64_t *out;     // (m_base + n_req) x gs final keys of the request
     int gs, k;
-    const int32_t *touched;  // dtag of the request's merge
+    const int32_t *touched;  // dtag of the request's merge (rows below tag0 untouched)
+    int32_t tag0;
     int64_t m_base, n_req, first;
     uint64_t *res;           // resident lists, k per row
     uint64_t *ctr;
@@ -127,6 +149,15 @@ hipError_t launch_zero_counters(uint64_t *ctr, int words, hipStream_t st);
 hipError_t launch_sample(const RoundArgs &a, hipStream_t st);
 hipError_t launch_prep_active(const RoundArgs &a, hipStream_t st);
 hipError_t launch_reverse(const RoundArgs &a, hipStream_t st);
+hipError_t launch_reverse_indexed(const RoundArgs &a, hipStream_t st);
+// Reverse index of the first kk entries of each of the m lists of gin (row
+// stride gs): off (m+1 words), src (up to m*kk), deg (m words) and part
+// (rindex_parts(m) words) are caller-provided scratch/outputs; an id outside
+// [0, m) sets ERR_ROW_REVERSE in ctr.
+int64_t rindex_parts(int64_t m);
+hipError_t launch_build_rindex(const uint64_t *gin, int gs, int kk, int64_t m, int64_t *off,
+                               int32_t *src, int32_t *deg, int64_t *part, uint64_t *ctr,
+                               hipStream_t st);
 hipError_t launch_count_fresh(const RoundArgs &a, hipStream_t st);
 
 // ---- knng_join.hip

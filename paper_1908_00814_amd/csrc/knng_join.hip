@@ -288,7 +288,7 @@ __device__ __forceinline__ void insert_into(const RoundArgs &a, int64_t dst, uin
     // dst and the key's id are neighbourhood members, range-checked when the
     // neighbourhood was formed
     if (bounded_insert<KB>(a.L + dst * a.k, a.k, key, true, a.worst + dst, a.ctr + C_ERR))
-        a.dtag[dst] = a.round + 1;
+        a.dtag[dst] = a.tag0 + a.round + 1;
 }
 
 // Drain a queue of (target row, key) words: every entry is offered to its
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, MU == 8 ? 3 : 2) void k_join(Row
     // rows wave0 + j*nwaves, 64 at a time; only rows with a NEW member join
     for (int64_t b = wave0; b < a.n; b += nwaves * WAVE) {
         const int64_t r = b + (int64_t)lane * nwaves;
-        uint64_t todo = __ballot(r < a.n && a.atag[r] == a.round);
+        uint64_t todo = __ballot(r < a.n && a.atag[r] == a.tag0 + a.round);
         while (todo) {
         const int64_t u = b + (int64_t)__builtin_ctzll(todo) * nwaves;
         todo &= todo - 1;
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
     // rows wave0 + j*nwaves, 64 at a time; only rows with a NEW member join
     for (int64_t b = wave0; b < a.n; b += nwaves * WAVE) {
         const int64_t r = b + (int64_t)lane * nwaves;
-        uint64_t todo = __ballot(r < a.n && a.atag[r] == a.round);
+        uint64_t todo = __ballot(r < a.n && a.atag[r] == a.tag0 + a.round);
         while (todo) {
         const int64_t u = b + (int64_t)__builtin_ctzll(todo) * nwaves;
         todo &= todo - 1;

@@ -174,11 +174,9 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
     const int lane = lane_id();
     const int w = threadIdx.x / WAVE;
     int32_t *picked = picked_all[w];
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     uint64_t evals = 0;
     int n0 = 0;
-    for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE; i < a.n;
-         i += nwaves) {
+    auto init_row = [&](const int64_t i) {
     __builtin_amdgcn_wave_barrier();
     const bool has_list = !a.joint || i < a.n1;
     int first, m;
@@ -284,12 +282,24 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
     const uint64_t wv = wave_max_u64(key_empty(key) ? key : key_strip(key));
     if (lane == 0) {
         a.worst[i] = wv;
-        a.dtag[i] = m > 0 ? 0 : -1;
-        a.atag[i] = -1;
+        a.dtag[i] = m > 0 ? a.tag0 : a.tag0 - 1;
+        a.atag[i] = a.tag0 - 1;
     }
     evals += (uint64_t)m;
     n0 += m > 0;
     __builtin_amdgcn_wave_barrier();
+    };
+    if (!a.incremental) {
+        const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+        for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE; i < a.n;
+             i += nwaves)
+            init_row(i);
+    } else {
+        // unselected base rows already hold their initial state
+        FOR_ROWS_IF(i, a.n, [&](int64_t r) {
+            return r >= a.n1 || selected_base_row(a.seed, a.balanced, r, a.n1, a.n - a.n1);
+        })
+        init_row(i);
     }
     // one atomic per wave for the distance evaluations of all its rows
     if (lane == 0 && evals)
@@ -298,27 +308,19 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
         atomicAdd((unsigned long long *)(a.ctr + C_N0), (unsigned long long)n0);
 }
 
-// one wave per row: top k of the list and the rear part, deduplicated
-__global__ __launch_bounds__(256) void k_final(FinalArgs a)
+// top k of row i's list and its rear part, deduplicated (one wave; cand and
+// kept are the wave's 2 x 64 words of LDS)
+__device__ inline void final_row(const FinalArgs &a, const int64_t i, uint64_t *cand,
+                                 uint64_t *kept)
 {
     const uint64_t *__restrict__ L = a.L;
     const uint64_t *gin = a.gin;
     const int k = a.k, kin = a.kin;
-    const int64_t n = a.n;
     int32_t *out_ids = a.out_ids;
     float *out_dist = a.out_dist;
     uint64_t *out_keys = a.out_keys;  // may alias gin: row i is read before it is written
-    __shared__ uint64_t cand_all[4][2 * WAVE];
-    __shared__ uint64_t kept_all[4][2 * WAVE];
     const int lane = lane_id();
-    const int w = threadIdx.x / WAVE;
-    uint64_t *cand = cand_all[w];
-    uint64_t *kept = kept_all[w];
-    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
-    if (i >= n)
-        return;
-    if (a.touched && i < a.rows_with_rear && a.touched[i] < 0)
-        return;
+    __builtin_amdgcn_wave_barrier();  // the previous row's reads of cand / kept are done
     int rear0 = a.k1;
     if (!selected_base_row(a.seed, a.balanced, i, a.rows_with_rear, a.n_raw))
         rear0 = kin < k ? kin : k;
@@ -388,23 +390,38 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a)
     }
 }
 
-// one wave per row: commit of one request into the resident lists
+// one wave per row; with a.touched, a wave-strided walk over the rows that
+// held a NEW entry and the rows without a rear part
+__global__ __launch_bounds__(256) void k_final(FinalArgs a)
+{
+    __shared__ uint64_t cand_all[4][2 * WAVE];
+    __shared__ uint64_t kept_all[4][2 * WAVE];
+    const int w = threadIdx.x / WAVE;
+    uint64_t *cand = cand_all[w];
+    uint64_t *kept = kept_all[w];
+    if (a.touched) {
+        const int32_t *touched = a.touched;
+        FOR_ROWS_IF(i, a.n, [&](int64_t r) {
+            return r >= a.rows_with_rear || touched[r] >= a.tag0;
+        })
+        final_row(a, i, cand, kept);
+        return;
+    }
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    if (i < a.n)
+        final_row(a, i, cand, kept);
+}
+
+// commit of row i of one request into the resident lists (one wave)
 template <int KB>
-__global__ __launch_bounds__(256) void k_commit(CommitArgs a)
+__device__ inline void commit_row(const CommitArgs &a, const int64_t i)
 {
     const int lane = lane_id();
-    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
-    if (i >= a.m_base + a.n_req)
-        return;
     const uint64_t e = lane < a.k ? a.out[i * a.gs + lane] : ~0ull;
     const bool real = lane < a.k && !key_empty(e);
     const uint32_t id = key_id(e);
     const uint32_t gid = id < a.m_base ? id : (uint32_t)(a.first + (id - a.m_base));
     const uint64_t ge = make_key(key_dist(e), gid, 0);
-    // rows of the base that never held a NEW entry were not written by the
-    // merge's Merge and Sort and are skipped before their entries are read
-    if (i < a.m_base && a.touched[i] < 0)
-        return;
     if (real && id >= a.m_base + a.n_req) {
         raise_err(a.ctr + C_ERR, ERR_ROW_COMMIT);
         return;
@@ -415,6 +432,44 @@ __global__ __launch_bounds__(256) void k_commit(CommitArgs a)
         bounded_insert<KB>(a.res + i * a.k, a.k, ge, true, nullptr, a.ctr + C_ERR);
     } else if (lane < a.k) {
         a.res[(a.first + (i - a.m_base)) * a.k + lane] = real ? ge : empty_key(lane);
+    }
+}
+
+// Rows of the base that never held a NEW entry were not written by the
+// merge's Merge and Sort and are skipped before their entries are read: a
+// wave-strided walk over the touched base rows and the request's rows.
+template <int KB>
+__global__ __launch_bounds__(256) void k_commit(CommitArgs a)
+{
+    const int32_t *touched = a.touched;
+    FOR_ROWS_IF(i, a.m_base + a.n_req, [&](int64_t r) {
+        return r >= a.m_base || touched[r] >= a.tag0;
+    })
+    commit_row<KB>(a, i);
+}
+
+// Restore of the rows an earlier merge changed (see launch_restore)
+__global__ __launch_bounds__(256) void k_restore(uint64_t *L, uint64_t *worst, const int32_t *dtag,
+                                                 const uint64_t *gin, int kin, int k, int64_t m,
+                                                 int32_t since)
+{
+    const int lane = lane_id();
+    const int first = kin < k ? kin : k;
+    FOR_ROWS_IF(u, m, [&](int64_t r) { return dtag[r] >= since; })
+    {
+        uint64_t key = 0;
+        if (lane < k) {
+            if (lane < first) {
+                key = gin[u * kin + lane];
+                key = key_empty(key) ? empty_key(lane) : key_strip(key);
+            } else {
+                key = empty_key(lane);
+            }
+            L[u * k + lane] = key;
+        }
+        const uint64_t wv = wave_max_u64(key_empty(key) ? key : key_strip(key));
+        if (lane == 0)
+            worst[u] = wv;
     }
 }
 
@@ -519,7 +574,21 @@ hipError_t launch_init(const Rows &R, int metric, const InitArgs &a, hipStream_t
 
 hipError_t launch_final(const FinalArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_final, dim3(grid_for(a.n, 4)), dim3(256), 0, st, a);
+    unsigned g = grid_for(a.n, 4);
+    if (a.touched && g > 8192u)
+        g = 8192u;
+    hipLaunchKernelGGL(k_final, dim3(g), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_restore(uint64_t *L, uint64_t *worst, const int32_t *dtag, const uint64_t *gin,
+                          int kin, int k, int64_t m, int32_t since, hipStream_t st)
+{
+    if (m <= 0)
+        return hipSuccess;
+    unsigned g = grid_for(m, 4);
+    hipLaunchKernelGGL(k_restore, dim3(g > 8192u ? 8192u : g), dim3(256), 0, st, L, worst, dtag,
+                       gin, kin, k, m, since);
     return hipGetLastError();
 }
 
@@ -528,7 +597,8 @@ hipError_t launch_commit(const CommitArgs &a, hipStream_t st)
     const int64_t rows = a.m_base + a.n_req;
     if (rows <= 0)
         return hipSuccess;
-    dim3 grid(grid_for(rows, 4)), block(256);
+    unsigned g = grid_for(rows, 4);
+    dim3 grid(g > 8192u ? 8192u : g), block(256);
     if (a.k <= 16)
         hipLaunchKernelGGL(k_commit<16>, grid, block, 0, st, a);
     else if (a.k <= 32)

@@ -15,17 +15,6 @@ namespace knng {
 
 namespace {
 
-// Rows are visited wave-strided (row u by wave u mod W), 64 candidate rows at
-// a time: one tag load per lane and a ballot pick the rows to work on.
-#define FOR_TAGGED_ROWS(u, n, tagarr, want)                                                   \
-    const int64_t nwaves_ = (int64_t)gridDim.x * (blockDim.x / WAVE);                        \
-    const int64_t wave0_ = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;          \
-    for (int64_t b_ = wave0_; b_ < (n); b_ += nwaves_ * WAVE)                                 \
-        for (uint64_t todo_ = __ballot(b_ + (int64_t)lane_id() * nwaves_ < (n) &&            \
-                                       (tagarr)[b_ + (int64_t)lane_id() * nwaves_] == (want)); \
-             todo_; todo_ &= todo_ - 1)                                                       \
-            if (const int64_t u = b_ + (int64_t)__builtin_ctzll(todo_) * nwaves_; true)
-
 // Forward sample of round t over the rows holding NEW entries (dtag == t), one
 // wave per row (k <= 64 lanes).  Marks u and every sampled NEW entry as
 // active in round t; a row left with more than s NEW entries is sampled
@@ -33,8 +22,9 @@ namespace {
 __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
 {
     const int lane = lane_id();
+    const int32_t tr = a.tag0 + a.round;
     int fresh_total = 0;
-    FOR_TAGGED_ROWS(u, a.n, a.dtag, a.round)
+    FOR_TAGGED_ROWS(u, a.n, a.dtag, tr)
     {
         const bool act = lane < a.k;
         uint64_t v = act ? a.L[u * a.k + lane] : ~0ull;
@@ -60,7 +50,7 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
         if (sampled) {
             a.new_f[u * a.s + rank] = (int32_t)id;
             if (id < a.n)
-                a.atag[id] = a.round;
+                a.atag[id] = tr;
             else
                 raise_err(a.ctr + C_ERR, ERR_ROW_SAMPLE);
         }
@@ -81,9 +71,9 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
             a.cnt_f[2 * u] = nnew < a.s ? nnew : a.s;
             a.cnt_f[2 * u + 1] = __popcll(om);
             if (nnew > 0)
-                a.atag[u] = a.round;
+                a.atag[u] = tr;
             if (nnew > a.s)
-                a.dtag[u] = a.round + 1;
+                a.dtag[u] = tr + 1;
         }
     }
     if (lane == 0 && fresh_total)
@@ -95,7 +85,8 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
 __global__ __launch_bounds__(256) void k_prep_active(RoundArgs a)
 {
     const int lane = lane_id();
-    FOR_TAGGED_ROWS(u, a.n, a.atag, a.round)
+    const int32_t tr = a.tag0 + a.round;
+    FOR_TAGGED_ROWS(u, a.n, a.atag, tr)
     {
         if (lane < a.s) {
             a.rnew[u * a.s + lane] = empty_key(lane);
@@ -103,7 +94,7 @@ __global__ __launch_bounds__(256) void k_prep_active(RoundArgs a)
         }
         if (lane < 2)
             a.rfill[2 * u + lane] = 0;
-        if (a.dtag[u] < a.round) {
+        if (a.dtag[u] < tr) {
             const uint64_t v = lane < a.k ? a.L[u * a.k + lane] : ~0ull;
             const bool has = lane < a.k && !key_empty(v);
             const uint64_t m = __ballot(has);
@@ -117,6 +108,23 @@ __global__ __launch_bounds__(256) void k_prep_active(RoundArgs a)
     }
 }
 
+// u offered to v's reverse reservoir of one kind (0: NEW, 1: OLD), which
+// keeps the s offers of smallest hash priority.  The first s offers take a
+// slot of their own (every slot change is a compare-and-swap to a smaller
+// word, as in bounded_insert, so a slot that a competing insert has taken
+// sends this offer the long way).
+__device__ inline void offer_reverse(const RoundArgs &a, int64_t v, int64_t u, int kind)
+{
+    const uint64_t h = hash5(a.seed, kind ? TAG_ROLD : TAG_RNEW, (uint64_t)a.round, (uint64_t)v,
+                             (uint64_t)u);
+    const uint64_t key = ((h >> 32) << 32) | (uint64_t)u;
+    uint64_t *slots = (kind ? a.rold : a.rnew) + v * a.s;
+    const int pos = atomicAdd(a.rfill + 2 * v + kind, 1);
+    if (pos < a.s && cas64(slots + pos, empty_key(pos), key))
+        return;
+    bounded_insert<MAX_S>(slots, a.s, key, false, nullptr, a.ctr + C_ERR);
+}
+
 // Reverse(G) of round t, one thread per (row u, slot): a sampled edge u -> v
 // offers u to v's reverse list of its kind.  NEW edges come from the rows
 // sampled this round (their targets are active by construction); OLD edges
@@ -127,14 +135,13 @@ __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
 {
     const int per = a.s + a.k;
     const int64_t total = a.n * per;
+    const int32_t tr = a.tag0 + a.round;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         int64_t u = e / per;
         int j = (int)(e - u * per);
-        const bool sampled = a.dtag[u] >= a.round;
+        const bool sampled = a.dtag[u] >= tr;
         int32_t v;
-        uint32_t tag;
-        uint64_t *res;
         int kind;
         if (j < a.s) {
             if (!sampled || j >= a.cnt_f[2 * u])
@@ -144,8 +151,6 @@ __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
                 raise_err(a.ctr + C_ERR, ERR_ROW_REVERSE);
                 continue;
             }
-            tag = TAG_RNEW;
-            res = a.rnew;
             kind = 0;
         } else {
             j -= a.s;
@@ -163,22 +168,242 @@ __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
                 raise_err(a.ctr + C_ERR, ERR_ROW_REVERSE);
                 continue;
             }
-            if (a.atag[v] != a.round)
+            if (a.atag[v] != tr)
                 continue;
-            tag = TAG_ROLD;
-            res = a.rold;
             kind = 1;
         }
-        uint64_t h = hash5(a.seed, tag, (uint64_t)a.round, (uint64_t)v, (uint64_t)u);
-        uint64_t key = ((h >> 32) << 32) | (uint64_t)u;
-        uint64_t *slots = res + (int64_t)v * a.s;
-        // the first s offers take a slot of their own (every slot change is a
-        // compare-and-swap to a smaller word, as in bounded_insert, so a slot
-        // that a competing insert has taken sends this offer the long way)
-        const int pos = atomicAdd(a.rfill + 2 * (int64_t)v + kind, 1);
-        if (pos < a.s && cas64(slots + pos, empty_key(pos), key))
+        offer_reverse(a, v, u, kind);
+    }
+}
+
+// Reverse(G) with a reverse index of the initial lists, part 1: the rows that
+// may differ from their initial list (dtag >= tag0: rows with appended or
+// initialised entries, and every row an insert has reached), one wave per
+// row, edges as in k_reverse.
+__global__ __launch_bounds__(256) void k_reverse_rows(RoundArgs a)
+{
+    const int lane = lane_id();
+    const int32_t *dtag = a.dtag;
+    const int32_t tag0 = a.tag0, tr = a.tag0 + a.round;
+    FOR_ROWS_IF(u, a.n, [&](int64_t r) { return dtag[r] >= tag0; })
+    {
+        const bool sampled = dtag[u] >= tr;
+        const int nn = sampled ? a.cnt_f[2 * u] : 0;
+        const int no = sampled ? a.cnt_f[2 * u + 1] : a.k;
+        for (int j = lane; j < nn; j += WAVE) {
+            const int32_t v = a.new_f[u * a.s + j];
+            if (v < 0 || v >= a.n)
+                raise_err(a.ctr + C_ERR, ERR_ROW_REVERSE);
+            else
+                offer_reverse(a, v, u, 0);
+        }
+        for (int j = lane; j < no; j += WAVE) {
+            int32_t v;
+            if (sampled) {
+                v = a.old_f[u * a.k + j];
+            } else {
+                const uint64_t w = a.L[u * a.k + j];
+                if (key_empty(w))
+                    continue;
+                v = (int32_t)key_id(w);
+            }
+            if (v < 0 || v >= a.n)
+                raise_err(a.ctr + C_ERR, ERR_ROW_REVERSE);
+            else if (a.atag[v] == tr)
+                offer_reverse(a, v, u, 1);
+        }
+    }
+}
+
+// Part 2, launched first: rows that still hold their initial list (dtag < tag0,
+// never sampled, all entries OLD) offer themselves to the active targets their
+// list holds, found through the index.  One wave per active target v < rev_m
+// is the only writer of v's OLD reservoir while this kernel runs (k_prep_active
+// has just emptied it), so the wave keeps the s offers of smallest priority
+// itself and stores them, with no atomics; rfill counts every offer made, so
+// that part 1's offers that follow take free slots or go through
+// bounded_insert as before.
+__global__ __launch_bounds__(256) void k_reverse_base(RoundArgs a)
+{
+    __shared__ uint64_t keep_all[256 / WAVE][MAX_S];
+    const int lane = lane_id();
+    uint64_t *keep = keep_all[threadIdx.x / WAVE];
+    const int32_t tr = a.tag0 + a.round;
+    FOR_TAGGED_ROWS(v, a.rev_m, a.atag, tr)
+    {
+        const int64_t lo = a.rev_off[v], hi = a.rev_off[v + 1];
+        uint64_t best = ~0ull;  // lane j < nkept: the offer of rank j so far
+        int nkept = 0, offers = 0;
+        for (int64_t b = lo; b < hi; b += WAVE) {
+            const int64_t i = b + lane;
+            uint64_t key = ~0ull;
+            if (i < hi) {
+                const int32_t u = a.rev_src[i];
+                if (u < 0 || u >= a.rev_m) {
+                    raise_err(a.ctr + C_ERR, ERR_ROW_REVERSE);
+                } else if (a.dtag[u] < a.tag0) {
+                    const uint64_t h = hash5(a.seed, TAG_ROLD, (uint64_t)a.round, (uint64_t)v,
+                                             (uint64_t)u);
+                    key = ((h >> 32) << 32) | (uint64_t)u;
+                }
+            }
+            const uint64_t has = __ballot(key != ~0ull);
+            offers += __popcll(has);
+            const uint64_t thr = nkept == a.s ? __shfl(best, a.s - 1, WAVE) : ~0ull;
+            if (!__ballot(key < thr))
+                continue;
+            // ranks in the union of the kept offers and this chunk's (all
+            // distinct: the sources of one target are distinct rows)
+            int rk = 0, rb = 0;
+            for (int j = 0; j < WAVE; j++) {
+                const uint64_t o = __shfl(key, j, WAVE);
+                rk += o < key;
+                rb += o < best;
+            }
+            for (int j = 0; j < nkept; j++) {
+                const uint64_t o = __shfl(best, j, WAVE);
+                rk += o < key;
+                rb += o < best;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nkept && rb < a.s)
+                keep[rb] = best;
+            if (key != ~0ull && rk < a.s)
+                keep[rk] = key;
+            __builtin_amdgcn_wave_barrier();
+            nkept = nkept + __popcll(has) < a.s ? nkept + __popcll(has) : a.s;
+            best = lane < nkept ? keep[lane] : ~0ull;
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (offers) {
+            if (lane < nkept)
+                a.rold[v * a.s + lane] = best;
+            if (lane == 0)
+                a.rfill[2 * v + 1] = offers;
+        }
+    }
+}
+
+// ------------------------------------------------ reverse index construction
+
+constexpr int RI_PER_THREAD = 8, RI_CHUNK = 256 * RI_PER_THREAD;
+
+__global__ __launch_bounds__(256) void k_ri_fill_zero(int32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// in-degree of every row over the first kk entries of the m lists
+__global__ __launch_bounds__(256) void k_ri_count(const uint64_t *gin, int gs, int kk, int64_t m,
+                                                  int32_t *deg, uint64_t *ctr)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m * kk;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = e / kk;
+        const uint64_t w = gin[u * gs + (e - u * kk)];
+        if (key_empty(w))
             continue;
-        bounded_insert<MAX_S>(slots, a.s, key, false, nullptr, a.ctr + C_ERR);
+        const int64_t v = (int64_t)key_id(w);
+        if (v >= m)
+            raise_err(ctr + C_ERR, ERR_ROW_REVERSE);
+        else
+            atomicAdd(deg + v, 1);
+    }
+}
+
+// exclusive prefix sum over a 256-thread block; *total gets the block's sum
+__device__ inline int64_t block_exclusive_sum(int64_t x, int64_t *total)
+{
+    __shared__ int64_t wsum[256 / WAVE];
+    const int lane = lane_id(), w = threadIdx.x / WAVE;
+    int64_t inc = x;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int64_t y = __shfl_up(inc, o, WAVE);
+        if (lane >= o)
+            inc += y;
+    }
+    if (lane == WAVE - 1)
+        wsum[w] = inc;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+    for (int q = 0; q < 256 / WAVE; q++) {
+        before += q < w ? wsum[q] : 0;
+        all += wsum[q];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - x;
+}
+
+// sum of each RI_CHUNK-row chunk of deg
+__global__ __launch_bounds__(256) void k_ri_chunk_sums(const int32_t *deg, int64_t m, int64_t *part)
+{
+    const int64_t r0 = (int64_t)blockIdx.x * RI_CHUNK + (int64_t)threadIdx.x * RI_PER_THREAD;
+    int64_t x = 0;
+    for (int q = 0; q < RI_PER_THREAD; q++)
+        x += r0 + q < m ? deg[r0 + q] : 0;
+    int64_t tot;
+    (void)block_exclusive_sum(x, &tot);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = tot;
+}
+
+// exclusive prefix sum of the chunk sums (one block)
+__global__ __launch_bounds__(256) void k_ri_scan_parts(int64_t *part, int64_t nparts)
+{
+    int64_t carry = 0;
+    for (int64_t b = 0; b < nparts; b += 256) {
+        const int64_t i = b + threadIdx.x;
+        const int64_t x = i < nparts ? part[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_sum(x, &tot);
+        if (i < nparts)
+            part[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+// off[r] = sum of deg over rows before r (off[m] = all entries); deg is
+// cleared for use as the fill cursor
+__global__ __launch_bounds__(256) void k_ri_offsets(int32_t *deg, int64_t m, const int64_t *part,
+                                                    int64_t *off)
+{
+    const int64_t r0 = (int64_t)blockIdx.x * RI_CHUNK + (int64_t)threadIdx.x * RI_PER_THREAD;
+    int32_t dv[RI_PER_THREAD];
+    int64_t x = 0;
+    for (int q = 0; q < RI_PER_THREAD; q++) {
+        dv[q] = r0 + q < m ? deg[r0 + q] : 0;
+        x += dv[q];
+    }
+    int64_t tot;
+    int64_t run = part[blockIdx.x] + block_exclusive_sum(x, &tot);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        off[0] = 0;
+    for (int q = 0; q < RI_PER_THREAD; q++) {
+        if (r0 + q < m) {
+            run += dv[q];
+            off[r0 + q + 1] = run;
+            deg[r0 + q] = 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ri_fill(const uint64_t *gin, int gs, int kk, int64_t m,
+                                                 const int64_t *off, int32_t *cur, int32_t *src)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m * kk;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = e / kk;
+        const uint64_t w = gin[u * gs + (e - u * kk)];
+        if (key_empty(w))
+            continue;
+        const int64_t v = (int64_t)key_id(w);
+        if (v < m) {
+            const int pos = atomicAdd(cur + v, 1);
+            src[off[v] + pos] = (int32_t)u;
+        }
     }
 }
 
@@ -223,6 +448,35 @@ hipError_t launch_reverse(const RoundArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reverse, dim3(grid_for(a.n * (a.s + a.k), 256, 1u << 20)), dim3(256),
                        0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse_indexed(const RoundArgs &a, hipStream_t st)
+{
+    // base first: it writes the reservoirs of its targets without atomics
+    if (a.rev_m > 0)
+        hipLaunchKernelGGL(k_reverse_base, dim3(grid_for(a.rev_m, 4, 8192)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_reverse_rows, dim3(grid_for(a.n, 4, 8192)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+int64_t rindex_parts(int64_t m) { return (m + RI_CHUNK - 1) / RI_CHUNK; }
+
+hipError_t launch_build_rindex(const uint64_t *gin, int gs, int kk, int64_t m, int64_t *off,
+                               int32_t *src, int32_t *deg, int64_t *part, uint64_t *ctr,
+                               hipStream_t st)
+{
+    if (m <= 0)
+        return hipSuccess;
+    const int64_t parts = rindex_parts(m);
+    hipLaunchKernelGGL(k_ri_fill_zero, dim3(grid_for(m, 256, 16384)), dim3(256), 0, st, deg, m);
+    hipLaunchKernelGGL(k_ri_count, dim3(grid_for(m * kk, 256, 1u << 16)), dim3(256), 0, st, gin,
+                       gs, kk, m, deg, ctr);
+    hipLaunchKernelGGL(k_ri_chunk_sums, dim3((unsigned)parts), dim3(256), 0, st, deg, m, part);
+    hipLaunchKernelGGL(k_ri_scan_parts, dim3(1), dim3(256), 0, st, part, parts);
+    hipLaunchKernelGGL(k_ri_offsets, dim3((unsigned)parts), dim3(256), 0, st, deg, m, part, off);
+    hipLaunchKernelGGL(k_ri_fill, dim3(grid_for(m * kk, 256, 1u << 16)), dim3(256), 0, st, gin,
+                       gs, kk, m, off, deg, src);
     return hipGetLastError();
 }
 

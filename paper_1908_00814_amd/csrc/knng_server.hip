@@ -66,6 +66,12 @@ struct Slot {
     Layout w{};               // per-request merge state; row arrays point at the store
     uint64_t *out = nullptr;  // capacity x gstride final keys of the request
     std::thread th;
+    // Merge state kept between requests: after a merge, only rows it changed
+    // (dtag >= prev_tag0) differ from the initial state of an unselected base
+    // row, and every tag it wrote is below tag0.  fresh: the state must be
+    // initialised in full (first merge, after a rebase or a failed merge).
+    int32_t tag0 = 0, prev_tag0 = 0;
+    bool fresh = true;
 };
 
 } // namespace
@@ -82,6 +88,9 @@ struct knng_server {
     uint64_t *res = nullptr;  // capacity x k resident lists
     float *stage = nullptr;   // max_request x d: host rows on their way in
     uint64_t *sub_ctr = nullptr;
+    // reverse index of the base lists (rebuilt by a rebase)
+    int64_t *ri_off = nullptr, *ri_part = nullptr;
+    int32_t *ri_src = nullptr, *ri_deg = nullptr;
     hipStream_t sub_st = nullptr;
     std::vector<Slot> slots;
     std::chrono::steady_clock::time_point t0;
@@ -120,6 +129,28 @@ void carve_store(Carve &c, knng_server &s)
     s.res = c.take<uint64_t>((size_t)s.capacity * s.k);
     s.stage = c.take<float>((size_t)s.max_request * s.d);
     s.sub_ctr = c.take<uint64_t>(C_WORDS);
+    s.ri_off = c.take<int64_t>((size_t)s.capacity + 1);
+    s.ri_src = c.take<int32_t>((size_t)s.capacity * s.k);
+    s.ri_deg = c.take<int32_t>(s.capacity);
+    s.ri_part = c.take<int64_t>(rindex_parts(s.capacity));
+    w.rev_off = s.ri_off;
+    w.rev_src = s.ri_src;
+}
+
+// the reverse index of the first k entries of the m base lists (those an
+// unselected base row starts a request with)
+knng_status build_rindex(knng_server *s, int64_t m)
+{
+    HIP_TRY(launch_zero_counters(s->sub_ctr, C_WORDS, s->sub_st));
+    HIP_TRY(launch_build_rindex(s->store.gin, s->gstride, s->k, m, s->ri_off, s->ri_src,
+                                s->ri_deg, s->ri_part, s->sub_ctr, s->sub_st));
+    uint64_t h[C_WORDS];
+    knng_status r = read_ctr(s->sub_ctr, h, s->sub_st);
+    if (r != KNNG_OK)
+        return r;
+    if (h[C_ERR])
+        return fail(KNNG_EDEVICE, "reverse index of the base lists: %s", err_text(h[C_ERR]));
+    return KNNG_OK;
 }
 
 // one slot's merge state for a problem of up to `capacity` rows
@@ -201,7 +232,15 @@ knng_status run_request(knng_server *s, Slot &sl, const std::vector<uint64_t> &t
         R.split = m;  // the request's rows m .. m+nr-1 are stored at first ..
         R.off2 = first - m;
         HIP_TRY(launch_zero_counters(sl.w.ctr, C_WORDS, sl.st));
-        knng_status r = run_merge(R, sl.w, s->metric, s->bf16, &o, m + nr, m, s->k,
+        Layout w = sl.w;
+        w.rev_m = m;  // rows 0 .. m-1 start from their base lists unless selected
+        if (!sl.fresh)
+            HIP_TRY(launch_restore(sl.w.L, sl.w.worst, sl.w.dtag, sl.w.gin, s->gstride, s->k, m,
+                                   sl.prev_tag0, sl.st));
+        w.tag0 = sl.tag0;
+        w.incremental = !sl.fresh;
+        sl.fresh = true;  // until this merge ends cleanly
+        knng_status r = run_merge(R, w, s->metric, s->bf16, &o, m + nr, m, s->k,
                                   keep_count(&o, s->k), 1, m, nullptr, sl.st, &st, prof, sl.out,
                                   true);
         if (r != KNNG_OK)
@@ -211,6 +250,7 @@ knng_status run_request(knng_server *s, Slot &sl, const std::vector<uint64_t> &t
         ca.gs = s->gstride;
         ca.k = s->k;
         ca.touched = sl.w.dtag;
+        ca.tag0 = sl.tag0;
         ca.m_base = m;
         ca.n_req = nr;
         ca.first = first;
@@ -225,6 +265,12 @@ knng_status run_request(knng_server *s, Slot &sl, const std::vector<uint64_t> &t
             return r;
         if (h[C_ERR])
             return fail(KNNG_EDEVICE, "%s", err_text(h[C_ERR]));
+        // every tag this merge wrote is below tag0 + rounds + 2
+        sl.prev_tag0 = sl.tag0;
+        sl.tag0 += st.rounds + 2;
+        sl.fresh = sl.tag0 > (1 << 30);
+        if (sl.fresh)
+            sl.tag0 = 0;
         return KNNG_OK;
     }();
     const std::string err = rc == KNNG_OK ? std::string() : g_err;
@@ -430,8 +476,7 @@ knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_
             return r;
         HIP_TRY(launch_sort_rows(s->store.gin, s->gstride, m, k, s->res, k, nullptr, nullptr,
                                  s->sub_st));
-        HIP_TRY(hipStreamSynchronize(s->sub_st));
-        return KNNG_OK;
+        return build_rindex(s, m);
     }();
     if (rc != KNNG_OK) {
         const std::string e = g_err;
@@ -648,7 +693,11 @@ knng_status knng_server_rebase(knng_server *s)
     // the resident graph, sorted, becomes the base lists
     HIP_TRY(launch_sort_rows(s->res, s->k, n, s->k, s->store.gin, s->gstride, nullptr, nullptr,
                              s->sub_st));
-    HIP_TRY(hipStreamSynchronize(s->sub_st));
+    rc = build_rindex(s, n);
+    if (rc != KNNG_OK)
+        return rc;
+    for (Slot &sl : s->slots)
+        sl.fresh = true;  // new base lists: the kept merge state is stale
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->m_base = n;

@@ -182,6 +182,35 @@ def test_rebase_lets_later_requests_meet_earlier_rows(hip):
         srv.close()
 
 
+def test_wide_base_lists_and_a_rebase(hip):
+    # base lists longer than k: a request keeps the first k entries of an
+    # unselected row and returns the rest as its rear part; after a rebase
+    # the base lists are the resident top k
+    k, s, seed = 6, 5, 41
+    base, reqs = _sets(700, [25, 18], 8, 125)
+    m = base.shape[0]
+    G = oracle.exact_graph(base, k + 3)
+    srv = _server(hip, base, G, k, "l2", capacity=760, max_request=32, slots=0, sample=s,
+                  seed=seed)
+    try:
+        t0 = srv.submit(reqs[0], 70)
+        assert srv.step()
+        ids, dist, info = srv.wait(t0, 25)
+        oi, od, _ = _alone(base, G, reqs[0], k, "l2", m, s, seed, 70)
+        assert_same_graph(ids.numpy(), dist.numpy(), oi[m:], od[m:], "wide base")
+        srv.rebase()
+        si, sd = (host(a) for a in srv.snapshot())
+        t1 = srv.submit(reqs[1], 71)
+        assert srv.step()
+        ids, dist, info = srv.wait(t1, 18)
+        X1 = np.concatenate([base, reqs[0]])
+        oi, od, _ = _alone(X1, (si, sd), reqs[1], k, "l2", m + 25, s, seed, 71)
+        assert_same_graph(ids.numpy(), dist.numpy(), oi[m + 25:], od[m + 25:],
+                          "after rebase of a wide base")
+    finally:
+        srv.close()
+
+
 def test_server_errors(hip):
     from paper_1908_00814_amd.knng import KnngError
     k = 6
