@@ -101,7 +101,7 @@ def join_roofline(st, n, d, k, s, prec="fp32"):
     launches = max(st["join_launches"], 1)
     secs = st["ms"]["join"] / 1e3
     achieved = traffic / secs if secs > 0 else 0.0
-    kernel = "k_join<0, 32, 8>" if prec == "fp32" else "k_join_bf16<0, 32>"
+    kernel = "k_join<0, 32, 4>" if prec == "fp32" else "k_join_bf16<0, 32>"
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": measured_traffic(kernel),
             "kernel": kernel,

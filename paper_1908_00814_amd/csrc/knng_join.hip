@@ -50,7 +50,7 @@ namespace knng {
 namespace {
 
 constexpr int JOIN_WAVES = 4;
-constexpr int CH = 16;                  // coordinates per staged chunk
+constexpr int CH = 8;                   // coordinates per staged chunk (FP32 path)
 constexpr int QCAP = 256;               // BF16 path: rescore-queue words per wave
 constexpr int QF = 192;                 // FP32 path: insert-queue entries per wave
 constexpr int TMAX = 4;                 // MFMA tiles held per batch
@@ -68,7 +68,7 @@ struct Regions {
 
 // per-wave LDS carve
 struct WaveLds {
-    float *vecT;     // CH x GS staged coordinates, transposed
+    float *vecT;     // CH x GS staged coordinates, transposed (FP32 path)
     uint64_t *gw;    // GS worst bound of each member's list
     uint64_t *q64;   // QCAP queue words (FP32 path: the QF queued keys)
     int32_t *grp;    // GS member ids (-1 = padding)
@@ -82,23 +82,27 @@ struct WaveLds {
     int32_t *qdst;   // FP32 path: target rows of the QF queued keys
 };
 
-__host__ __device__ inline int wave_lds_bytes(int GS, int s, int k)
+// The FP32 carve (bf = false) leaves out the BF16 arrays and holds QF queue
+// words: 8.3 KB per wave for s = k = 20, so that four 4-wave blocks fit the
+// CU's 160 KB of LDS (4 waves per SIMD).
+__host__ __device__ inline int wave_lds_bytes(int GS, int s, int k, bool bf)
 {
-    int b = CH * GS * 4 + GS * 8 + QCAP * 8 + 4 * GS * 4 + (2 * s + 3 * (k + s) + QF) * 4;
+    int b = bf ? CH * GS * 4 + GS * 8 + QCAP * 8 + 4 * GS * 4 + (2 * s + 3 * (k + s) + QF) * 4
+               : CH * GS * 4 + GS * 8 + QF * 8 + 2 * GS * 4 + (2 * s + 3 * (k + s) + QF) * 4;
     return (b + 15) / 16 * 16;
 }
 
-__device__ inline WaveLds carve_lds(unsigned char *base, int GS, int s, int k)
+__device__ inline WaveLds carve_lds(unsigned char *base, int GS, int s, int k, bool bf)
 {
     WaveLds L;
     L.vecT = reinterpret_cast<float *>(base);
     L.gw = reinterpret_cast<uint64_t *>(base + CH * GS * 4);
     L.q64 = L.gw + GS;
-    L.grp = reinterpret_cast<int32_t *>(L.q64 + QCAP);
+    L.grp = reinterpret_cast<int32_t *>(L.q64 + (bf ? QCAP : QF));
     L.gnorm = reinterpret_cast<float *>(L.grp + GS);
-    L.gsq = L.gnorm + GS;
-    L.gerr = L.gsq + GS;
-    L.tnew = reinterpret_cast<int32_t *>(L.gerr + GS);
+    L.gsq = bf ? L.gnorm + GS : nullptr;
+    L.gerr = bf ? L.gsq + GS : nullptr;
+    L.tnew = reinterpret_cast<int32_t *>(bf ? L.gerr + GS : L.gnorm + GS);
     L.told = L.tnew + 2 * s;
     L.toldA = L.told + (k + s);
     L.toldB = L.toldA + (k + s);
@@ -338,12 +342,12 @@ __device__ inline void flush_counters(const RoundArgs &a, uint64_t pairs_lane, u
 
 // ============================================================ FP32 path
 template <int METRIC, int KB, int MU>
-__global__ __launch_bounds__(JOIN_WAVES * WAVE, MU == 8 ? 3 : 2) void k_join(Rows R, RoundArgs a, int GS,
+__global__ __launch_bounds__(JOIN_WAVES * WAVE, MU == 4 ? 4 : 2) void k_join(Rows R, RoundArgs a, int GS,
                                                             int wave_bytes)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     const int lane = lane_id();
-    const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS, a.s, a.k);
+    const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS, a.s, a.k, false);
     // the insert queue lives across tiles and rows: it is drained in whole
     // 64-entry steps when it runs full, and once more at the end
     uint64_t *qkey = L.q64;
@@ -527,7 +531,7 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     const int lane = lane_id();
-    const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS, a.s, a.k);
+    const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS, a.s, a.k, true);
     // queue word: slot r | slot c << 8 | (p gets q) << 16 | (q gets p) << 17 in
     // the low half, the screening distance's bits in the high half
     uint64_t *qw = L.q64;
@@ -699,12 +703,13 @@ hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, 
     // the BF16 tiles read 16 slots past a region start (+16); +4 spreads banks
     const int g_max = 3 * a.s + a.k;
     const int GS = r4(g_max) + 12 + 16 + 4;
-    const int wave_bytes = wave_lds_bytes(GS, a.s, a.k);
+    const bool use_bf = bf16 && metric != M_L1;
+    const int wave_bytes = wave_lds_bytes(GS, a.s, a.k, use_bf);
     const size_t shmem = (size_t)wave_bytes * JOIN_WAVES;
     const int units = GS * (CH / 4);
-    if (units > 12 * WAVE)
+    if (units > 8 * WAVE)
         return hipErrorInvalidValue;  // neighbourhood larger than the staging bound
-    const bool small = units <= 8 * WAVE;
+    const bool small = units <= 4 * WAVE;
     const int64_t waves = a.n < 32768 ? a.n : 32768;
     int64_t grid = (waves + JOIN_WAVES - 1) / JOIN_WAVES;
     if (grid < 1)
@@ -736,11 +741,11 @@ hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, 
             e = small ? KNNG_BF16_SET(64, 8) : KNNG_BF16_SET(64, 12);
     } else {
         if (a.k <= 16)
-            e = small ? KNNG_FP32_SET(16, 8) : KNNG_FP32_SET(16, 12);
+            e = small ? KNNG_FP32_SET(16, 4) : KNNG_FP32_SET(16, 8);
         else if (a.k <= 32)
-            e = small ? KNNG_FP32_SET(32, 8) : KNNG_FP32_SET(32, 12);
+            e = small ? KNNG_FP32_SET(32, 4) : KNNG_FP32_SET(32, 8);
         else
-            e = small ? KNNG_FP32_SET(64, 8) : KNNG_FP32_SET(64, 12);
+            e = small ? KNNG_FP32_SET(64, 4) : KNNG_FP32_SET(64, 8);
     }
 #undef KNNG_FP32_SET
 #undef KNNG_BF16_SET
