@@ -102,6 +102,8 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     a.rev_src = w.rev_src;
     a.rev_m = w.rev_m;
     a.tag0 = w.tag0;
+    a.alist = w.alist;
+    a.n_active = 0;
     a.n = n;
     a.n1 = n1;
     a.k = k;
@@ -119,12 +121,15 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
         else
             HIP_TRY(launch_count_fresh(a, st));
         prof.end();
-        if (t > 0) {
+        if (t > 0 || a.alist) {
             knng_status s = read_ctr(w.ctr, h, st);
             if (s != KNNG_OK)
                 return s;
             if (h[C_ERR])
                 return fail(KNNG_EDEVICE, "%s", err_text(h[C_ERR]));
+            a.n_active = (int64_t)h[C_ACTIVE];  // list mode: the round's active rows
+        }
+        if (t > 0) {
             if (stats && t - 1 < KNNG_STATS_ROUNDS) {
                 stats->updates[t - 1] = (int64_t)h[C_FRESH];
                 stats->pairs[t - 1] = (int64_t)h[C_PAIRS];

@@ -46,16 +46,17 @@ enum : int {
     C_FRESH = 0,    // entries inserted during the last round and still present
     C_PAIRS = 1,    // joined pairs this round
     C_GATHER = 2,   // neighbourhood members staged this round
-    C_ROUND_WORDS = 3,
+    C_ACTIVE = 3,   // rows appended to the round's active list (list mode)
+    C_ROUND_WORDS = 4,
     // whole-call words
-    C_EVALS = 3,    // distance evaluations (scanning-rate numerator)
-    C_RESCORE = 4,  // pairs rescored in FP32 (BF16 path)
-    C_MAXG = 5,     // largest neighbourhood (max)
-    C_ERR = 6,      // error bits
-    C_ATTEMPT = 7,  // list inserts attempted after the screen
-    C_VIOL = 8,     // BF16 path: rescored pairs outside the screening margin
-    C_N0 = 9,       // rows holding a NEW entry when the loop starts
-    C_WORDS = 10,
+    C_EVALS = 4,    // distance evaluations (scanning-rate numerator)
+    C_RESCORE = 5,  // pairs rescored in FP32 (BF16 path)
+    C_MAXG = 6,     // largest neighbourhood (max)
+    C_ERR = 7,      // error bits
+    C_ATTEMPT = 8,  // list inserts attempted after the screen
+    C_VIOL = 9,     // BF16 path: rescored pairs outside the screening margin
+    C_N0 = 10,       // rows holding a NEW entry when the loop starts
+    C_WORDS = 11,
 };
 
 // ---------------------------------------------------------------- keys
@@ -302,5 +303,13 @@ __device__ inline uint64_t ballot_rows(int64_t b, int64_t stride, int64_t n, P p
     for (int64_t b_ = wave0_; b_ < (n); b_ += nwaves_ * WAVE)                                 \
         for (uint64_t todo_ = ballot_rows(b_, nwaves_, (n), pred); todo_; todo_ &= todo_ - 1) \
             if (const int64_t u = b_ + (int64_t)__builtin_ctzll(todo_) * nwaves_; true)
+
+// Rows active in round tag tr: from the round's active list when there is one
+// (a.alist, a.n_active entries), else by a walk over a.atag.
+#define FOR_ACTIVE_ROWS(u, a, tr)                                                              \
+    const bool listed_ = (a).alist != nullptr;                                                 \
+    const int64_t span_ = listed_ ? (a).n_active : (a).n;                                      \
+    FOR_ROWS_IF(j_, span_, [&](int64_t r) { return listed_ || (a).atag[r] == (tr); })          \
+    if (const int64_t u = listed_ ? (int64_t)(a).alist[j_] : j_; true)
 
 } // namespace knng

@@ -76,6 +76,7 @@ struct Layout {
     // initial lists of unselected base rows (server slots; see RoundArgs)
     int32_t tag0 = 0;
     bool incremental = false;
+    int32_t *alist = nullptr;  // n words: the round's active rows (list mode)
 };
 
 inline bool uses_bf16(knng_metric m, const knng_opts *o)

@@ -51,6 +51,12 @@ struct RoundArgs {
     int32_t *dtag;
     int32_t *atag;
     int32_t tag0;
+    // List mode (alist != nullptr): the sampling step also appends every row it
+    // makes active to alist (each row once per round, counted in C_ACTIVE),
+    // and the active-row kernels of the round take their n_active rows from
+    // there instead of walking atag over all n rows.
+    int32_t *alist;
+    int64_t n_active;
     uint64_t *ctr;      // counter words
     // Reverse index of the initial lists of rows 0 .. rev_m-1 (or rev_off ==
     // nullptr): the rows u whose initial list holds v are

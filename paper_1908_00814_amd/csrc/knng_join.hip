@@ -358,12 +358,16 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, MU == 4 ? 4 : 2) void k_join(Row
     int maxg = 0;
     const int64_t nwaves = (int64_t)gridDim.x * JOIN_WAVES;
     const int64_t wave0 = (int64_t)blockIdx.x * JOIN_WAVES + threadIdx.x / WAVE;
-    // rows wave0 + j*nwaves, 64 at a time; only rows with a NEW member join
-    for (int64_t b = wave0; b < a.n; b += nwaves * WAVE) {
+    // rows (or active-list entries) wave0 + j*nwaves, 64 at a time; only rows
+    // with a NEW member join
+    const bool listed = a.alist != nullptr;
+    const int64_t span = listed ? a.n_active : a.n;
+    for (int64_t b = wave0; b < span; b += nwaves * WAVE) {
         const int64_t r = b + (int64_t)lane * nwaves;
-        uint64_t todo = __ballot(r < a.n && a.atag[r] == a.tag0 + a.round);
+        uint64_t todo = __ballot(r < span && (listed || a.atag[r] == a.tag0 + a.round));
         while (todo) {
-        const int64_t u = b + (int64_t)__builtin_ctzll(todo) * nwaves;
+        const int64_t j = b + (int64_t)__builtin_ctzll(todo) * nwaves;
+        const int64_t u = listed ? (int64_t)a.alist[j] : j;
         todo &= todo - 1;
         __builtin_amdgcn_wave_barrier();
         Regions g;
@@ -543,12 +547,16 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE) void k_join_bf16(Rows R, RoundAr
     int maxg = 0;
     const int64_t nwaves = (int64_t)gridDim.x * JOIN_WAVES;
     const int64_t wave0 = (int64_t)blockIdx.x * JOIN_WAVES + threadIdx.x / WAVE;
-    // rows wave0 + j*nwaves, 64 at a time; only rows with a NEW member join
-    for (int64_t b = wave0; b < a.n; b += nwaves * WAVE) {
+    // rows (or active-list entries) wave0 + j*nwaves, 64 at a time; only rows
+    // with a NEW member join
+    const bool listed = a.alist != nullptr;
+    const int64_t span = listed ? a.n_active : a.n;
+    for (int64_t b = wave0; b < span; b += nwaves * WAVE) {
         const int64_t r = b + (int64_t)lane * nwaves;
-        uint64_t todo = __ballot(r < a.n && a.atag[r] == a.tag0 + a.round);
+        uint64_t todo = __ballot(r < span && (listed || a.atag[r] == a.tag0 + a.round));
         while (todo) {
-        const int64_t u = b + (int64_t)__builtin_ctzll(todo) * nwaves;
+        const int64_t j = b + (int64_t)__builtin_ctzll(todo) * nwaves;
+        const int64_t u = listed ? (int64_t)a.alist[j] : j;
         todo &= todo - 1;
         __builtin_amdgcn_wave_barrier();
         Regions g;
@@ -710,7 +718,8 @@ hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, 
     if (units > 8 * WAVE)
         return hipErrorInvalidValue;  // neighbourhood larger than the staging bound
     const bool small = units <= 4 * WAVE;
-    const int64_t waves = a.n < 32768 ? a.n : 32768;
+    const int64_t rows = a.alist ? a.n_active : a.n;  // list mode: the listed rows
+    const int64_t waves = rows < 32768 ? rows : 32768;
     int64_t grid = (waves + JOIN_WAVES - 1) / JOIN_WAVES;
     if (grid < 1)
         grid = 1;

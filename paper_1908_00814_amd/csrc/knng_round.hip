@@ -47,10 +47,11 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
             nnew += o != ~0ull;
         }
         const bool sampled = isnew && rank < a.s;
+        bool mark = false;  // the sampled id becomes active
         if (sampled) {
             a.new_f[u * a.s + rank] = (int32_t)id;
             if (id < a.n)
-                a.atag[id] = tr;
+                mark = true;
             else
                 raise_err(a.ctr + C_ERR, ERR_ROW_SAMPLE);
         }
@@ -70,10 +71,32 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
             a.worst[u] = wv;
             a.cnt_f[2 * u] = nnew < a.s ? nnew : a.s;
             a.cnt_f[2 * u + 1] = __popcll(om);
-            if (nnew > 0)
-                a.atag[u] = tr;
             if (nnew > a.s)
                 a.dtag[u] = tr + 1;
+        }
+        const bool mark_u = lane == 0 && nnew > 0;  // u itself is active
+        if (!a.alist) {
+            if (mark)
+                a.atag[id] = tr;
+            if (mark_u)
+                a.atag[u] = tr;
+        } else {
+            // the first mark of a row in this round appends it to the list
+            const bool fm = mark && atomicExch(a.atag + id, tr) != tr;
+            const bool fu = mark_u && atomicExch(a.atag + u, tr) != tr;
+            const uint64_t m1 = __ballot(fm), m2 = __ballot(fu);
+            const int cnt = __popcll(m1) + __popcll(m2);
+            if (cnt) {
+                unsigned long long base = 0;
+                if (lane == 0)
+                    base = atomicAdd((unsigned long long *)(a.ctr + C_ACTIVE),
+                                     (unsigned long long)cnt);
+                base = __shfl(base, 0, WAVE);
+                if (fm)
+                    a.alist[base + __popcll(m1 & below)] = (int32_t)id;
+                if (fu)
+                    a.alist[base + __popcll(m1)] = (int32_t)u;
+            }
         }
     }
     if (lane == 0 && fresh_total)
@@ -86,7 +109,7 @@ __global__ __launch_bounds__(256) void k_prep_active(RoundArgs a)
 {
     const int lane = lane_id();
     const int32_t tr = a.tag0 + a.round;
-    FOR_TAGGED_ROWS(u, a.n, a.atag, tr)
+    FOR_ACTIVE_ROWS(u, a, tr)
     {
         if (lane < a.s) {
             a.rnew[u * a.s + lane] = empty_key(lane);
@@ -229,8 +252,10 @@ __global__ __launch_bounds__(256) void k_reverse_base(RoundArgs a)
     const int lane = lane_id();
     uint64_t *keep = keep_all[threadIdx.x / WAVE];
     const int32_t tr = a.tag0 + a.round;
-    FOR_TAGGED_ROWS(v, a.rev_m, a.atag, tr)
+    FOR_ACTIVE_ROWS(v, a, tr)
     {
+        if (v >= a.rev_m)
+            continue;  // rows past the base have no base sources
         const int64_t lo = a.rev_off[v], hi = a.rev_off[v + 1];
         uint64_t best = ~0ull;  // lane j < nkept: the offer of rank j so far
         int nkept = 0, offers = 0;
@@ -438,9 +463,13 @@ hipError_t launch_sample(const RoundArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
+// rows an active-row kernel walks: the list, or all n
+inline int64_t active_span(const RoundArgs &a) { return a.alist ? a.n_active : a.n; }
+
 hipError_t launch_prep_active(const RoundArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_prep_active, dim3(grid_for(a.n, 4, 8192)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_prep_active, dim3(grid_for(active_span(a), 4, 8192)), dim3(256), 0, st,
+                       a);
     return hipGetLastError();
 }
 
@@ -455,7 +484,8 @@ hipError_t launch_reverse_indexed(const RoundArgs &a, hipStream_t st)
 {
     // base first: it writes the reservoirs of its targets without atomics
     if (a.rev_m > 0)
-        hipLaunchKernelGGL(k_reverse_base, dim3(grid_for(a.rev_m, 4, 8192)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_reverse_base, dim3(grid_for(active_span(a), 4, 8192)), dim3(256), 0,
+                           st, a);
     hipLaunchKernelGGL(k_reverse_rows, dim3(grid_for(a.n, 4, 8192)), dim3(256), 0, st, a);
     return hipGetLastError();
 }

@@ -171,6 +171,7 @@ void carve_slot(Carve &c, const knng_server &s, Slot &sl)
     w.dtag = c.take<int32_t>(n);
     w.atag = c.take<int32_t>(n);
     w.rfill = c.take<int32_t>((size_t)n * 2);
+    w.alist = c.take<int32_t>(n);  // active rows of a round: a request touches few rows
     sl.out = c.take<uint64_t>((size_t)n * s.gstride);
 }
 
