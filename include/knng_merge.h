@@ -213,8 +213,10 @@ size_t knng_expand_workspace_size(int64_t n_base, int64_t n_raw, int32_t d, int3
  * knng_merge; an odd last range moves up unchanged.  out: X->n rows, k
  * columns, ids = row indices of X.  stats (may be NULL): totals over all
  * merges; updates[l] holds the distance evaluations of level l, pairs[l] its
- * rounds and gathered[l] its wall time in microseconds.  Synchronises the
- * stream.
+ * rounds and gathered[l] its wall time in microseconds.  The merges of one
+ * level are independent and run at the same time, each in a host thread and
+ * on a stream of its own (default priority) with a slice of the workspace;
+ * the call first waits for `stream` and returns when `out` is complete.
  */
 knng_status knng_merge_tree(const knng_set *X, const int64_t *starts, const knng_graph *G,
                             int32_t nblocks, int32_t k, knng_metric metric,

@@ -9,6 +9,8 @@
 
 #include "knng_host.h"
 
+#include <thread>
+
 using namespace knng;
 using namespace knng::host;
 
@@ -348,26 +350,43 @@ void carve_tree(Carve &c, TreeBufs &t, int64_t n, int k)
     c.off = (c.off + 255) / 256 * 256;
 }
 
-size_t tree_merge_ws(const int64_t *starts, int nb, int d, int k, int kin_max, knng_metric m,
-                     const knng_opts *o)
+// Workspace slices of the merges of every level (the merges of a level run
+// at the same time, each in a 256-byte aligned slice of its own); the tree
+// needs the largest per-level sum.
+std::vector<std::vector<size_t>> tree_plan(const int64_t *starts, int nb, int d, int k,
+                                           int kin_max, knng_metric m, const knng_opts *o)
 {
-    // the largest single merge of the tree; every level merges neighbours
     std::vector<int64_t> b(starts, starts + nb + 1);
-    size_t best = 0;
+    std::vector<std::vector<size_t>> plan;
     int kin = kin_max;
     while (b.size() > 2) {
         std::vector<int64_t> nxt;
+        std::vector<size_t> lvl;
         nxt.push_back(b[0]);
         for (size_t i = 0; i + 2 < b.size(); i += 2) {
-            size_t w = knng_merge_workspace_size(b[i + 1] - b[i], b[i + 2] - b[i + 1], d, k, kin,
-                                                 kin, m, o);
-            best = w > best ? w : best;
+            const size_t w = knng_merge_workspace_size(b[i + 1] - b[i], b[i + 2] - b[i + 1], d, k,
+                                                       kin, kin, m, o);
+            lvl.push_back((w + 255) / 256 * 256);
             nxt.push_back(b[i + 2]);
         }
         if ((b.size() - 1) % 2 == 1)
             nxt.push_back(b.back());
         b.swap(nxt);
+        plan.push_back(lvl);
         kin = kin > k ? kin : k;
+    }
+    return plan;
+}
+
+size_t tree_merge_ws(const int64_t *starts, int nb, int d, int k, int kin_max, knng_metric m,
+                     const knng_opts *o)
+{
+    size_t best = 0;
+    for (const auto &lvl : tree_plan(starts, nb, d, k, kin_max, m, o)) {
+        size_t sum = 0;
+        for (size_t w : lvl)
+            sum += w;
+        best = sum > best ? sum : best;
     }
     return best;
 }
@@ -423,46 +442,94 @@ extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
     int32_t *const *ids = t.ids;
     float *const *dist = t.dist;
     uint8_t *mws = static_cast<uint8_t *>(workspace) + c.off;
-    const size_t mws_bytes = workspace_bytes - c.off;
+    const int kin_plan = kin_max > k ? kin_max : k;
+    const auto plan = tree_plan(starts, nblocks, X->d, k, kin_plan, metric, opts);
     knng_stats total;
     memset(&total, 0, sizeof total);
     std::vector<Seg> segs;
     for (int b = 0; b < nblocks; b++)
         segs.push_back({starts[b], starts[b + 1], G[b].ids, G[b].dist, G[b].k});
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    HIP_TRY(hipStreamSynchronize(st));  // inputs written on the caller's stream are complete
+    // one stream per merge of a level (the first level has the most)
+    std::vector<hipStream_t> streams(plan.empty() ? 0 : plan[0].size(), nullptr);
+    auto destroy = [&]() {
+        for (hipStream_t x : streams)
+            if (x)
+                (void)hipStreamDestroy(x);
+    };
+    for (hipStream_t &x : streams)
+        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) {
+            destroy();
+            return fail(KNNG_EDEVICE, "stream creation failed");
+        }
     int level = 0;
     while (segs.size() > 1) {
         const bool last = segs.size() == 2;
         const auto t_level = std::chrono::steady_clock::now();
         int32_t *li = last ? out->ids : ids[level & 1];
         float *ld = last ? out->dist : dist[level & 1];
+        const size_t npairs = segs.size() / 2;
+        std::vector<knng_stats> one(npairs);
+        std::vector<knng_status> rc(npairs, KNNG_OK);
+        std::vector<std::string> msg(npairs);
+        std::vector<std::thread> workers;
+        size_t off = 0;
+        // the merges of a level are independent: each runs in a host thread
+        // of its own, on its own stream and workspace slice
+        for (size_t i = 0; i < npairs; i++) {
+            const Seg p = segs[2 * i], q = segs[2 * i + 1];
+            uint8_t *ws = mws + off;
+            const size_t ws_bytes = plan[level][i];
+            off += ws_bytes;
+            hipStream_t sx = streams[i];
+            workers.emplace_back([=, &one, &rc, &msg]() {
+                if (hipSetDevice(device) != hipSuccess) {
+                    rc[i] = KNNG_EDEVICE;
+                    msg[i] = "hipSetDevice failed in a merge-tree worker";
+                    return;
+                }
+                knng_set s1{p.c - p.a, X->d, X->x + p.a * X->d};
+                knng_set s2{q.c - q.a, X->d, X->x + q.a * X->d};
+                knng_graph g1{p.c - p.a, p.kk, p.ids, p.dist};
+                knng_graph g2{q.c - q.a, q.kk, q.ids, q.dist};
+                knng_graph o{q.c - p.a, k, li + p.a * k, ld + p.a * k};
+                memset(&one[i], 0, sizeof one[i]);
+                rc[i] = knng_merge(&s1, &g1, &s2, &g2, k, metric, opts, &o, ws, ws_bytes, sx,
+                                   &one[i]);
+                if (rc[i] != KNNG_OK)
+                    msg[i] = g_err;
+            });
+        }
+        for (std::thread &w : workers)
+            w.join();
+        for (size_t i = 0; i < npairs; i++) {
+            if (rc[i] != KNNG_OK) {
+                destroy();
+                return fail(rc[i], "merge %zu of level %d: %s", i, level, msg[i].c_str());
+            }
+        }
         std::vector<Seg> nxt;
-        for (size_t i = 0; i + 1 < segs.size(); i += 2) {
-            const Seg &p = segs[i], &q = segs[i + 1];
-            knng_set s1{p.c - p.a, X->d, X->x + p.a * X->d};
-            knng_set s2{q.c - q.a, X->d, X->x + q.a * X->d};
-            knng_graph g1{p.c - p.a, p.kk, p.ids, p.dist};
-            knng_graph g2{q.c - q.a, q.kk, q.ids, q.dist};
-            knng_graph o{q.c - p.a, k, li + p.a * k, ld + p.a * k};
-            knng_stats one;
-            s = knng_merge(&s1, &g1, &s2, &g2, k, metric, opts, &o, mws, mws_bytes, stream, &one);
-            if (s != KNNG_OK)
-                return s;
-            total.rounds += one.rounds;
-            total.evals += one.evals;
-            total.rescored += one.rescored;
-            total.insert_attempts += one.insert_attempts;
-            total.screen_violations += one.screen_violations;
-            total.max_group = one.max_group > total.max_group ? one.max_group : total.max_group;
-            total.ms_prep += one.ms_prep;
-            total.ms_init += one.ms_init;
-            total.ms_sample += one.ms_sample;
-            total.ms_reverse += one.ms_reverse;
-            total.ms_join += one.ms_join;
-            total.ms_final += one.ms_final;
-            total.join_launches += one.join_launches;
+        for (size_t i = 0; i < npairs; i++) {
+            const Seg &p = segs[2 * i], &q = segs[2 * i + 1];
+            const knng_stats &o1 = one[i];
+            total.rounds += o1.rounds;
+            total.evals += o1.evals;
+            total.rescored += o1.rescored;
+            total.insert_attempts += o1.insert_attempts;
+            total.screen_violations += o1.screen_violations;
+            total.max_group = o1.max_group > total.max_group ? o1.max_group : total.max_group;
+            total.ms_prep += o1.ms_prep;
+            total.ms_init += o1.ms_init;
+            total.ms_sample += o1.ms_sample;
+            total.ms_reverse += o1.ms_reverse;
+            total.ms_join += o1.ms_join;
+            total.ms_final += o1.ms_final;
+            total.join_launches += o1.join_launches;
             if (level < KNNG_STATS_ROUNDS) {
-                total.updates[level] += one.evals;  // distance evaluations per level
-                total.pairs[level] += one.rounds;   // rounds per level
+                total.updates[level] += o1.evals;  // distance evaluations per level
+                total.pairs[level] += o1.rounds;   // rounds per level
             }
             nxt.push_back({p.a, q.c, li + p.a * k, ld + p.a * k, k});
         }
@@ -471,18 +538,23 @@ extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
             // writes into the buffer it lives in)
             const Seg &r = segs.back();
             const int64_t rows = r.c - r.a;
-            if (r.kk < k || !r.dist)
+            if (r.kk < k || !r.dist) {
+                destroy();
                 return fail(KNNG_EINVAL, "a block carried up unmerged needs k_in >= k and "
                                          "distances");
-            HIP_TRY(hipMemcpy2DAsync(li + r.a * k, (size_t)k * 4, r.ids, (size_t)r.kk * 4,
-                                     (size_t)(r.kk < k ? r.kk : k) * 4, (size_t)rows,
-                                     hipMemcpyDeviceToDevice, st));
-            HIP_TRY(hipMemcpy2DAsync(ld + r.a * k, (size_t)k * 4, r.dist, (size_t)r.kk * 4,
-                                     (size_t)(r.kk < k ? r.kk : k) * 4, (size_t)rows,
-                                     hipMemcpyDeviceToDevice, st));
+            }
+            if (hipMemcpy2DAsync(li + r.a * k, (size_t)k * 4, r.ids, (size_t)r.kk * 4,
+                                 (size_t)k * 4, (size_t)rows, hipMemcpyDeviceToDevice,
+                                 st) != hipSuccess ||
+                hipMemcpy2DAsync(ld + r.a * k, (size_t)k * 4, r.dist, (size_t)r.kk * 4,
+                                 (size_t)k * 4, (size_t)rows, hipMemcpyDeviceToDevice,
+                                 st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                destroy();
+                return fail(KNNG_EDEVICE, "copy of an unmerged block failed");
+            }
             nxt.push_back({r.a, r.c, li + r.a * k, ld + r.a * k, k});
         }
-        HIP_TRY(hipStreamSynchronize(st));
         if (level < KNNG_STATS_ROUNDS)
             total.gathered[level] = (int64_t)std::chrono::duration<double, std::micro>(
                                         std::chrono::steady_clock::now() - t_level)
@@ -490,7 +562,7 @@ extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
         segs.swap(nxt);
         level++;
     }
-    HIP_TRY(hipStreamSynchronize(st));
+    destroy();
     if (stats)
         *stats = total;
     return ok();

@@ -62,7 +62,8 @@ def test_host_queries(lib):
 @pytest.mark.parametrize("sizes", [(300, 257, 310, 280), (260, 240, 301), (1000, 3, 2, 7, 999)])
 def test_merge_tree_workspace_covers_every_merge(lib, sizes):
     # the tree keeps two ping-pong n x k levels (ids and distances, each on its
-    # own 256-byte boundary) in front of the workspace of its largest merge
+    # own 256-byte boundary) in front of the workspaces of one level's merges,
+    # which run at the same time (each in a 256-byte aligned slice)
     from paper_1908_00814_amd import knng
     k, d, n = 8, 10, sum(sizes)
     o = knng.opts(sample=6)
@@ -74,11 +75,13 @@ def test_merge_tree_workspace_covers_every_merge(lib, sizes):
     bufs = 4 * ((n * k * 4 + 255) // 256 * 256)
     b, biggest = list(starts), 0
     while len(b) > 2:
-        nxt = [b[0]]
+        nxt, level = [b[0]], 0
         for i in range(0, len(b) - 2, 2):
-            biggest = max(biggest, lib.knng_merge_workspace_size(
-                b[i + 1] - b[i], b[i + 2] - b[i + 1], d, k, k, k, 2, ctypes.byref(o)))
+            w = lib.knng_merge_workspace_size(b[i + 1] - b[i], b[i + 2] - b[i + 1], d, k, k, k, 2,
+                                              ctypes.byref(o))
+            level += (w + 255) // 256 * 256
             nxt.append(b[i + 2])
+        biggest = max(biggest, level)
         if (len(b) - 1) % 2:
             nxt.append(b[-1])
         b = nxt
