@@ -15,6 +15,8 @@ is points merged per second.  After the timed steps the script
     (log-uniform sizes) arriving as a Poisson stream at 0.7x the capacity
     measured on a warm-up burst, several requests on the device at once;
     p50/p99 of submit-to-result latency,
+  - NN-Descent from random lists and J-Merge (S1 with its graph, S2 raw) on the
+    same 1M rows: distance evaluations relative to NN-Descent (Eqs. 3-4),
   - merge tree: 8 blocks of 125,000 x d100 Gaussian-mixture rows with exact
     k=16 l1 block graphs merged pairwise in 3 levels to 1,000,000 rows,
   - times the CPU oracle on a bounded sample of the headline workload.
@@ -356,6 +358,46 @@ def cosine_bench(args, dev):
     return out
 
 
+def complexity_bench(args, dev, dS1, dG1, dS2, X, rows, smerge):
+    """Comparisons of S-Merge and J-Merge against NN-Descent on the same 1M rows
+    (Eqs. 3-4: about one third and two thirds of NN-Descent's comparisons, or
+    fewer when the inputs are good).  NN-Descent is J-Merge with an empty base
+    (random initial lists); J-Merge is Algorithm 2 as printed (every base list
+    appended to), S1 with its input graph and S2 raw."""
+    import torch
+    from paper_1908_00814_amd import knng
+    k, n = args.k, X.shape[0]
+    kw = dict(sample=args.sample, delta=args.delta, seed=args.seed + 11)
+    dX = torch.cat([dS1, dS2])
+    out = {"s_merge": {"evals": smerge["evals"], "rounds": smerge["rounds"],
+                       "recall@10": smerge["recall@10"],
+                       "points_per_s": smerge["value"]}}
+    for name, call in (("nn_descent", lambda: knng.expand(None, None, dX, k, "l2", **kw)),
+                       ("j_merge", lambda: knng.expand(dS1, dG1, dS2, k, "l2", **kw))):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ids, _, st = call()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        rec = recall_at10(ids.cpu().numpy(), X, rows, dev)
+        out[name] = {"ms": dt * 1e3, "points_per_s": n / dt, "rounds": st["rounds"],
+                     "evals": st["evals"], "recall@10": rec}
+        log(f"[nnd] {name}: {dt * 1e3:.0f} ms, {n / dt / 1e6:.2f} M points/s, "
+            f"{st['rounds']} rounds, {st['evals'] / 1e6:.0f}M distance evaluations, "
+            f"recall@10 {rec:.4f}")
+        del ids
+    e = out["nn_descent"]["evals"]
+    out["s_merge_over_nn_descent"] = out["s_merge"]["evals"] / e
+    out["j_merge_over_nn_descent"] = out["j_merge"]["evals"] / e
+    out["workload"] = ("1M rows of the headline set: NN-Descent from random lists, J-Merge of "
+                       "S1 (input graph) with S2 raw, S-Merge as timed above; k=20, s=20, "
+                       "delta=0.001")
+    log(f"[nnd] comparisons relative to NN-Descent: S-Merge "
+        f"{out['s_merge_over_nn_descent']:.3f}, J-Merge {out['j_merge_over_nn_descent']:.3f}")
+    del dX
+    return out
+
+
 def cpu_baseline(n_per, k, s, delta, seed, dev, precision):
     """The oracle timed on a bounded sample of the headline workload; the GPU
     merges the same sample and the two graphs are compared."""
@@ -416,6 +458,8 @@ def main():
     ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--no-tree", action="store_true", help="skip the merge-tree workload")
     ap.add_argument("--no-cosine", action="store_true", help="skip the d960 cosine workload")
+    ap.add_argument("--no-nnd", action="store_true",
+                    help="skip NN-Descent and J-Merge on the headline rows")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -521,7 +565,11 @@ def main():
                            if len(paths) == 2 else None),
         "paths_identical": same,
     }
-    del dS1, dS2, dG1, dG2, ws, out
+    del ws, out
+    torch.cuda.empty_cache()
+    if not args.no_nnd:
+        line["complexity"] = complexity_bench(args, dev, dS1, dG1, dS2, X, rows, paths[best])
+    del dS1, dS2, dG1, dG2
     torch.cuda.empty_cache()
     if not args.no_tree:
         line["tree"] = tree_bench(args, dev)
