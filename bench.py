@@ -15,8 +15,9 @@ is points merged per second.  After the timed steps the script
     (log-uniform sizes) arriving as a Poisson stream at 0.7x the capacity
     measured on a warm-up burst, several requests on the device at once;
     p50/p99 of submit-to-result latency,
-  - NN-Descent from random lists and J-Merge (S1 with its graph, S2 raw) on the
-    same 1M rows: distance evaluations relative to NN-Descent (Eqs. 3-4),
+  - NN-Descent from random lists, J-Merge (S1 with its graph, S2 raw) and
+    H-Merge on the same 1M rows: distance evaluations relative to NN-Descent
+    (Eqs. 3-4, Table 1),
   - merge tree: 8 blocks of 125,000 x d100 Gaussian-mixture rows with exact
     k=16 l1 block graphs merged pairwise in 3 levels to 1,000,000 rows,
   - times the CPU oracle on a bounded sample of the headline workload.
@@ -386,14 +387,34 @@ def complexity_bench(args, dev, dS1, dG1, dS2, X, rows, smerge):
             f"{st['rounds']} rounds, {st['evals'] / 1e6:.0f}M distance evaluations, "
             f"recall@10 {rec:.4f}")
         del ids
+    # H-Merge (Section 3.3): NN-Descent on n/64 random rows, then J-Merges
+    # doubling the graph to all rows (k/2 lists above the bottom layer)
+    n_top = n // 64
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ids, _, st = knng.hmerge(dX, k, n_top, "l2", **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    rec = recall_at10(ids.cpu().numpy(), X, rows, dev)
+    out["h_merge"] = {"ms": dt * 1e3, "points_per_s": n / dt, "n_top": n_top,
+                      "layers": len(st["layer_rounds"]), "rounds": st["rounds"],
+                      "evals": st["evals"], "recall@10": rec,
+                      "layer_ms": [round(v, 2) for v in st["layer_ms"]],
+                      "layer_rounds": st["layer_rounds"]}
+    log(f"[nnd] h_merge: {dt * 1e3:.0f} ms, {n / dt / 1e6:.2f} M points/s, "
+        f"{len(st['layer_rounds'])} layers from {n_top:,} rows, {st['evals'] / 1e6:.0f}M "
+        f"distance evaluations, recall@10 {rec:.4f}; layer ms {out['h_merge']['layer_ms']}")
+    del ids
     e = out["nn_descent"]["evals"]
     out["s_merge_over_nn_descent"] = out["s_merge"]["evals"] / e
     out["j_merge_over_nn_descent"] = out["j_merge"]["evals"] / e
+    out["h_merge_over_nn_descent"] = out["h_merge"]["evals"] / e
     out["workload"] = ("1M rows of the headline set: NN-Descent from random lists, J-Merge of "
-                       "S1 (input graph) with S2 raw, S-Merge as timed above; k=20, s=20, "
-                       "delta=0.001")
+                       "S1 (input graph) with S2 raw, H-Merge from n/64 random rows, S-Merge "
+                       "as timed above; k=20, s=20, delta=0.001")
     log(f"[nnd] comparisons relative to NN-Descent: S-Merge "
-        f"{out['s_merge_over_nn_descent']:.3f}, J-Merge {out['j_merge_over_nn_descent']:.3f}")
+        f"{out['s_merge_over_nn_descent']:.3f}, J-Merge {out['j_merge_over_nn_descent']:.3f}, "
+        f"H-Merge {out['h_merge_over_nn_descent']:.3f}")
     del dX
     return out
 

@@ -228,6 +228,32 @@ size_t knng_merge_tree_workspace_size(int64_t n, int32_t d, int32_t nblocks,
                                       knng_metric metric, const knng_opts *opts);
 
 /*
+ * H-Merge (Section 3.3): the graph of X built layer by layer.  The rows are
+ * taken in a random order (the blocks joined in must be random subsets):
+ * position i holds row perm(i), a seeded bijection of [0, n) (a 4-round
+ * Feistel network on the counter hash, walked until the value falls below
+ * n).  NN-Descent (J-Merge with an empty base) builds the graph of the first
+ * n_top positions; each later layer joins a raw block as large as the current
+ * graph (the last one: the rows left) with J-Merge, doubling the rows until
+ * all n are in.  Lists hold k/2 entries on every layer above the bottom one
+ * and k on the bottom layer, at most the layer's rows - 1.  Layer l is seeded
+ * SplitMix64(opts->seed ^ SplitMix64(l)); every layer uses opts otherwise
+ * (keep_ratio must keep at most the upper layer's list size).
+ *   out: X->n rows, k columns, ids = row indices of X, rows sorted by
+ *   (distance, id).  stats (may be NULL): totals over the layers;
+ *   updates[l], pairs[l] and gathered[l] hold layer l's distance
+ *   evaluations, rounds and wall time in microseconds.  The workspace holds
+ *   the permuted rows, two layer graphs and one J-Merge's workspace.
+ *   Errors as knng_merge; n_top < 2 is EINVAL.
+ */
+knng_status knng_hmerge(const knng_set *X, int32_t k, int64_t n_top, knng_metric metric,
+                        const knng_opts *opts, knng_graph *out, void *workspace,
+                        size_t workspace_bytes, void *stream, knng_stats *stats);
+
+size_t knng_hmerge_workspace_size(int64_t n, int32_t d, int32_t k, int64_t n_top,
+                                  knng_metric metric, const knng_opts *opts);
+
+/*
  * Brute-force cross merge (Section 1): row i of S1 becomes the top k of
  * G1[i] and every (m(x_i, y_j), n1+j); S2 rows likewise against S1.
  * Deterministic: equal to the exact result in canonical FP32 with ties broken

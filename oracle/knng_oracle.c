@@ -80,6 +80,7 @@
 #define TAG_RNEW 0xB2u
 #define TAG_ROLD 0xB3u
 #define TAG_SELECT 0xA3u
+#define TAG_PERM 0xC1u
 
 /* ------------------------------------------------------------------------ */
 /* SplitMix64                                                                */
@@ -941,4 +942,49 @@ void orc_draws(uint64_t seed, uint32_t tag, uint64_t row, uint32_t N, int64_t sk
                int32_t *out)
 {
     distinct_draws(seed, tag, row, N, skip, m, out);
+}
+
+/*
+ * The order in which H-Merge (Section 3.3) takes the rows; the blocks it
+ * joins in must be random subsets of the whole set.  Reading: a seeded
+ * bijection of [0, n).  Let h >= 1 be the smallest count with 4^h >= n.  A
+ * balanced Feistel network of four rounds on 2h-bit values splits x into a
+ * high half L and a low half R (h bits each); round r (0..3) replaces (L, R)
+ * with (R, L xor F_r(R)), where F_r(R) is the low h bits of
+ * H(seed, PERM, r, R, 0).  Every round is invertible, so the network permutes
+ * [0, 4^h); a result >= n is put through the network again until it falls
+ * below n ("cycle walking", Black and Rogaway, Ciphers with Arbitrary Finite
+ * Domains, 2002), which keeps a bijection on [0, n).  order[i] = the row at
+ * position i.
+ */
+static uint64_t feistel4(uint64_t seed, uint64_t x, int h)
+{
+    const uint64_t mask = ((uint64_t)1 << h) - 1;
+    uint64_t L = x >> h, R = x & mask;
+    for (int r = 0; r < 4; r++) {
+        uint64_t f = orc_hash(seed, TAG_PERM, (uint64_t)r, R, 0) & mask;
+        uint64_t nl = R, nr = L ^ f;
+        L = nl;
+        R = nr;
+    }
+    return (L << h) | R;
+}
+
+void orc_hmerge_order(uint64_t seed, int64_t n, int32_t *order)
+{
+    int h = 1;
+    while (((uint64_t)1 << (2 * h)) < (uint64_t)n)
+        h++;
+    for (int64_t i = 0; i < n; i++) {
+        uint64_t x = feistel4(seed, (uint64_t)i, h);
+        while (x >= (uint64_t)n)
+            x = feistel4(seed, x, h);
+        order[i] = (int32_t)x;
+    }
+}
+
+/* one Feistel pass on 2h-bit values (exposed for tests) */
+uint64_t orc_feistel4(uint64_t seed, uint64_t x, int h)
+{
+    return feistel4(seed, x, h);
 }

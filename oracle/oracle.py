@@ -81,6 +81,10 @@ def lib():
         L.orc_draws.restype = None
         L.orc_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                 ctypes.c_uint32, I64, ctypes.c_int, P]
+        L.orc_hmerge_order.restype = None
+        L.orc_hmerge_order.argtypes = [ctypes.c_uint64, I64, P]
+        L.orc_feistel4.restype = ctypes.c_uint64
+        L.orc_feistel4.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int]
         L.orc_dist64_rows.restype = None
         L.orc_dist64_rows.argtypes = [P, I64, ctypes.c_int, ctypes.c_int, P, I64, P]
         _lib = L
@@ -265,6 +269,61 @@ def merge_tree(X, starts, graphs, k, metric="l2", **kw):
                                np.ascontiguousarray(g[1][:, :k]))))
         segs = nxt
     return segs[0][2]
+
+
+def hmerge_order(seed, n):
+    """Row at each position of H-Merge's random order (Section 3.3; the
+    Feistel bijection documented in knng_oracle.c)."""
+    out = np.empty(n, np.int32)
+    lib().orc_hmerge_order(seed & (2**64 - 1), n, _ptr(out))
+    return out
+
+
+def feistel4(seed, x, h):
+    """One pass of the 4-round Feistel network on 2h-bit values."""
+    return int(lib().orc_feistel4(seed & (2**64 - 1), x, h))
+
+
+def hmerge_layers(n, n_top, k):
+    """(rows, list size) of every H-Merge layer, top first (Section 3.3): the
+    first n_top rows, then doubling until n; k/2 entries above the bottom
+    layer, k on it, never more than rows - 1."""
+    rows = [min(n_top, n)]
+    while rows[-1] < n:
+        rows.append(min(2 * rows[-1], n))
+    return [(m, min(k if m == n else k // 2, m - 1)) for m in rows]
+
+
+def hmerge(X, k, n_top, metric="l2", keep_ratio=0.5, sample=10, delta=0.0, max_rounds=30,
+           seed=0):
+    """H-Merge, Section 3.3: NN-Descent builds the graph of a random subset of
+    n_top rows; each later layer joins a raw random block as large as the
+    current graph with J-Merge (Algorithm 2), until every row is in.  The
+    rows are taken in the order hmerge_order(seed, n); layer l is seeded
+    SplitMix64(seed ^ SplitMix64(l)).  Returns (ids, dist, per-layer stats)
+    in the caller's row numbering, rows sorted by (distance, id)."""
+    X = _f32(X)
+    n = X.shape[0]
+    order = hmerge_order(seed, n)
+    Xp = X[order]
+    ids = dist = None
+    stats, below = [], 0
+    for l, (rows, kk) in enumerate(hmerge_layers(n, n_top, k)):
+        s_l = splitmix64(seed ^ splitmix64(l))
+        base = Xp[:below] if below else None
+        ids, dist, st = jmerge(base, (ids, dist), Xp[below:rows], kk, metric,
+                               keep_ratio=keep_ratio, sample=sample, delta=delta,
+                               max_rounds=max_rounds, seed=s_l)
+        stats.append(st)
+        below = rows
+    # position i is row order[i]; ids are positions too
+    rid = order[ids]
+    srt = np.lexsort((rid, dist), axis=1)
+    out_i = np.empty_like(rid)
+    out_d = np.empty_like(dist)
+    out_i[order] = np.take_along_axis(rid, srt, axis=1)
+    out_d[order] = np.take_along_axis(dist, srt, axis=1)
+    return out_i, out_d, stats
 
 
 # --------------------------------------------------------------------------

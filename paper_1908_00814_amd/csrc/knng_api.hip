@@ -568,6 +568,174 @@ extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
     return ok();
 }
 
+// ---------------------------------------------------------------- H-Merge
+namespace {
+
+// Layers of H-Merge (Section 3.3): NN-Descent on the first n_top positions,
+// then J-Merges that double the rows until all n are in.  Lists hold k/2
+// entries on the layers above the bottom one and k on the bottom layer, never
+// more than the layer's rows - 1.
+struct HPlan {
+    std::vector<int64_t> rows;
+    std::vector<int> kk;
+};
+
+HPlan hmerge_plan(int64_t n, int64_t n_top, int k)
+{
+    HPlan p;
+    const int kh = k / 2;
+    auto list = [&](int64_t rows) {
+        const int v = rows == n ? k : kh;
+        return (int64_t)v > rows - 1 ? (int)(rows - 1) : v;
+    };
+    int64_t m = n_top < n ? n_top : n;
+    p.rows.push_back(m);
+    p.kk.push_back(list(m));
+    while (m < n) {
+        m = 2 * m < n ? 2 * m : n;
+        p.rows.push_back(m);
+        p.kk.push_back(list(m));
+    }
+    return p;
+}
+
+// bits of each Feistel half: 2 * half >= bits of n - 1
+int perm_half(int64_t n)
+{
+    int b = 2;
+    while (b < 62 && ((int64_t)1 << b) < n)
+        b++;
+    return (b + 1) / 2;
+}
+
+struct HBufs {
+    int32_t *perm, *ids[2];
+    float *xp, *dist[2];
+};
+
+void carve_hmerge(Carve &c, HBufs &h, int64_t n, int d, int k)
+{
+    h.perm = c.take<int32_t>(n);
+    h.xp = c.take<float>((size_t)n * d);
+    for (int i = 0; i < 2; i++) {
+        h.ids[i] = c.take<int32_t>((size_t)n * k);
+        h.dist[i] = c.take<float>((size_t)n * k);
+    }
+    c.off = (c.off + 255) / 256 * 256;
+}
+
+knng_opts layer_opts(const knng_opts *o, int level)
+{
+    knng_opts lo = *o;
+    lo.seed = sm64_host(o->seed ^ sm64_host((uint64_t)level));
+    return lo;
+}
+
+} // namespace
+
+extern "C" size_t knng_hmerge_workspace_size(int64_t n, int32_t d, int32_t k, int64_t n_top,
+                                            knng_metric metric, const knng_opts *opts)
+{
+    if (n < 2 || d < 1 || k < 1 || n_top < 2 || !opts)
+        return 0;
+    Carve c(nullptr);
+    HBufs h;
+    carve_hmerge(c, h, n, d, k);
+    const HPlan p = hmerge_plan(n, n_top, k);
+    size_t best = 0;
+    for (size_t l = 0; l < p.rows.size(); l++) {
+        const int64_t nb = l ? p.rows[l - 1] : 0, nr = p.rows[l] - nb;
+        const knng_opts lo = layer_opts(opts, (int)l);
+        const size_t w =
+            knng_expand_workspace_size(nb, nr, d, p.kk[l], l ? p.kk[l - 1] : 0, metric, &lo);
+        best = w > best ? w : best;
+    }
+    return c.off + best + 256;
+}
+
+extern "C" knng_status knng_hmerge(const knng_set *X, int32_t k, int64_t n_top,
+                                   knng_metric metric, const knng_opts *opts, knng_graph *out,
+                                   void *workspace, size_t workspace_bytes, void *stream,
+                                   knng_stats *stats)
+{
+    knng_status s;
+    if ((s = check_metric(metric)) || (s = check_set(X, "X")) || (s = check_opts(opts, k)))
+        return s;
+    const int64_t n = X->n;
+    if (k < 1 || k > MAX_K || k > n - 1)
+        return fail(KNNG_EINVAL, "k = %d out of range [1, min(64, n-1)]", k);
+    if (n_top < 2)
+        return fail(KNNG_EINVAL, "n_top = %lld: the top layer needs at least 2 rows",
+                    (long long)n_top);
+    const HPlan p = hmerge_plan(n, n_top, k);
+    for (size_t l = 0; l < p.rows.size(); l++) {
+        if (p.kk[l] < 1)
+            return fail(KNNG_EINVAL, "layer %zu would hold empty lists (k = %d)", l, k);
+        if (l && keep_count(opts, p.kk[l]) > p.kk[l - 1])
+            return fail(KNNG_EINVAL, "keep_ratio keeps %d entries of a layer with %d-entry lists",
+                        keep_count(opts, p.kk[l]), p.kk[l - 1]);
+    }
+    if ((s = check_out(out, n, k)))
+        return s;
+    const size_t need = knng_hmerge_workspace_size(n, X->d, k, n_top, metric, opts);
+    if (!workspace || workspace_bytes < need)
+        return fail(KNNG_ENOMEM, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    if (!is_device_ptr(workspace))
+        return fail(KNNG_EINVAL, "workspace is not device memory");
+    hipStream_t st = (hipStream_t)stream;
+    Carve c(workspace);
+    HBufs h;
+    carve_hmerge(c, h, n, X->d, k);
+    uint8_t *mws = static_cast<uint8_t *>(workspace) + c.off;
+    const size_t mws_bytes = workspace_bytes - c.off;
+    // random order of the rows: the blocks joined in are random subsets
+    HIP_TRY(launch_permute_rows(X->x, n, X->d, opts->seed, perm_half(n), h.perm, h.xp, st));
+    knng_stats total;
+    memset(&total, 0, sizeof total);
+    int cur = 0;
+    for (size_t l = 0; l < p.rows.size(); l++) {
+        const auto t_level = std::chrono::steady_clock::now();
+        const int64_t nb = l ? p.rows[l - 1] : 0, nr = p.rows[l] - nb;
+        const knng_opts lo = layer_opts(opts, (int)l);
+        knng_set base{nb, X->d, nb ? h.xp : nullptr};
+        knng_graph g{nb, l ? p.kk[l - 1] : 0, l ? h.ids[cur] : nullptr,
+                     l ? h.dist[cur] : nullptr};
+        knng_set raw{nr, X->d, h.xp + nb * X->d};
+        const int nxt = l ? 1 - cur : cur;
+        knng_graph o{p.rows[l], p.kk[l], h.ids[nxt], h.dist[nxt]};
+        knng_stats one;
+        s = knng_expand(&base, &g, &raw, p.kk[l], metric, &lo, &o, mws, mws_bytes, stream, &one);
+        if (s != KNNG_OK)
+            return s;
+        cur = nxt;
+        total.rounds += one.rounds;
+        total.evals += one.evals;
+        total.rescored += one.rescored;
+        total.insert_attempts += one.insert_attempts;
+        total.screen_violations += one.screen_violations;
+        total.max_group = one.max_group > total.max_group ? one.max_group : total.max_group;
+        total.ms_prep += one.ms_prep;
+        total.ms_init += one.ms_init;
+        total.ms_sample += one.ms_sample;
+        total.ms_reverse += one.ms_reverse;
+        total.ms_join += one.ms_join;
+        total.ms_final += one.ms_final;
+        total.join_launches += one.join_launches;
+        if (l < KNNG_STATS_ROUNDS) {
+            total.updates[l] = one.evals;  // distance evaluations of the layer
+            total.pairs[l] = one.rounds;   // its rounds
+            total.gathered[l] = (int64_t)std::chrono::duration<double, std::micro>(
+                                    std::chrono::steady_clock::now() - t_level)
+                                    .count();
+        }
+    }
+    // back to the caller's row numbering
+    HIP_TRY(launch_unpermute_graph(h.ids[cur], h.dist[cur], n, k, h.perm, out->ids, out->dist, st));
+    if (stats)
+        *stats = total;
+    return ok();
+}
+
 size_t knng_bruteforce_workspace_size(int64_t n1, int64_t n2, int32_t d, int32_t k,
                                       int32_t kin1, int32_t kin2, knng_metric metric)
 {

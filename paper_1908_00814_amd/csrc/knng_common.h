@@ -103,7 +103,7 @@ __device__ __forceinline__ uint64_t hash5(uint64_t seed, uint64_t tag, uint64_t 
 }
 
 constexpr uint32_t TAG_APPEND = 0xA1u, TAG_INIT = 0xA2u, TAG_SELECT = 0xA3u, TAG_FWD = 0xB1u,
-                   TAG_RNEW = 0xB2u, TAG_ROLD = 0xB3u;
+                   TAG_RNEW = 0xB2u, TAG_ROLD = 0xB3u, TAG_PERM = 0xC1u;
 
 // uniform draw below N from the high 32 bits (multiply-shift)
 __device__ __forceinline__ uint32_t draw_below(uint64_t h, uint32_t N)

@@ -79,6 +79,15 @@ struct Layout {
     int32_t *alist = nullptr;  // n words: the round's active rows (list mode)
 };
 
+// SplitMix64 (one step of the published generator), for seeds derived on the host
+inline uint64_t sm64_host(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 inline bool uses_bf16(knng_metric m, const knng_opts *o)
 {
     return o && o->precision == KNNG_BF16_RESCORE && m != KNNG_L1;

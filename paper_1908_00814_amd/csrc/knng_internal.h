@@ -151,6 +151,20 @@ hipError_t launch_sort_rows(const uint64_t *src, int src_stride, int64_t n, int 
                             hipStream_t st);
 hipError_t launch_zero_counters(uint64_t *ctr, int words, hipStream_t st);
 
+// ---- H-Merge (knng_prep.hip)
+// Random order of n rows (the blocks H-Merge joins in are random subsets):
+// perm[i] = the row placed at position i, from a 4-round Feistel network on
+// 2*half bits (2^(2*half) >= n) walked until the value falls below n; then
+// xp[i] = x[perm[i]] (rows of d floats).
+hipError_t launch_permute_rows(const float *x, int64_t n, int d, uint64_t seed, int half,
+                               int32_t *perm, float *xp, hipStream_t st);
+// Graph over positions (ids and distances, n x k) back to row numbering: row
+// perm[i] of out gets row i with every id j replaced by perm[j], sorted by
+// (distance, id).
+hipError_t launch_unpermute_graph(const int32_t *ids, const float *dist, int64_t n, int k,
+                                  const int32_t *perm, int32_t *out_ids, float *out_dist,
+                                  hipStream_t st);
+
 // ---- knng_round.hip
 hipError_t launch_sample(const RoundArgs &a, hipStream_t st);
 hipError_t launch_prep_active(const RoundArgs &a, hipStream_t st);

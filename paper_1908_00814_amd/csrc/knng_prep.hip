@@ -504,6 +504,75 @@ __global__ __launch_bounds__(256) void k_sort_rows(const uint64_t *__restrict__ 
         dst[i * dstst + lane] = empty_key(lane);
 }
 
+// position i -> row: Feistel network with cycle walking (a bijection of
+// [0, n) for any n; Black and Rogaway's construction for arbitrary domains).
+// Round r maps (L, R) to (R, L ^ F_r(R)) with F_r(R) the low `half` bits of
+// H(seed, PERM, r, R).
+__device__ inline uint32_t perm_position(uint64_t seed, uint32_t i, uint32_t n, int half)
+{
+    const uint32_t mask = (1u << half) - 1u;
+    uint32_t x = i;
+    do {
+        uint32_t L = x >> half, R = x & mask;
+        for (int r = 0; r < 4; r++) {
+            const uint32_t f =
+                (uint32_t)hash5(seed, TAG_PERM, (uint64_t)r, (uint64_t)R, 0) & mask;
+            const uint32_t t = L ^ f;
+            L = R;
+            R = t;
+        }
+        x = (L << half) | R;
+    } while (x >= n);  // i < n lies on the cycle, so the walk ends
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_perm(uint64_t seed, int64_t n, int half, int32_t *perm)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n)
+        perm[i] = (int32_t)perm_position(seed, (uint32_t)i, (uint32_t)n, half);
+}
+
+__global__ __launch_bounds__(256) void k_gather_rows(const float *__restrict__ x, int64_t n, int d,
+                                                     const int32_t *__restrict__ perm,
+                                                     float *__restrict__ xp)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * d;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / d;
+        xp[e] = x[(int64_t)perm[i] * d + (e - i * d)];
+    }
+}
+
+// one wave per position
+__global__ __launch_bounds__(256) void k_unpermute(const int32_t *__restrict__ ids,
+                                                   const float *__restrict__ dist, int64_t n,
+                                                   int k, const int32_t *__restrict__ perm,
+                                                   int32_t *out_ids, float *out_dist)
+{
+    const int lane = lane_id();
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    if (i >= n)
+        return;
+    uint64_t key = ~0ull;
+    if (lane < k) {
+        const int32_t id = ids[i * k + lane];
+        if (id >= 0 && id < n)
+            key = make_key(dist[i * k + lane], (uint32_t)perm[id], 0);
+    }
+    int rank = 0;
+    for (int j = 0; j < k; j++) {
+        const uint64_t o = __shfl(key, j, WAVE);
+        rank += o < key || (o == key && j < lane);
+    }
+    if (lane < k) {
+        const int64_t row = perm[i];
+        const bool real = key != ~0ull;
+        out_ids[row * k + rank] = real ? (int32_t)key_id(key) : -1;
+        out_dist[row * k + rank] = real ? key_dist(key) : __uint_as_float(0x7F800000u);
+    }
+}
+
 __global__ void k_zero(uint64_t *p, int words)
 {
     int t = threadIdx.x;
@@ -615,6 +684,29 @@ hipError_t launch_sort_rows(const uint64_t *src, int src_stride, int64_t n, int 
         return hipSuccess;
     hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n, 4)), dim3(256), 0, st, src, src_stride, n, k,
                        dst, dst_stride, ids, dist);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_rows(const float *x, int64_t n, int d, uint64_t seed, int half,
+                               int32_t *perm, float *xp, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_perm, dim3(grid_for(n, 256)), dim3(256), 0, st, seed, n, half, perm);
+    unsigned g = grid_for(n * d, 256);
+    hipLaunchKernelGGL(k_gather_rows, dim3(g > 65536u ? 65536u : g), dim3(256), 0, st, x, n, d,
+                       perm, xp);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute_graph(const int32_t *ids, const float *dist, int64_t n, int k,
+                                  const int32_t *perm, int32_t *out_ids, float *out_dist,
+                                  hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_unpermute, dim3(grid_for(n, 4)), dim3(256), 0, st, ids, dist, n, k, perm,
+                       out_ids, out_dist);
     return hipGetLastError();
 }
 

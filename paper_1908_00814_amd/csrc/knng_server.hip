@@ -52,13 +52,6 @@ double now_us(std::chrono::steady_clock::time_point t0)
         .count();
 }
 
-uint64_t sm64_host(uint64_t x)
-{
-    uint64_t z = x + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
 
 struct Slot {
     int idx = 0;

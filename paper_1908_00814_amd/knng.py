@@ -26,7 +26,8 @@ ENTRY_POINTS = ["knng_opts_default", "knng_merge", "knng_merge_workspace_size", 
                 "knng_expand_workspace_size", "knng_merge_bruteforce",
                 "knng_bruteforce_workspace_size", "knng_exact_graph",
                 "knng_exact_graph_workspace_size", "knng_last_error", "knng_version",
-                "knng_merge_tree", "knng_merge_tree_workspace_size", "knng_server_bytes",
+                "knng_merge_tree", "knng_merge_tree_workspace_size", "knng_hmerge",
+                "knng_hmerge_workspace_size", "knng_server_bytes",
                 "knng_server_create", "knng_server_submit", "knng_server_step",
                 "knng_server_wait", "knng_server_snapshot", "knng_server_rebase",
                 "knng_server_status", "knng_server_slots", "knng_server_destroy"]
@@ -132,6 +133,10 @@ def load():
     lib.knng_merge_tree.argtypes = [pS, P, pG, I32, I32, ctypes.c_int, pO, pG, P, SZ, P, pSt]
     lib.knng_merge_tree_workspace_size.restype = SZ
     lib.knng_merge_tree_workspace_size.argtypes = [I64, I32, I32, P, I32, I32, ctypes.c_int, pO]
+    lib.knng_hmerge.restype = ctypes.c_int
+    lib.knng_hmerge.argtypes = [pS, I32, I64, ctypes.c_int, pO, pG, P, SZ, P, pSt]
+    lib.knng_hmerge_workspace_size.restype = SZ
+    lib.knng_hmerge_workspace_size.argtypes = [I64, I32, I32, I64, ctypes.c_int, pO]
     lib.knng_server_bytes.restype = SZ
     lib.knng_server_bytes.argtypes = [I64, I64, I32, I32, I32, ctypes.c_int, pO, I32]
     lib.knng_server_create.restype = ctypes.c_int
@@ -326,6 +331,31 @@ def merge_tree(X, starts, graphs, k, metric="l2", stream=None, workspace=None, *
     d["level_evals"] = [st.updates[lvl] for lvl in levels]
     d["level_rounds"] = [st.pairs[lvl] for lvl in levels]
     d["level_ms"] = [st.gathered[lvl] / 1e3 for lvl in levels]
+    return ids, dist, d
+
+
+def hmerge(X, k, n_top, metric="l2", stream=None, workspace=None, **kw):
+    """H-Merge (knng_hmerge): NN-Descent on n_top randomly chosen rows, then
+    J-Merges that double the graph until it covers X.  Returns (ids, dist,
+    stats dict with per-layer evaluations, rounds and wall times)."""
+    lib = load()
+    o = opts(**kw)
+    xs = _set(X)
+    need = lib.knng_hmerge_workspace_size(X.shape[0], X.shape[1], k, n_top, _metric(metric),
+                                          ctypes.byref(o))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    ids, dist = _out(X.shape[0], k, X.device)
+    go = _graph(ids, dist)
+    st = Stats()
+    _check(lib.knng_hmerge(ctypes.byref(xs), k, n_top, _metric(metric), ctypes.byref(o),
+                           ctypes.byref(go), _ptr(workspace), workspace.numel(), _stream(stream),
+                           ctypes.byref(st)))
+    d = st.to_dict()
+    layers = [lvl for lvl in range(STATS_ROUNDS) if st.pairs[lvl]]
+    d["layer_evals"] = [st.updates[lvl] for lvl in layers]
+    d["layer_rounds"] = [st.pairs[lvl] for lvl in layers]
+    d["layer_ms"] = [st.gathered[lvl] / 1e3 for lvl in layers]
     return ids, dist, d
 
 

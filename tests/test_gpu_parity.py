@@ -348,3 +348,46 @@ def test_merge_tree_identical_to_oracle(hip, sizes, metric):
                                  sample=6, seed=21)
     assert_same_graph(host(gi), host(gd), oi, od, f"merge tree {metric}")
     assert len(gst["level_rounds"]) == (2 if len(sizes) == 4 else 2)
+
+
+# ---------------------------------------------------------------- H-Merge
+
+@pytest.mark.parametrize("metric", ["l2", "l1", "cos"])
+def test_hmerge_identical_to_oracle(hip, metric):
+    # layers of 150, 300, 600, 1200, 2400 and 2,517 rows (a ragged last block)
+    X = synth.rng(131).standard_normal((2517, 9)).astype(np.float32) + 0.25
+    oi, od, ost = oracle.hmerge(X, 10, 150, metric, sample=6, seed=41)
+    gi, gd, gst = hip.hmerge(dev(X), 10, 150, metric, sample=6, seed=41)
+    assert_same_graph(host(gi), host(gd), oi, od, f"hmerge {metric}")
+    assert gst["layer_rounds"] == [s["rounds"] for s in ost]
+    assert gst["layer_evals"] == [s["evals"] for s in ost]
+    assert gst["evals"] == sum(s["evals"] for s in ost)
+
+
+def test_hmerge_exact_when_lists_hold_every_row(hip):
+    # k = n - 1 with n = 4 n_top: every layer starts from lists holding every
+    # other row, so the result is the exact graph
+    X = synth.rng(132).standard_normal((64, 7)).astype(np.float32)
+    gi, gd, _ = hip.hmerge(dev(X), 63, 16, "l2", sample=5, seed=3)
+    ei, ed = oracle.exact_graph(X, 63)
+    assert_same_graph(host(gi), host(gd), ei, ed, "hmerge exact")
+
+
+def test_hmerge_single_layer_and_bf16(hip):
+    # n_top >= n: one NN-Descent layer; the BF16 screen gives the same graph
+    X = synth.rng(133).standard_normal((700, 24)).astype(np.float32)
+    oi, od, _ = oracle.hmerge(X, 8, 5000, "l2", sample=6, seed=8)
+    for prec in ("fp32", "bf16"):
+        gi, gd, gst = hip.hmerge(dev(X), 8, 5000, "l2", sample=6, seed=8, precision=prec)
+        assert_same_graph(host(gi), host(gd), oi, od, f"hmerge one layer {prec}")
+        assert len(gst["layer_rounds"]) == 1
+
+
+def test_hmerge_invalid_inputs(hip):
+    X = synth.rng(134).standard_normal((100, 4)).astype(np.float32)
+    with pytest.raises(hip.KnngError, match="EINVAL"):
+        hip.hmerge(dev(X), 8, 1, "l2")                  # top layer of one row
+    with pytest.raises(hip.KnngError, match="EINVAL"):
+        hip.hmerge(dev(X), 8, 10, "l2", keep_ratio=0.9)  # keeps more than a k/2 layer holds
+    with pytest.raises(hip.KnngError, match="EINVAL"):
+        hip.hmerge(dev(X), 100, 10, "l2")               # k > n - 1

@@ -477,3 +477,55 @@ def test_delta_threshold_counts_rows_that_start_with_new_entries():
     _, _, st = oracle.jmerge(S1, G, S2, 8, sample=6, seed=5, balanced=True, delta=0.02)
     assert st["c"][-1] <= 0.02 * n0 * 8
     assert all(c > 0.02 * n0 * 8 for c in st["c"][:-1])
+
+
+# ---------------------------------------------------------------- H-Merge
+
+@pytest.mark.parametrize("h", [1, 2, 3, 4, 5])
+def test_feistel_pass_permutes_its_whole_domain(h):
+    # every round (L, R) -> (R, L ^ F(R)) is invertible, so one pass of the
+    # network is a bijection of [0, 4^h); a dropped xor or swapped half fails
+    size = 4 ** h
+    for seed in (0, 3):
+        img = sorted(oracle.feistel4(seed, x, h) for x in range(size))
+        assert img == list(range(size))
+
+
+def test_hmerge_order_is_a_seeded_bijection():
+    for n in list(range(1, 70)) + [255, 256, 257, 1000, 4097]:
+        o = oracle.hmerge_order(11, n)
+        assert np.array_equal(np.sort(o), np.arange(n)), n
+    a, b = oracle.hmerge_order(1, 500), oracle.hmerge_order(2, 500)
+    assert not np.array_equal(a, b)
+    # cycle walking keeps the points below n that one pass already maps
+    # below n: position i takes feistel(i) whenever that value is < n
+    n, h = 300, 5
+    o = oracle.hmerge_order(4, n)
+    for i in range(n):
+        f = oracle.feistel4(4, i, h)
+        if f < n:
+            assert o[i] == f
+
+
+def test_hmerge_layers_double_from_the_top_block():
+    # Section 3.3: each layer joins a block as large as the graph so far;
+    # k/2 lists above the bottom layer, k on it, capped at rows - 1
+    assert oracle.hmerge_layers(1000, 100, 20) == [(100, 10), (200, 10), (400, 10), (800, 10),
+                                                   (1000, 20)]
+    assert oracle.hmerge_layers(64, 16, 63) == [(16, 15), (32, 31), (64, 63)]
+    assert oracle.hmerge_layers(50, 80, 8) == [(50, 8)]
+
+
+@pytest.mark.parametrize("metric", ["l2", "l1", "cos"])
+@pytest.mark.parametrize("n,n_top", [(24, 6), (32, 4)])
+def test_hmerge_is_exact_when_lists_hold_every_row(metric, n, n_top):
+    # with k = n - 1 and n = 2^j n_top every layer's lists start with every
+    # other row of the layer (NN-Descent draws all rows; J-Merge keeps all of
+    # the upper layer and appends the whole raw block), so H-Merge must return
+    # the exact graph, in the caller's row numbering and (distance, id) order
+    X = synth.rng(900 + n).standard_normal((n, 5)).astype(np.float32) + 0.5
+    ids, dist, st = oracle.hmerge(X, n - 1, n_top, metric, sample=4, seed=n)
+    ei, ed = oracle.exact_graph(X, n - 1, metric)
+    assert np.array_equal(ids, ei)
+    assert np.array_equal(dist.view(np.uint32), ed.view(np.uint32))
+    assert len(st) == len(oracle.hmerge_layers(n, n_top, n - 1))
