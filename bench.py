@@ -18,6 +18,8 @@ is points merged per second.  After the timed steps the script
   - NN-Descent from random lists, J-Merge (S1 with its graph, S2 raw) and
     H-Merge on the same 1M rows: distance evaluations relative to NN-Descent
     (Eqs. 3-4, Table 1),
+  - Table 2's scanning rates of NN-Descent, S-Merge and J-Merge on 100,000
+    uniform rows, d from 2 to 100, l1 and l2,
   - merge tree: 8 blocks of 125,000 x d100 Gaussian-mixture rows with exact
     k=16 l1 block graphs merged pairwise in 3 levels to 1,000,000 rows,
   - times the CPU oracle on a bounded sample of the headline workload.
@@ -419,6 +421,63 @@ def complexity_bench(args, dev, dS1, dG1, dS2, X, rows, smerge):
     return out
 
 
+TABLE2 = [(2, 10), (5, 10), (10, 20), (20, 20), (50, 30), (100, 40)]
+
+
+def table2_bench(args, dev):
+    """Scanning rates of Table 2 on its synthetic sets: 100,000 uniform rows in
+    [0, 1)^d, d from 2 to 100 with the table's k, l1 and l2.  NN-Descent builds
+    the whole graph from random lists; for the merges it builds the graphs of
+    the two halves first (not counted), then S-Merge merges them and J-Merge
+    joins the second half raw into the first half's graph.  c = distance
+    evaluations / (n (n - 1) / 2); sampling rate 1 (s = min(k, 32)),
+    delta = 0.001."""
+    import torch
+    import synth
+    from paper_1908_00814_amd import knng
+    n = 100_000
+    h = n // 2
+    out = []
+    pairs = n * (n - 1) / 2.0
+    rows = synth.rng(6100).choice(n, 1000, replace=False)
+    for metric in ("l1", "l2"):
+        for d, k in TABLE2:
+            X = synth.rng(6000 + d).random((n, d), dtype=np.float32)
+            dX = torch.from_numpy(X).to(dev)
+            kw = dict(sample=min(k, 32), delta=0.001, seed=args.seed + d)
+            rec = {"metric": metric, "d": d, "k": k}
+
+            def timed(fn):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = fn()
+                torch.cuda.synchronize()
+                return r, (time.perf_counter() - t) * 1e3
+
+            (ids, _, st), ms = timed(lambda: knng.expand(None, None, dX, k, metric, **kw))
+            rec["nn_descent"] = {"c": st["evals"] / pairs, "ms": ms,
+                                 "recall@10": recall_at10(ids.cpu().numpy(), X, rows, dev, metric)}
+            g1 = knng.expand(None, None, dX[:h], k, metric, **kw)
+            g2 = knng.expand(None, None, dX[h:], k, metric, **kw)
+            (ids, _, st), ms = timed(lambda: knng.merge(dX[:h], g1[:2], dX[h:], g2[:2], k, metric,
+                                                        **kw))
+            rec["s_merge"] = {"c": st["evals"] / pairs, "ms": ms,
+                              "recall@10": recall_at10(ids.cpu().numpy(), X, rows, dev, metric)}
+            (ids, _, st), ms = timed(lambda: knng.expand(dX[:h], g1[:2], dX[h:], k, metric, **kw))
+            rec["j_merge"] = {"c": st["evals"] / pairs, "ms": ms,
+                              "recall@10": recall_at10(ids.cpu().numpy(), X, rows, dev, metric)}
+            log(f"[table2] {metric} d={d:3d} k={k}: c NN-Descent {rec['nn_descent']['c']:.4f} "
+                f"S-Merge {rec['s_merge']['c']:.4f} J-Merge {rec['j_merge']['c']:.4f}; "
+                f"recall@10 {rec['nn_descent']['recall@10']:.3f} / "
+                f"{rec['s_merge']['recall@10']:.3f} / {rec['j_merge']['recall@10']:.3f}; ms "
+                f"{rec['nn_descent']['ms']:.1f} / {rec['s_merge']['ms']:.1f} / "
+                f"{rec['j_merge']['ms']:.1f}")
+            out.append(rec)
+            del dX, ids, g1, g2
+    return {"workload": "Table 2 synthetic sets: 100,000 rows uniform in [0,1)^d, halves of "
+                        "50,000; sampling rate 1, delta 0.001", "rows": out}
+
+
 def cpu_baseline(n_per, k, s, delta, seed, dev, precision):
     """The oracle timed on a bounded sample of the headline workload; the GPU
     merges the same sample and the two graphs are compared."""
@@ -481,6 +540,8 @@ def main():
     ap.add_argument("--no-cosine", action="store_true", help="skip the d960 cosine workload")
     ap.add_argument("--no-nnd", action="store_true",
                     help="skip NN-Descent and J-Merge on the headline rows")
+    ap.add_argument("--no-table2", action="store_true",
+                    help="skip the scanning rates on Table 2's uniform sets")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -592,6 +653,9 @@ def main():
         line["complexity"] = complexity_bench(args, dev, dS1, dG1, dS2, X, rows, paths[best])
     del dS1, dS2, dG1, dG2
     torch.cuda.empty_cache()
+    if not args.no_table2:
+        line["table2"] = table2_bench(args, dev)
+        torch.cuda.empty_cache()
     if not args.no_tree:
         line["tree"] = tree_bench(args, dev)
         torch.cuda.empty_cache()

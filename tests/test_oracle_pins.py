@@ -529,3 +529,37 @@ def test_hmerge_is_exact_when_lists_hold_every_row(metric, n, n_top):
     assert np.array_equal(ids, ei)
     assert np.array_equal(dist.view(np.uint32), ed.view(np.uint32))
     assert len(st) == len(oracle.hmerge_layers(n, n_top, n - 1))
+
+
+# ---------------------------------------------------------------- Table 2
+
+def _table2():
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", "table2_scanning_rates.json")
+    return {(r[0], r[1]): r for r in json.load(open(p))["rows"]}
+
+
+@pytest.mark.parametrize("d", [2, 5])
+def test_scanning_rates_match_table2(d):
+    # Table 2 on its own synthetic set (100K uniform rows, halves merged):
+    # NN-Descent builds the whole graph, and the halves' graphs for S-Merge and
+    # J-Merge.  The paper states neither sampling rate nor delta; with rate 1
+    # (s = k) and delta = 0.001 each rate lies within half of the printed
+    # value plus half a unit of its last printed digit, and both merges scan
+    # fewer pairs than NN-Descent, the table's point.
+    _, _, k, c_nnd, c_s, c_j = _table2()[("l2", d)]
+    n = 100_000
+    h = n // 2
+    X = synth.rng(6000 + d).random((n, d), dtype=np.float32)
+    kw = dict(sample=k, delta=0.001, seed=2004 + d)
+    pairs = n * (n - 1) / 2.0
+    _, _, st = oracle.jmerge(None, None, X, k, "l2", **kw)
+    g1 = oracle.jmerge(None, None, X[:h], k, "l2", **kw)
+    g2 = oracle.jmerge(None, None, X[h:], k, "l2", **kw)
+    _, _, ss = oracle.smerge(X[:h], g1[:2], X[h:], g2[:2], k, "l2", **kw)
+    _, _, sj = oracle.jmerge(X[:h], g1[:2], X[h:], k, "l2", **kw)
+    got = {"nnd": st["evals"] / pairs, "s": ss["evals"] / pairs, "j": sj["evals"] / pairs}
+    for name, printed in (("nnd", c_nnd), ("s", c_s), ("j", c_j)):
+        assert abs(got[name] - printed) <= 0.5 * printed + 0.0005, (name, got[name], printed)
+    assert got["s"] < got["nnd"] and got["j"] < got["nnd"]
