@@ -19,7 +19,7 @@ is points merged per second.  After the timed steps the script
     H-Merge on the same 1M rows: distance evaluations relative to NN-Descent
     (Eqs. 3-4, Table 1),
   - Table 2's scanning rates of NN-Descent, S-Merge and J-Merge on 100,000
-    uniform rows, d from 2 to 100, l1 and l2,
+    uniform rows, d from 2 to 100, l1 and l2, and Fig. 4's keep-ratio sweep,
   - merge tree: 8 blocks of 125,000 x d100 Gaussian-mixture rows with exact
     k=16 l1 block graphs merged pairwise in 3 levels to 1,000,000 rows,
   - times the CPU oracle on a bounded sample of the headline workload.
@@ -478,6 +478,44 @@ def table2_bench(args, dev):
                         "50,000; sampling rate 1, delta 0.001", "rows": out}
 
 
+FIG4_R = [0.0, 0.2, 1.0 / 3.0, 0.5, 0.8]
+FIG4_SPLIT = [(2, 8), (3, 7), (5, 5), (7, 3), (8, 2)]
+
+
+def fig4_bench(args, dev):
+    """Fig. 4's ablation of the keep ratio r on the uniform d = 100 set of
+    100,000 rows, k = 30, l2: recall@10 of S-Merge and J-Merge for r from 0 to
+    4/5 with |S1|:|S2| from 2:8 to 8:2 (subgraphs by NN-Descent; one seed,
+    the paper averages 20)."""
+    import torch
+    import synth
+    from paper_1908_00814_amd import knng
+    n, d, k = 100_000, 100, 30
+    X = synth.rng(6000 + d).random((n, d), dtype=np.float32)
+    dX = torch.from_numpy(X).to(dev)
+    rows = synth.rng(6101).choice(n, 1000, replace=False)
+    kw = dict(sample=min(k, 32), delta=0.001, seed=args.seed)
+    out = []
+    for a, b in FIG4_SPLIT:
+        h = n * a // (a + b)
+        g1 = knng.expand(None, None, dX[:h], k, "l2", **kw)
+        g2 = knng.expand(None, None, dX[h:], k, "l2", **kw)
+        rec = {"split": f"{a}:{b}", "r": FIG4_R, "s_merge": [], "j_merge": []}
+        for r in FIG4_R:
+            ids = knng.merge(dX[:h], g1[:2], dX[h:], g2[:2], k, "l2", keep_ratio=r, **kw)[0]
+            rec["s_merge"].append(recall_at10(ids.cpu().numpy(), X, rows, dev))
+            ids = knng.expand(dX[:h], g1[:2], dX[h:], k, "l2", keep_ratio=r, **kw)[0]
+            rec["j_merge"].append(recall_at10(ids.cpu().numpy(), X, rows, dev))
+        log(f"[fig4] |S1|:|S2| = {a}:{b}: recall@10 for r = 0, 1/5, 1/3, 1/2, 4/5: S-Merge "
+            f"{' '.join(f'{v:.3f}' for v in rec['s_merge'])}; J-Merge "
+            f"{' '.join(f'{v:.3f}' for v in rec['j_merge'])}")
+        out.append(rec)
+        del g1, g2, ids
+    del dX
+    return {"workload": "Fig. 4: 100,000 uniform rows in [0,1)^100, k = 30, l2, keep ratio r "
+                        "swept at five size ratios", "rows": out}
+
+
 def cpu_baseline(n_per, k, s, delta, seed, dev, precision):
     """The oracle timed on a bounded sample of the headline workload; the GPU
     merges the same sample and the two graphs are compared."""
@@ -541,7 +579,7 @@ def main():
     ap.add_argument("--no-nnd", action="store_true",
                     help="skip NN-Descent and J-Merge on the headline rows")
     ap.add_argument("--no-table2", action="store_true",
-                    help="skip the scanning rates on Table 2's uniform sets")
+                    help="skip Table 2's scanning rates and Fig. 4's keep-ratio sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -655,6 +693,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_table2:
         line["table2"] = table2_bench(args, dev)
+        line["fig4"] = fig4_bench(args, dev)
         torch.cuda.empty_cache()
     if not args.no_tree:
         line["tree"] = tree_bench(args, dev)
