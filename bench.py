@@ -84,23 +84,30 @@ def measured_traffic(kernel):
     p = os.path.join(ROOT, "profiles", "k_join_traffic.json")
     if not os.path.exists(p):
         return None
-    rec = json.load(open(p))
     h = hashlib.sha256()
     for f in JOIN_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if rec.get("kernel") != kernel or rec.get("sources_sha256") != h.hexdigest():
-        return None
-    return rec["traffic_bytes_per_launch"]
+    data = json.load(open(p))
+    for rec in data.get("records", [data]):
+        if rec.get("kernel") == kernel and rec.get("sources_sha256") == h.hexdigest():
+            return rec["traffic_bytes_per_launch"]
+    return None
 
 
 def join_roofline(st, n, d, k, s, prec="fp32"):
     """Algorithmic bytes of the local-join launches of one merge and the
     achieved rate over their summed duration."""
     dp = (d + 3) // 4 * 4
+    db = (d + 31) // 32 * 32
     rounds = st["rounds"]
     members = sum(st["gathered"])
     per_u_lists = 8 + 4 * s + 8 * s + 4 * k + 8 * s  # counts, samples, reservoirs
-    traffic = (members * (4 * dp + 8)                    # member vectors + worst
+    if prec == "fp32":
+        gathers = members * (4 * dp + 8)              # fp32 member vectors + worst
+    else:
+        gathers = (members * (2 * db + 8)             # bf16 member vectors + worst
+                   + st["rescored"] * 2 * 4 * dp)     # fp32 rows of every rescored pair
+    traffic = (gathers
                + rounds * n * per_u_lists                 # neighbourhood id lists
                + st["insert_attempts"] * (8 * k + 16))   # list scan + CAS per insert
     launches = max(st["join_launches"], 1)
