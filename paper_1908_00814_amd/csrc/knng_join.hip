@@ -53,7 +53,7 @@ constexpr int JOIN_WAVES = 4;
 constexpr int CH = 8;                   // coordinates per staged chunk (FP32 path)
 constexpr int QCAP = 256;               // BF16 path: rescore-queue words per wave
 constexpr int QF = 192;                 // FP32 path: insert-queue entries per wave
-constexpr int TMAX = 2;                 // MFMA tiles held per batch (3 waves per SIMD)
+constexpr int TMAX = 1;                 // MFMA tiles held per batch (4 waves per SIMD)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -530,7 +530,7 @@ __device__ __forceinline__ float l2_threshold(uint64_t worst, float na, float nb
 }
 
 template <int METRIC, int KB>
-__global__ __launch_bounds__(JOIN_WAVES * WAVE, 3) void k_join_bf16(Rows R, RoundArgs a, int GS,
+__global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, RoundArgs a, int GS,
                                                                  int wave_bytes)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
