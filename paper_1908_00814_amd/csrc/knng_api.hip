@@ -9,6 +9,8 @@
 
 #include "knng_host.h"
 
+#include <new>
+
 #include <thread>
 
 using namespace knng;
@@ -240,10 +242,10 @@ size_t knng_expand_workspace_size(int64_t n_base, int64_t n_raw, int32_t d, int3
     return c.off + 256;
 }
 
-knng_status knng_merge(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
-                       const knng_graph *G2, int32_t k, knng_metric metric,
-                       const knng_opts *opts, knng_graph *out, void *workspace,
-                       size_t workspace_bytes, void *stream, knng_stats *stats)
+static knng_status knng_merge_impl(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
+                                   const knng_graph *G2, int32_t k, knng_metric metric,
+                                   const knng_opts *opts, knng_graph *out, void *workspace,
+                                   size_t workspace_bytes, void *stream, knng_stats *stats)
 {
     knng_status s;
     if ((s = check_metric(metric)) || (s = check_set(S1, "S1")) || (s = check_set(S2, "S2")) ||
@@ -281,10 +283,25 @@ knng_status knng_merge(const knng_set *S1, const knng_graph *G1, const knng_set 
     return run_merge(R, w, metric, bf16, opts, n, n1, k, k1, 0, n, out, st, stats, prof);
 }
 
-knng_status knng_expand(const knng_set *S, const knng_graph *G, const knng_set *raw, int32_t k,
-                        knng_metric metric, const knng_opts *opts, knng_graph *out,
-                        void *workspace, size_t workspace_bytes, void *stream,
-                        knng_stats *stats)
+knng_status knng_merge(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
+                       const knng_graph *G2, int32_t k, knng_metric metric,
+                       const knng_opts *opts, knng_graph *out, void *workspace,
+                       size_t workspace_bytes, void *stream, knng_stats *stats)
+{
+    try {
+        return knng_merge_impl(S1, G1, S2, G2, k, metric, opts, out, workspace, workspace_bytes,
+                               stream, stats);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
+}
+
+static knng_status knng_expand_impl(const knng_set *S, const knng_graph *G, const knng_set *raw,
+                                    int32_t k, knng_metric metric, const knng_opts *opts,
+                                    knng_graph *out, void *workspace, size_t workspace_bytes,
+                                    void *stream, knng_stats *stats)
 {
     knng_status s;
     if ((s = check_metric(metric)) || (s = check_set(S, "S", true)) ||
@@ -322,6 +339,21 @@ knng_status knng_expand(const knng_set *S, const knng_graph *G, const knng_set *
         return s;
     return run_merge(R, w, metric, bf16, opts, n, nb, k, nb > 0 ? k1 : 0, 1, nb, out, st, stats,
                      prof);
+}
+
+knng_status knng_expand(const knng_set *S, const knng_graph *G, const knng_set *raw, int32_t k,
+                        knng_metric metric, const knng_opts *opts, knng_graph *out,
+                        void *workspace, size_t workspace_bytes, void *stream,
+                        knng_stats *stats)
+{
+    try {
+        return knng_expand_impl(S, G, raw, k, metric, opts, out, workspace, workspace_bytes, stream,
+                                stats);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
 }
 
 // ---------------------------------------------------------------- merge tree
@@ -393,10 +425,9 @@ size_t tree_merge_ws(const int64_t *starts, int nb, int d, int k, int kin_max, k
 
 } // namespace
 
-extern "C" size_t knng_merge_tree_workspace_size(int64_t n, int32_t d, int32_t nblocks,
-                                                 const int64_t *starts, int32_t k,
-                                                 int32_t kin_max, knng_metric metric,
-                                                 const knng_opts *opts)
+static size_t knng_merge_tree_workspace_size_impl(int64_t n, int32_t d, int32_t nblocks,
+                                                  const int64_t *starts, int32_t k, int32_t kin_max,
+                                                  knng_metric metric, const knng_opts *opts)
 {
     if (!starts || nblocks < 2 || n < 2 || d < 1 || k < 1 || !opts || starts[nblocks] != n)
         return 0;
@@ -407,11 +438,25 @@ extern "C" size_t knng_merge_tree_workspace_size(int64_t n, int32_t d, int32_t n
     return c.off + 256 + tree_merge_ws(starts, nblocks, d, k, kin, metric, opts);
 }
 
-extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
-                                       const knng_graph *G, int32_t nblocks, int32_t k,
-                                       knng_metric metric, const knng_opts *opts,
-                                       knng_graph *out, void *workspace, size_t workspace_bytes,
-                                       void *stream, knng_stats *stats)
+extern "C" size_t knng_merge_tree_workspace_size(int64_t n, int32_t d, int32_t nblocks,
+                                                 const int64_t *starts, int32_t k,
+                                                 int32_t kin_max, knng_metric metric,
+                                                 const knng_opts *opts)
+{
+    try {
+        return knng_merge_tree_workspace_size_impl(n, d, nblocks, starts, k, kin_max, metric, opts);
+    } catch (const std::bad_alloc &) {
+        return 0;
+    } catch (...) {
+        return 0;
+    }
+}
+
+static knng_status knng_merge_tree_impl(const knng_set *X, const int64_t *starts,
+                                        const knng_graph *G, int32_t nblocks, int32_t k,
+                                        knng_metric metric, const knng_opts *opts, knng_graph *out,
+                                        void *workspace, size_t workspace_bytes, void *stream,
+                                        knng_stats *stats)
 {
     knng_status s;
     if ((s = check_metric(metric)) || (s = check_set(X, "X")) || (s = check_opts(opts, k)))
@@ -484,7 +529,7 @@ extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
             const size_t ws_bytes = plan[level][i];
             off += ws_bytes;
             hipStream_t sx = streams[i];
-            workers.emplace_back([=, &one, &rc, &msg]() {
+            auto work = [=, &one, &rc, &msg]() {
                 if (hipSetDevice(device) != hipSuccess) {
                     rc[i] = KNNG_EDEVICE;
                     msg[i] = "hipSetDevice failed in a merge-tree worker";
@@ -500,7 +545,13 @@ extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
                                    &one[i]);
                 if (rc[i] != KNNG_OK)
                     msg[i] = g_err;
-            });
+            };
+            // a thread that cannot be started: the merge runs here instead
+            try {
+                workers.emplace_back(work);
+            } catch (...) {
+                work();
+            }
         }
         for (std::thread &w : workers)
             w.join();
@@ -568,6 +619,22 @@ extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
     return ok();
 }
 
+extern "C" knng_status knng_merge_tree(const knng_set *X, const int64_t *starts,
+                                       const knng_graph *G, int32_t nblocks, int32_t k,
+                                       knng_metric metric, const knng_opts *opts,
+                                       knng_graph *out, void *workspace, size_t workspace_bytes,
+                                       void *stream, knng_stats *stats)
+{
+    try {
+        return knng_merge_tree_impl(X, starts, G, nblocks, k, metric, opts, out, workspace,
+                                    workspace_bytes, stream, stats);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
+}
+
 // ---------------------------------------------------------------- H-Merge
 namespace {
 
@@ -633,8 +700,8 @@ knng_opts layer_opts(const knng_opts *o, int level)
 
 } // namespace
 
-extern "C" size_t knng_hmerge_workspace_size(int64_t n, int32_t d, int32_t k, int64_t n_top,
-                                            knng_metric metric, const knng_opts *opts)
+static size_t knng_hmerge_workspace_size_impl(int64_t n, int32_t d, int32_t k, int64_t n_top,
+                                              knng_metric metric, const knng_opts *opts)
 {
     if (n < 2 || d < 1 || k < 1 || n_top < 2 || !opts)
         return 0;
@@ -653,10 +720,21 @@ extern "C" size_t knng_hmerge_workspace_size(int64_t n, int32_t d, int32_t k, in
     return c.off + best + 256;
 }
 
-extern "C" knng_status knng_hmerge(const knng_set *X, int32_t k, int64_t n_top,
-                                   knng_metric metric, const knng_opts *opts, knng_graph *out,
-                                   void *workspace, size_t workspace_bytes, void *stream,
-                                   knng_stats *stats)
+extern "C" size_t knng_hmerge_workspace_size(int64_t n, int32_t d, int32_t k, int64_t n_top,
+                                            knng_metric metric, const knng_opts *opts)
+{
+    try {
+        return knng_hmerge_workspace_size_impl(n, d, k, n_top, metric, opts);
+    } catch (const std::bad_alloc &) {
+        return 0;
+    } catch (...) {
+        return 0;
+    }
+}
+
+static knng_status knng_hmerge_impl(const knng_set *X, int32_t k, int64_t n_top, knng_metric metric,
+                                    const knng_opts *opts, knng_graph *out, void *workspace,
+                                    size_t workspace_bytes, void *stream, knng_stats *stats)
 {
     knng_status s;
     if ((s = check_metric(metric)) || (s = check_set(X, "X")) || (s = check_opts(opts, k)))
@@ -736,6 +814,21 @@ extern "C" knng_status knng_hmerge(const knng_set *X, int32_t k, int64_t n_top,
     return ok();
 }
 
+extern "C" knng_status knng_hmerge(const knng_set *X, int32_t k, int64_t n_top,
+                                   knng_metric metric, const knng_opts *opts, knng_graph *out,
+                                   void *workspace, size_t workspace_bytes, void *stream,
+                                   knng_stats *stats)
+{
+    try {
+        return knng_hmerge_impl(X, k, n_top, metric, opts, out, workspace, workspace_bytes, stream,
+                                stats);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
+}
+
 size_t knng_bruteforce_workspace_size(int64_t n1, int64_t n2, int32_t d, int32_t k,
                                       int32_t kin1, int32_t kin2, knng_metric metric)
 {
@@ -751,10 +844,10 @@ size_t knng_bruteforce_workspace_size(int64_t n1, int64_t n2, int32_t d, int32_t
     return c.off + 256;
 }
 
-knng_status knng_merge_bruteforce(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
-                                  const knng_graph *G2, int32_t k, knng_metric metric,
-                                  knng_graph *out, void *workspace, size_t workspace_bytes,
-                                  void *stream)
+static knng_status knng_merge_bruteforce_impl(const knng_set *S1, const knng_graph *G1,
+                                              const knng_set *S2, const knng_graph *G2, int32_t k,
+                                              knng_metric metric, knng_graph *out, void *workspace,
+                                              size_t workspace_bytes, void *stream)
 {
     knng_status s;
     if ((s = check_metric(metric)) || (s = check_set(S1, "S1")) || (s = check_set(S2, "S2")))
@@ -793,6 +886,21 @@ knng_status knng_merge_bruteforce(const knng_set *S1, const knng_graph *G1, cons
     return ok();
 }
 
+knng_status knng_merge_bruteforce(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
+                                  const knng_graph *G2, int32_t k, knng_metric metric,
+                                  knng_graph *out, void *workspace, size_t workspace_bytes,
+                                  void *stream)
+{
+    try {
+        return knng_merge_bruteforce_impl(S1, G1, S2, G2, k, metric, out, workspace,
+                                          workspace_bytes, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
+}
+
 size_t knng_exact_graph_workspace_size(int64_t n, int32_t d, int32_t k, knng_metric metric)
 {
     if (n < 2 || d < 1 || k < 1)
@@ -805,8 +913,9 @@ size_t knng_exact_graph_workspace_size(int64_t n, int32_t d, int32_t k, knng_met
     return c.off + 256;
 }
 
-knng_status knng_exact_graph(const knng_set *S, int32_t k, knng_metric metric, knng_graph *out,
-                             void *workspace, size_t workspace_bytes, void *stream)
+static knng_status knng_exact_graph_impl(const knng_set *S, int32_t k, knng_metric metric,
+                                         knng_graph *out, void *workspace, size_t workspace_bytes,
+                                         void *stream)
 {
     knng_status s;
     if ((s = check_metric(metric)) || (s = check_set(S, "S")))
@@ -837,6 +946,18 @@ knng_status knng_exact_graph(const knng_set *S, int32_t k, knng_metric metric, k
                          st));
     HIP_TRY(hipStreamSynchronize(st));
     return ok();
+}
+
+knng_status knng_exact_graph(const knng_set *S, int32_t k, knng_metric metric, knng_graph *out,
+                             void *workspace, size_t workspace_bytes, void *stream)
+{
+    try {
+        return knng_exact_graph_impl(S, k, metric, out, workspace, workspace_bytes, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
 }
 
 } // extern "C"

@@ -29,6 +29,8 @@
 
 #include "knng_host.h"
 
+#include <new>
+
 using namespace knng;
 using namespace knng::host;
 
@@ -340,6 +342,29 @@ void finish_request(knng_server *s)
     s->cv_done.notify_all();
 }
 
+// run_request, with a host exception (an allocation that failed) turned into
+// a failed result for every ticket of the merge instead of leaving them running
+knng_status run_request_guarded(knng_server *s, Slot &sl, const std::vector<uint64_t> &t)
+{
+    try {
+        return run_request(s, sl, t);
+    } catch (...) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const double t_done = now_us(s->t0);
+        for (uint64_t ticket : t) {
+            auto it = s->reqs.find(ticket);
+            if (it == s->reqs.end() || it->second.state == Q_DONE)
+                continue;
+            it->second.state = Q_DONE;
+            it->second.rc = KNNG_ENOMEM;
+            it->second.err = "host memory exhausted while merging the request";
+            it->second.info.done_us = t_done;
+        }
+        sl.fresh = true;  // the slot state is unknown: initialise it in full next time
+        return fail(KNNG_ENOMEM, "host memory exhausted while merging a request");
+    }
+}
+
 void slot_main(knng_server *s, Slot *sl)
 {
     (void)hipSetDevice(s->device);
@@ -357,7 +382,7 @@ void slot_main(knng_server *s, Slot *sl)
         }
         {
             std::shared_lock<std::shared_mutex> state(s->state_mu);
-            (void)run_request(s, *sl, t);
+            (void)run_request_guarded(s, *sl, t);
         }
         finish_request(s);
     }
@@ -379,8 +404,9 @@ knng_status drain(knng_server *s)
 
 extern "C" {
 
-size_t knng_server_bytes(int64_t capacity, int64_t max_request, int32_t d, int32_t k, int32_t kin,
-                         knng_metric metric, const knng_opts *opts, int32_t slots)
+static size_t knng_server_bytes_impl(int64_t capacity, int64_t max_request, int32_t d, int32_t k,
+                                     int32_t kin, knng_metric metric, const knng_opts *opts,
+                                     int32_t slots)
 {
     if (capacity < 2 || max_request < 1 || d < 1 || k < 1 || !opts || slots < 1)
         return 0;
@@ -396,9 +422,21 @@ size_t knng_server_bytes(int64_t capacity, int64_t max_request, int32_t d, int32
     return store_bytes(probe) + (size_t)slots * slot_bytes(probe);
 }
 
-knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_t k,
-                               knng_metric metric, const knng_opts *opts,
-                               const knng_server_config *cfg, knng_server **out)
+size_t knng_server_bytes(int64_t capacity, int64_t max_request, int32_t d, int32_t k, int32_t kin,
+                         knng_metric metric, const knng_opts *opts, int32_t slots)
+{
+    try {
+        return knng_server_bytes_impl(capacity, max_request, d, k, kin, metric, opts, slots);
+    } catch (const std::bad_alloc &) {
+        return 0;
+    } catch (...) {
+        return 0;
+    }
+}
+
+static knng_status knng_server_create_impl(const knng_set *base, const knng_graph *G, int32_t k,
+                                           knng_metric metric, const knng_opts *opts,
+                                           const knng_server_config *cfg, knng_server **out)
 {
     knng_status rc;
     if (!out)
@@ -486,15 +524,34 @@ knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_
     }
     s->m_base = s->reserved = m;
     s->t0 = std::chrono::steady_clock::now();
-    if (!s->manual)
-        for (Slot &sl : s->slots)
-            sl.th = std::thread(slot_main, s, &sl);
+    if (!s->manual) {
+        try {
+            for (Slot &sl : s->slots)
+                sl.th = std::thread(slot_main, s, &sl);
+        } catch (...) {
+            knng_server_destroy(s);  // stops and joins the slots that did start
+            return fail(KNNG_EDEVICE, "could not start the slot threads");
+        }
+    }
     *out = s;
     return ok();
 }
 
-knng_status knng_server_submit(knng_server *s, const float *raw, int64_t n_raw, uint64_t req_id,
-                               uint64_t *ticket)
+knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_t k,
+                               knng_metric metric, const knng_opts *opts,
+                               const knng_server_config *cfg, knng_server **out)
+{
+    try {
+        return knng_server_create_impl(base, G, k, metric, opts, cfg, out);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
+}
+
+static knng_status knng_server_submit_impl(knng_server *s, const float *raw, int64_t n_raw,
+                                           uint64_t req_id, uint64_t *ticket)
 {
     if (!s || !ticket)
         return fail(KNNG_EINVAL, "server or ticket is NULL");
@@ -562,7 +619,19 @@ knng_status knng_server_submit(knng_server *s, const float *raw, int64_t n_raw, 
     return ok();
 }
 
-knng_status knng_server_step(knng_server *s, int32_t *ran)
+knng_status knng_server_submit(knng_server *s, const float *raw, int64_t n_raw, uint64_t req_id,
+                               uint64_t *ticket)
+{
+    try {
+        return knng_server_submit_impl(s, raw, n_raw, req_id, ticket);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
+}
+
+static knng_status knng_server_step_impl(knng_server *s, int32_t *ran)
 {
     if (!s)
         return fail(KNNG_EINVAL, "server is NULL");
@@ -583,14 +652,25 @@ knng_status knng_server_step(knng_server *s, int32_t *ran)
     knng_status rc;
     {
         std::shared_lock<std::shared_mutex> state(s->state_mu);
-        rc = run_request(s, s->slots[0], t);
+        rc = run_request_guarded(s, s->slots[0], t);
     }
     finish_request(s);
     return rc == KNNG_OK ? ok() : rc;
 }
 
-knng_status knng_server_wait(knng_server *s, uint64_t ticket, int64_t timeout_us, int32_t *ids,
-                             float *dist, knng_request_info *info)
+knng_status knng_server_step(knng_server *s, int32_t *ran)
+{
+    try {
+        return knng_server_step_impl(s, ran);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
+}
+
+static knng_status knng_server_wait_impl(knng_server *s, uint64_t ticket, int64_t timeout_us,
+                                         int32_t *ids, float *dist, knng_request_info *info)
 {
     if (!s)
         return fail(KNNG_EINVAL, "server is NULL");
@@ -640,7 +720,19 @@ knng_status knng_server_wait(knng_server *s, uint64_t ticket, int64_t timeout_us
     return ok();
 }
 
-knng_status knng_server_snapshot(knng_server *s, knng_graph *out, int64_t *n_rows)
+knng_status knng_server_wait(knng_server *s, uint64_t ticket, int64_t timeout_us, int32_t *ids,
+                             float *dist, knng_request_info *info)
+{
+    try {
+        return knng_server_wait_impl(s, ticket, timeout_us, ids, dist, info);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
+}
+
+static knng_status knng_server_snapshot_impl(knng_server *s, knng_graph *out, int64_t *n_rows)
 {
     if (!s)
         return fail(KNNG_EINVAL, "server is NULL");
@@ -669,7 +761,18 @@ knng_status knng_server_snapshot(knng_server *s, knng_graph *out, int64_t *n_row
     return ok();
 }
 
-knng_status knng_server_rebase(knng_server *s)
+knng_status knng_server_snapshot(knng_server *s, knng_graph *out, int64_t *n_rows)
+{
+    try {
+        return knng_server_snapshot_impl(s, out, n_rows);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
+}
+
+static knng_status knng_server_rebase_impl(knng_server *s)
 {
     if (!s)
         return fail(KNNG_EINVAL, "server is NULL");
@@ -698,6 +801,17 @@ knng_status knng_server_rebase(knng_server *s)
         s->committed = 0;
     }
     return ok();
+}
+
+knng_status knng_server_rebase(knng_server *s)
+{
+    try {
+        return knng_server_rebase_impl(s);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
 }
 
 knng_status knng_server_status(knng_server *s, int64_t *base_rows, int64_t *committed_rows,
