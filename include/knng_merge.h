@@ -53,7 +53,7 @@ extern "C" {
 typedef enum {
     KNNG_OK = 0,
     KNNG_EINVAL = 1,  /* bad argument or invalid input data */
-    KNNG_ENOMEM = 2,  /* workspace smaller than required */
+    KNNG_ENOMEM = 2,  /* workspace smaller than required, or host memory exhausted */
     KNNG_EDEVICE = 3, /* a HIP call failed; see knng_last_error() */
     KNNG_EBUSY = 4,   /* knng_server_wait: the request has not finished in time */
 } knng_status;
