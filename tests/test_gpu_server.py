@@ -250,3 +250,32 @@ def test_server_errors(hip):
             srv.wait(t3, 10)                          # already collected
     finally:
         srv.close()
+
+
+def test_many_requests_on_one_slot_each_equal_the_oracle(hip):
+    # one slot keeps its merge state between requests (tags of earlier merges
+    # read as "never", only rows they changed are restored): 25 requests in a
+    # row, sizes from 1 to 60 rows, each must equal its merge on fresh state
+    k, s, seed = 8, 6, 17
+    sizes = [int(v) for v in synth.rng(140).integers(1, 61, 25)]
+    base, reqs = _sets(900, sizes, 7, 141)
+    m = base.shape[0]
+    G = oracle.exact_graph(base, k)
+    srv = _server(hip, base, G, k, "l2", capacity=m + sum(sizes), max_request=64, slots=0,
+                  sample=s, seed=seed)
+    try:
+        first, results = m, []
+        for i, r in enumerate(reqs):
+            t = srv.submit(dev(r), 500 + i)
+            assert srv.step()
+            ids, dist, info = srv.wait(t, len(r))
+            oi, od, ost = _alone(base, G, r, k, "l2", first, s, seed, 500 + i)
+            assert info["rounds"] == ost["rounds"]
+            assert_same_graph(ids.numpy(), dist.numpy(), oi[m:], od[m:], f"request {i}")
+            results.append((oi, od, ost, first, len(r)))
+            first += len(r)
+        si, sd = srv.snapshot()
+        ei, ed = _fold(G, results, m, k)
+        assert_same_graph(host(si), host(sd), ei, ed, "resident graph after 25 requests")
+    finally:
+        srv.close()
