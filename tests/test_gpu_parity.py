@@ -391,3 +391,39 @@ def test_hmerge_invalid_inputs(hip):
         hip.hmerge(dev(X), 8, 10, "l2", keep_ratio=0.9)  # keeps more than a k/2 layer holds
     with pytest.raises(hip.KnngError, match="EINVAL"):
         hip.hmerge(dev(X), 100, 10, "l2")               # k > n - 1
+
+
+# ---------------------------------------------------------------- limits
+
+@pytest.mark.parametrize("case", ["k64_s32", "d1", "one_row_set", "k_near_n"])
+def test_smerge_limits_identical_to_oracle(hip, case):
+    # the largest list and sample (3s + k = 160 members per neighbourhood),
+    # one coordinate, a second set of one row, and k close to n - 1
+    g = synth.rng(150)
+    if case == "k64_s32":
+        n1, n2, d, k, s, kin1, kin2 = 400, 333, 3, 64, 32, 64, 64
+    elif case == "d1":
+        n1, n2, d, k, s, kin1, kin2 = 300, 257, 1, 12, 8, 12, 12
+    elif case == "one_row_set":
+        n1, n2, d, k, s, kin1, kin2 = 60, 1, 5, 10, 6, 10, 0
+    else:
+        n1, n2, d, k, s, kin1, kin2 = 20, 18, 6, 33, 10, 19, 17
+    S1 = g.standard_normal((n1, d)).astype(np.float32)
+    S2 = (g.standard_normal((n2, d)) + 0.5).astype(np.float32)
+    if case == "one_row_set":
+        # a one-row set has no neighbours of its own: merged as the raw side
+        # of J-Merge instead
+        G = oracle.exact_graph(S1, kin1)
+        (gi, gd, gst), (oi, od, ost) = _jmerge_both(hip, S1, G, S2, k, "l2", sample=s, seed=4)
+        assert_same_graph(gi, gd, oi, od, case)
+        return
+    G1 = oracle.exact_graph(S1, kin1)
+    G2 = oracle.exact_graph(S2, kin2)
+    precs = ("fp32", "bf16") if case == "k64_s32" else ("fp32",)
+    oi, od, ost = oracle.smerge(S1, G1, S2, G2, k, "l2", sample=s, seed=12)
+    for prec in precs:
+        gi, gd, gst = hip.merge(dev(S1), (dev(G1[0]), dev(G1[1])), dev(S2),
+                                (dev(G2[0]), dev(G2[1])), k, "l2", sample=s, seed=12,
+                                precision=prec)
+        assert_same_graph(host(gi), host(gd), oi, od, f"{case} {prec}")
+        _same_stats(gst, ost)
