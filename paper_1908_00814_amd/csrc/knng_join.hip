@@ -85,10 +85,20 @@ struct WaveLds {
 // The FP32 carve (bf = false) leaves out the BF16 arrays and holds QF queue
 // words: 8.3 KB per wave for s = k = 20, so that four 4-wave blocks fit the
 // CU's 160 KB of LDS (4 waves per SIMD).
+// first region of a wave's carve: the staged coordinates (FP32 path), or the
+// BF16 path's 16 x 16 grid of a tile's rescored distances (1 KB) and offer
+// flags (256 bytes)
+constexpr int GRID_BYTES = 16 * 16 * 4 + 16 * 16;
+__host__ __device__ inline int stage_bytes(int GS, bool bf)
+{
+    return bf && CH * GS * 4 < GRID_BYTES ? GRID_BYTES : CH * GS * 4;
+}
+
 __host__ __device__ inline int wave_lds_bytes(int GS, int s, int k, bool bf)
 {
-    int b = bf ? CH * GS * 4 + GS * 8 + QCAP * 8 + 4 * GS * 4 + (2 * s + 3 * (k + s) + QF) * 4
-               : CH * GS * 4 + GS * 8 + QF * 8 + 2 * GS * 4 + (2 * s + 3 * (k + s) + QF) * 4;
+    const int st = stage_bytes(GS, bf);
+    int b = bf ? st + GS * 8 + QCAP * 8 + 4 * GS * 4 + (2 * s + 3 * (k + s) + QF) * 4
+               : st + GS * 8 + QF * 8 + 2 * GS * 4 + (2 * s + 3 * (k + s) + QF) * 4;
     return (b + 15) / 16 * 16;
 }
 
@@ -96,7 +106,7 @@ __device__ inline WaveLds carve_lds(unsigned char *base, int GS, int s, int k, b
 {
     WaveLds L;
     L.vecT = reinterpret_cast<float *>(base);
-    L.gw = reinterpret_cast<uint64_t *>(base + CH * GS * 4);
+    L.gw = reinterpret_cast<uint64_t *>(base + stage_bytes(GS, bf));
     L.q64 = L.gw + GS;
     L.grp = reinterpret_cast<int32_t *>(L.q64 + (bf ? QCAP : QF));
     L.gnorm = reinterpret_cast<float *>(L.grp + GS);
@@ -292,6 +302,74 @@ __device__ __forceinline__ void insert_into(const RoundArgs &a, int64_t dst, uin
     // dst and the key's id are neighbourhood members, range-checked when the
     // neighbourhood was formed
     if (bounded_insert<KB>(a.L + dst * a.k, a.k, key, true, a.worst + dst, a.ctr + C_ERR))
+        a.dtag[dst] = a.tag0 + a.round + 1;
+}
+
+// UpdateNN of several proposals for one list by one lane: one read of the
+// list, then one compare-and-swap per proposal on the maximum of the lane's
+// local view of the list (read again only after a failed swap).  Proposal t
+// (bit t of `have`) is key(t).  The local view only ever holds values at or
+// above the list's (slot values only decrease, and the lane's own swaps are
+// exact), so each successful swap replaces the true maximum, as in
+// bounded_insert, and the same argument keeps duplicates out.
+template <int KB, class KeyFn>
+__device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t have, KeyFn key_of)
+{
+    constexpr int B = KB <= 16 ? KB : (KB == 32 ? 20 : 16);
+    const int cap = a.k;
+    if (cap > B) {
+        for (; have; have &= have - 1)
+            insert_into<KB>(a, dst, key_of(__builtin_ctz(have)));
+        return;
+    }
+    uint64_t *slots = a.L + dst * cap;
+    bool any = false;
+    for (int spin = 0; spin < SPIN_BUDGET && have; spin++) {
+        uint64_t v[B];
+#pragma unroll
+        for (int j = 0; j < B; j++)
+            v[j] = j < cap ? ld_agent(slots + j) : 0ull;
+        bool failed = false;
+        while (have) {
+            const uint64_t key = key_of(__builtin_ctz(have));
+            const uint64_t kid = key_strip(key);
+            uint64_t mx = 0, second = 0;
+            int mj = 0;
+            bool dup = false;
+#pragma unroll
+            for (int j = 0; j < B; j++) {
+                if (j < cap) {
+                    dup |= key_strip(v[j]) == kid;
+                    if (v[j] > mx) {
+                        second = mx;
+                        mx = v[j];
+                        mj = j;
+                    } else if (v[j] > second) {
+                        second = v[j];
+                    }
+                }
+            }
+            if (dup || key >= mx) {
+                have &= have - 1;
+                continue;
+            }
+            if (!cas64(slots + mj, mx, key)) {
+                failed = true;
+                break;
+            }
+#pragma unroll
+            for (int j = 0; j < B; j++)
+                v[j] = j == mj ? key : v[j];
+            atomic_min_u64(a.worst + dst, key > second ? key_strip(key) : key_strip(second));
+            any = true;
+            have &= have - 1;
+        }
+        if (!failed)
+            break;
+    }
+    if (have)
+        atomicOr((unsigned long long *)(a.ctr + C_ERR), (unsigned long long)ERR_SPIN);
+    if (any)
         a.dtag[dst] = a.tag0 + a.round + 1;
 }
 
@@ -653,19 +731,25 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
                         qn += __popcll(m);
                     }
                 }
-                // rescore in canonical FP32 (unless certified), then insert
-                // (UpdateNN both ways)
+                // rescore in canonical FP32 (unless certified) into the tile's
+                // 16 x 16 grid of distances and offer flags, then insert
+                // (UpdateNN both ways) member by member: one lane per tile row
+                // and per tile column offers that member its proposals, so no
+                // two lanes race on one list (but a member that is both)
+                static_assert(TMAX == 1, "the insert grid holds one tile");
+                float *gl = L.vecT;
+                uint8_t *gflag = reinterpret_cast<uint8_t *>(L.vecT) + 16 * 16 * 4;
+                const int rb = tl[0] & 0xFF, cb = (tl[0] >> 8) & 0xFF;
+                __builtin_amdgcn_wave_barrier();
+                reinterpret_cast<uint32_t *>(gflag)[lane] = 0u;
                 __builtin_amdgcn_wave_barrier();
                 for (int e0 = 0; e0 < qn; e0 += WAVE) {
                     const int e = e0 + lane;
                     bool gp = false, gq = false;
-                    int32_t pp = 0, qq = 0;
-                    uint64_t kp = 0, kqk = 0;
                     if (e < qn) {
                         const uint64_t w = qw[e];
                         const int sr = (int)(w & 0xFF), sc = (int)((w >> 8) & 0xFF);
-                        pp = L.grp[sr];
-                        qq = L.grp[sc];
+                        const int32_t pp = L.grp[sr], qq = L.grp[sc];
                         const float db = __uint_as_float((uint32_t)(w >> 32));
                         float D = db;
                         if (!(signbit(L.gerr[sr]) && signbit(L.gerr[sc]))) {
@@ -684,16 +768,33 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
                         float l = D;
                         if (METRIC == M_COS)
                             l = cos_finish(D, L.gnorm[sr], L.gnorm[sc]);
-                        kp = make_key(l, (uint32_t)qq, F_NEW | F_FRESH);
-                        kqk = make_key(l, (uint32_t)pp, F_NEW | F_FRESH);
                         gp = ((w >> 16) & 1) != 0;
                         gq = ((w >> 17) & 1) != 0;
+                        const int cell = (sr - rb) * 16 + (sc - cb);
+                        gl[cell] = l;
+                        gflag[cell] = (uint8_t)((gp ? 1 : 0) | (gq ? 2 : 0));
                     }
                     n_attempt += __popcll(__ballot(gp)) + __popcll(__ballot(gq));
-                    if (gp)
-                        insert_into<KB>(a, pp, kp);
-                    if (gq)
-                        insert_into<KB>(a, qq, kqk);
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane < 32) {
+                    const bool rowside = lane < 16;
+                    const int j = lane & 15;
+                    const int slot = (rowside ? rb : cb) + j;
+                    const int32_t me = slot < g.GP ? L.grp[slot] : -1;
+                    uint32_t have = 0;
+                    if (me >= 0) {
+                        for (int t = 0; t < 16; t++) {
+                            const int cell = rowside ? j * 16 + t : t * 16 + j;
+                            have |= (uint32_t)((gflag[cell] >> (rowside ? 0 : 1)) & 1) << t;
+                        }
+                    }
+                    if (have)
+                        insert_local<KB>(a, me, have, [&](int t) {
+                            const int cell = rowside ? j * 16 + t : t * 16 + j;
+                            const int ps = (rowside ? cb : rb) + t;
+                            return make_key(gl[cell], (uint32_t)L.grp[ps], F_NEW | F_FRESH);
+                        });
                 }
                 __builtin_amdgcn_wave_barrier();
             }
