@@ -86,12 +86,13 @@ struct WaveLds {
 // words: 8.3 KB per wave for s = k = 20, so that four 4-wave blocks fit the
 // CU's 160 KB of LDS (4 waves per SIMD).
 // first region of a wave's carve: the staged coordinates (FP32 path), or the
-// BF16 path's 16 x 16 grid of a tile's rescored distances (1 KB) and offer
-// flags (256 bytes)
-constexpr int GRID_BYTES = 16 * 16 * 4 + 16 * 16;
+// BF16 path's two insert grids, each a tile's 16 x 16 rescored distances
+// (1 KB), offer flags (256 bytes) and the ids of its 16 row and 16 column
+// members (128 bytes)
+constexpr int GRID_BYTES = 16 * 16 * 4 + 16 * 16 + 32 * 4;
 __host__ __device__ inline int stage_bytes(int GS, bool bf)
 {
-    return bf && CH * GS * 4 < GRID_BYTES ? GRID_BYTES : CH * GS * 4;
+    return bf && CH * GS * 4 < 2 * GRID_BYTES ? 2 * GRID_BYTES : CH * GS * 4;
 }
 
 __host__ __device__ inline int wave_lds_bytes(int GS, int s, int k, bool bf)
@@ -623,6 +624,41 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
     const int koff = 8 * (lane >> 4);  // this lane's 8 coordinates of a 32-step
     uint64_t n_pairs = 0, n_gather = 0, n_attempt = 0, n_rescore = 0, n_viol = 0;
     int maxg = 0;
+    // Insert grids: a tile's proposals wait in grid 0 until the next tile (of
+    // this row or a later one) fills grid 1; then lanes 0-31 offer grid 0's
+    // and lanes 32-63 grid 1's, one lane per member (row members by lanes
+    // 0-15 of a half, column members by 16-31), so the two lists' round trips
+    // overlap.  A member of both grids is offered by two lanes, which the
+    // insert's CAS keeps correct.
+    auto grid_at = [&](int gi) { return reinterpret_cast<unsigned char *>(L.vecT) + gi * GRID_BYTES; };
+    auto offer_grids = [&](int ng) {
+        __builtin_amdgcn_wave_barrier();
+        const int gi = lane >> 5;
+        if (gi < ng) {
+            const unsigned char *gb = grid_at(gi);
+            const float *gl = reinterpret_cast<const float *>(gb);
+            const uint8_t *gflag = gb + 16 * 16 * 4;
+            const int32_t *gid = reinterpret_cast<const int32_t *>(gflag + 16 * 16);
+            const bool rowside = (lane & 31) < 16;
+            const int j = lane & 15;
+            const int32_t me = gid[rowside ? j : 16 + j];
+            uint32_t have = 0;
+            if (me >= 0) {
+                for (int t = 0; t < 16; t++) {
+                    const int cell = rowside ? j * 16 + t : t * 16 + j;
+                    have |= (uint32_t)((gflag[cell] >> (rowside ? 0 : 1)) & 1) << t;
+                }
+            }
+            if (have)
+                insert_local<KB>(a, me, have, [&](int t) {
+                    const int cell = rowside ? j * 16 + t : t * 16 + j;
+                    return make_key(gl[cell], (uint32_t)gid[rowside ? 16 + t : t],
+                                    F_NEW | F_FRESH);
+                });
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    bool pending = false;  // grid 0 holds a tile not yet offered
     const int64_t nwaves = (int64_t)gridDim.x * JOIN_WAVES;
     const int64_t wave0 = (int64_t)blockIdx.x * JOIN_WAVES + threadIdx.x / WAVE;
     // rows (or active-list entries) wave0 + j*nwaves, 64 at a time; only rows
@@ -731,17 +767,22 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
                         qn += __popcll(m);
                     }
                 }
-                // rescore in canonical FP32 (unless certified) into the tile's
-                // 16 x 16 grid of distances and offer flags, then insert
-                // (UpdateNN both ways) member by member: one lane per tile row
-                // and per tile column offers that member its proposals, so no
-                // two lanes race on one list (but a member that is both)
-                static_assert(TMAX == 1, "the insert grid holds one tile");
-                float *gl = L.vecT;
-                uint8_t *gflag = reinterpret_cast<uint8_t *>(L.vecT) + 16 * 16 * 4;
+                // rescore in canonical FP32 (unless certified) into a 16 x 16
+                // grid of distances and offer flags with the tile's member
+                // ids; the grids are then offered (UpdateNN both ways) member
+                // by member, two tiles at a time
+                static_assert(TMAX == 1, "an insert grid holds one tile");
+                unsigned char *gb = grid_at(pending ? 1 : 0);
+                float *gl = reinterpret_cast<float *>(gb);
+                uint8_t *gflag = gb + 16 * 16 * 4;
+                int32_t *gid = reinterpret_cast<int32_t *>(gflag + 16 * 16);
                 const int rb = tl[0] & 0xFF, cb = (tl[0] >> 8) & 0xFF;
                 __builtin_amdgcn_wave_barrier();
                 reinterpret_cast<uint32_t *>(gflag)[lane] = 0u;
+                if (lane < 32) {
+                    const int slot = (lane < 16 ? rb : cb) + (lane & 15);
+                    gid[lane] = slot < g.GP ? L.grp[slot] : -1;
+                }
                 __builtin_amdgcn_wave_barrier();
                 for (int e0 = 0; e0 < qn; e0 += WAVE) {
                     const int e = e0 + lane;
@@ -776,31 +817,15 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
                     }
                     n_attempt += __popcll(__ballot(gp)) + __popcll(__ballot(gq));
                 }
-                __builtin_amdgcn_wave_barrier();
-                if (lane < 32) {
-                    const bool rowside = lane < 16;
-                    const int j = lane & 15;
-                    const int slot = (rowside ? rb : cb) + j;
-                    const int32_t me = slot < g.GP ? L.grp[slot] : -1;
-                    uint32_t have = 0;
-                    if (me >= 0) {
-                        for (int t = 0; t < 16; t++) {
-                            const int cell = rowside ? j * 16 + t : t * 16 + j;
-                            have |= (uint32_t)((gflag[cell] >> (rowside ? 0 : 1)) & 1) << t;
-                        }
-                    }
-                    if (have)
-                        insert_local<KB>(a, me, have, [&](int t) {
-                            const int cell = rowside ? j * 16 + t : t * 16 + j;
-                            const int ps = (rowside ? cb : rb) + t;
-                            return make_key(gl[cell], (uint32_t)L.grp[ps], F_NEW | F_FRESH);
-                        });
-                }
-                __builtin_amdgcn_wave_barrier();
+                if (pending)
+                    offer_grids(2);
+                pending = !pending;
             }
         }
         }
     }
+    if (pending)
+        offer_grids(1);
     flush_counters(a, n_pairs, n_gather, n_attempt, n_rescore, n_viol, maxg);
 }
 
