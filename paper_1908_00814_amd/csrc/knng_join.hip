@@ -325,6 +325,7 @@ __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t ha
     }
     uint64_t *slots = a.L + dst * cap;
     bool any = false;
+    uint64_t bound = ~0ull;  // an upper bound of the list's maximum after our inserts
     for (int spin = 0; spin < SPIN_BUDGET && have; spin++) {
         uint64_t v[B];
 #pragma unroll
@@ -361,7 +362,7 @@ __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t ha
 #pragma unroll
             for (int j = 0; j < B; j++)
                 v[j] = j == mj ? key : v[j];
-            atomic_min_u64(a.worst + dst, key > second ? key_strip(key) : key_strip(second));
+            bound = key > second ? key_strip(key) : key_strip(second);
             any = true;
             have &= have - 1;
         }
@@ -370,8 +371,11 @@ __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t ha
     }
     if (have)
         atomicOr((unsigned long long *)(a.ctr + C_ERR), (unsigned long long)ERR_SPIN);
-    if (any)
+    if (any) {
+        // the last success's bound is the tightest: lists only improve
+        atomic_min_u64(a.worst + dst, bound);
         a.dtag[dst] = a.tag0 + a.round + 1;
+    }
 }
 
 // Drain a queue of (target row, key) words: every entry is offered to its
