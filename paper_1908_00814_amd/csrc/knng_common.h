@@ -216,7 +216,11 @@ __device__ __forceinline__ void atomic_min_u64(uint64_t *p, uint64_t v)
 // every interleaving of inserts leaves the `cap` smallest distinct keys offered.
 //
 // Slots are loaded in batches (all 20 of a k = 20 list at once) before any
-// decision on them, one memory round trip per batch.  On success, `live_worst` (when given) is lowered to an
+// decision on them, one memory round trip per batch.  The first pass reads
+// through the caches: a stale value is an older, hence larger, value of its
+// slot, which the argument above allows (a stale duplicate was evicted for
+// good, since the list's maximum has been below it ever since), and it can
+// only make the CAS fail; later passes read at device scope.  On success, `live_worst` (when given) is lowered to an
 // upper bound of the new maximum: max(key, largest value read besides M).
 template <int KB>
 __device__ inline bool bounded_insert(uint64_t *slots, int cap, uint64_t key, bool dedupe,
@@ -232,7 +236,8 @@ __device__ inline bool bounded_insert(uint64_t *slots, int cap, uint64_t key, bo
             uint64_t v[B];
 #pragma unroll
             for (int j = 0; j < B; j++)
-                v[j] = j0 + j < cap ? ld_agent(slots + j0 + j) : 0ull;
+                v[j] = j0 + j < cap ? (spin == 0 ? slots[j0 + j] : ld_agent(slots + j0 + j))
+                                    : 0ull;
 #pragma unroll
             for (int j = 0; j < B; j++) {
                 if (j0 + j < cap) {
