@@ -203,9 +203,14 @@ __device__ __forceinline__ void atomic_min_u64(uint64_t *p, uint64_t v)
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A slot is a duplicate of a key when the two agree under the mask: the
+// (distance, id) of a list word, or the whole word of a reverse-reservoir key
+// (whose low bits are the source id).
+constexpr uint64_t DUP_NONE = 0, DUP_ID = ~3ull, DUP_EXACT = ~0ull;
+
 // Insert `key` into the unordered bounded set slots[0..cap) (cap <= KB): when
-// the key is below the current maximum and (if `dedupe`) no slot holds the
-// same (distance, id), the maximum slot is replaced by a CAS.
+// the key is below the current maximum and no slot is a duplicate of it under
+// `dup_mask` (DUP_NONE: no test), the maximum slot is replaced by a CAS.
 //
 // Correctness: slot values only ever decrease and are pairwise distinct, so if
 // the CAS on the slot that held the maximum M of the values read succeeds,
@@ -220,14 +225,15 @@ __device__ __forceinline__ void atomic_min_u64(uint64_t *p, uint64_t v)
 // through the caches: a stale value is an older, hence larger, value of its
 // slot, which the argument above allows (a stale duplicate was evicted for
 // good, since the list's maximum has been below it ever since), and it can
-// only make the CAS fail; later passes read at device scope.  On success, `live_worst` (when given) is lowered to an
-// upper bound of the new maximum: max(key, largest value read besides M).
+// only make the CAS fail; later passes read at device scope.  On success,
+// `live_worst` (when given) is lowered to an upper bound of the new maximum:
+// max(key, largest value read besides M).
 template <int KB>
-__device__ inline bool bounded_insert(uint64_t *slots, int cap, uint64_t key, bool dedupe,
+__device__ inline bool bounded_insert(uint64_t *slots, int cap, uint64_t key, uint64_t dup_mask,
                                       uint64_t *live_worst, uint64_t *err_word)
 {
     constexpr int B = KB <= 16 ? KB : (KB == 32 ? 20 : 16);
-    const uint64_t kid = key_strip(key);
+    const uint64_t kid = key & dup_mask;
     for (int spin = 0; spin < SPIN_BUDGET; spin++) {
         uint64_t mx = 0, second = 0;
         int mj = 0;
@@ -241,7 +247,7 @@ __device__ inline bool bounded_insert(uint64_t *slots, int cap, uint64_t key, bo
 #pragma unroll
             for (int j = 0; j < B; j++) {
                 if (j0 + j < cap) {
-                    dup |= dedupe && key_strip(v[j]) == kid;
+                    dup |= dup_mask != DUP_NONE && (v[j] & dup_mask) == kid;
                     if (v[j] > mx) {
                         second = mx;
                         mx = v[j];

@@ -302,7 +302,7 @@ __device__ __forceinline__ void insert_into(const RoundArgs &a, int64_t dst, uin
 {
     // dst and the key's id are neighbourhood members, range-checked when the
     // neighbourhood was formed
-    if (bounded_insert<KB>(a.L + dst * a.k, a.k, key, true, a.worst + dst, a.ctr + C_ERR))
+    if (bounded_insert<KB>(a.L + dst * a.k, a.k, key, DUP_ID, a.worst + dst, a.ctr + C_ERR))
         a.dtag[dst] = a.tag0 + a.round + 1;
 }
 

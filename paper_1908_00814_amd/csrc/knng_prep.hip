@@ -429,7 +429,7 @@ __device__ inline void commit_row(const CommitArgs &a, const int64_t i)
     if (i < a.m_base) {
         if (!real || id < a.m_base)
             return;
-        bounded_insert<KB>(a.res + i * a.k, a.k, ge, true, nullptr, a.ctr + C_ERR);
+        bounded_insert<KB>(a.res + i * a.k, a.k, ge, DUP_ID, nullptr, a.ctr + C_ERR);
     } else if (lane < a.k) {
         a.res[(a.first + (i - a.m_base)) * a.k + lane] = real ? ge : empty_key(lane);
     }

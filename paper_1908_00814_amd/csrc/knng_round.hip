@@ -145,7 +145,7 @@ __device__ inline void offer_reverse(const RoundArgs &a, int64_t v, int64_t u, i
     const int pos = atomicAdd(a.rfill + 2 * v + kind, 1);
     if (pos < a.s && cas64(slots + pos, empty_key(pos), key))
         return;
-    bounded_insert<MAX_S>(slots, a.s, key, false, nullptr, a.ctr + C_ERR);
+    bounded_insert<MAX_S>(slots, a.s, key, DUP_NONE, nullptr, a.ctr + C_ERR);
 }
 
 // Reverse(G) of round t, one thread per (row u, slot): a sampled edge u -> v
