@@ -196,6 +196,13 @@ __device__ __forceinline__ bool cas64(uint64_t *p, uint64_t expect, uint64_t des
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// As cas64; on failure `expect` receives the word the slot held instead.
+__device__ __forceinline__ bool cas64_seen(uint64_t *p, uint64_t &expect, uint64_t desired)
+{
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int SPIN_BUDGET = 1 << 16;
 
 __device__ __forceinline__ void atomic_min_u64(uint64_t *p, uint64_t v)

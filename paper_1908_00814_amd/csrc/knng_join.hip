@@ -308,11 +308,12 @@ __device__ __forceinline__ void insert_into(const RoundArgs &a, int64_t dst, uin
 
 // UpdateNN of several proposals for one list by one lane: one read of the
 // list, then one compare-and-swap per proposal on the maximum of the lane's
-// local view of the list (read again only after a failed swap).  Proposal t
-// (bit t of `have`) is key(t).  The local view only ever holds values at or
-// above the list's (slot values only decrease, and the lane's own swaps are
-// exact), so each successful swap replaces the true maximum, as in
-// bounded_insert, and the same argument keeps duplicates out.
+// local view of the list; a failed swap returns the slot's current word, which
+// replaces the view's, and the proposal is tried again.  Proposal t (bit t of
+// `have`) is key(t).  Every word of the view is one its slot held at some time
+// before the swap (the lane's own swaps included), which is all the argument
+// of bounded_insert needs: each successful swap replaces the true maximum, and
+// duplicates stay out.
 template <int KB, class KeyFn>
 __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t have, KeyFn key_of)
 {
@@ -326,48 +327,45 @@ __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t ha
     uint64_t *slots = a.L + dst * cap;
     bool any = false;
     uint64_t bound = ~0ull;  // an upper bound of the list's maximum after our inserts
-    for (int spin = 0; spin < SPIN_BUDGET && have; spin++) {
-        uint64_t v[B];
+    uint64_t v[B];
 #pragma unroll
-        for (int j = 0; j < B; j++)
-            v[j] = j < cap ? ld_agent(slots + j) : 0ull;
-        bool failed = false;
-        while (have) {
-            const uint64_t key = key_of(__builtin_ctz(have));
-            const uint64_t kid = key_strip(key);
-            uint64_t mx = 0, second = 0;
-            int mj = 0;
-            bool dup = false;
+    for (int j = 0; j < B; j++)
+        v[j] = j < cap ? ld_agent(slots + j) : 0ull;
+    for (int fails = 0; have && fails < SPIN_BUDGET;) {
+        const uint64_t key = key_of(__builtin_ctz(have));
+        const uint64_t kid = key_strip(key);
+        uint64_t mx = 0, second = 0;
+        int mj = 0;
+        bool dup = false;
 #pragma unroll
-            for (int j = 0; j < B; j++) {
-                if (j < cap) {
-                    dup |= key_strip(v[j]) == kid;
-                    if (v[j] > mx) {
-                        second = mx;
-                        mx = v[j];
-                        mj = j;
-                    } else if (v[j] > second) {
-                        second = v[j];
-                    }
+        for (int j = 0; j < B; j++) {
+            if (j < cap) {
+                dup |= key_strip(v[j]) == kid;
+                if (v[j] > mx) {
+                    second = mx;
+                    mx = v[j];
+                    mj = j;
+                } else if (v[j] > second) {
+                    second = v[j];
                 }
             }
-            if (dup || key >= mx) {
-                have &= have - 1;
-                continue;
-            }
-            if (!cas64(slots + mj, mx, key)) {
-                failed = true;
-                break;
-            }
-#pragma unroll
-            for (int j = 0; j < B; j++)
-                v[j] = j == mj ? key : v[j];
-            bound = key > second ? key_strip(key) : key_strip(second);
-            any = true;
-            have &= have - 1;
         }
-        if (!failed)
-            break;
+        if (dup || key >= mx) {
+            have &= have - 1;
+            continue;
+        }
+        uint64_t seen = mx;
+        const bool ok = cas64_seen(slots + mj, seen, key);
+#pragma unroll
+        for (int j = 0; j < B; j++)
+            v[j] = j == mj ? (ok ? key : seen) : v[j];
+        if (!ok) {
+            fails++;
+            continue;
+        }
+        bound = key > second ? key_strip(key) : key_strip(second);
+        any = true;
+        have &= have - 1;
     }
     if (have)
         atomicOr((unsigned long long *)(a.ctr + C_ERR), (unsigned long long)ERR_SPIN);
