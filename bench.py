@@ -71,6 +71,49 @@ def recall_at10(ids, X, rows, device, metric="l2"):
     return hits / (len(rows) * 10)
 
 
+def fp64_error(X, ids, dist, rows, metric, floor=1e-6):
+    """Error of stored FP32 distances against an FP64 recomputation from the
+    stored FP32 rows (plain definitions): relative above `floor`, absolute
+    below it.  X: host rows; ids/dist: host (n, k) graph; rows: sampled rows."""
+    rel, ab = [], []
+    for i in rows:
+        j = ids[i]
+        ok = j >= 0
+        a = X[i].astype(np.float64)
+        B = X[j[ok]].astype(np.float64)
+        if metric == "l2":
+            e = ((B - a) ** 2).sum(1)
+        elif metric == "l1":
+            e = np.abs(B - a).sum(1)
+        else:
+            e = 1.0 - (B @ a) / (np.linalg.norm(B, axis=1) * np.linalg.norm(a))
+        g = dist[i][ok].astype(np.float64)
+        big = e >= floor
+        rel.extend((np.abs(g[big] - e[big]) / e[big]).tolist())
+        ab.extend(np.abs(g[~big] - e[~big]).tolist())
+    return {"max_rel": float(max(rel)) if rel else 0.0,
+            "p999_rel": float(np.percentile(rel, 99.9)) if rel else 0.0,
+            "max_abs_below_floor": float(max(ab)) if ab else 0.0, "floor": floor,
+            "entries": len(rel) + len(ab), "rows": len(rows)}
+
+
+def host_cpu():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable": usable}
+
+
 JOIN_SOURCES = ["paper_1908_00814_amd/csrc/knng_join.hip", "paper_1908_00814_amd/csrc/knng_common.h",
                 "paper_1908_00814_amd/csrc/knng_internal.h"]
 
@@ -95,31 +138,39 @@ def measured_traffic(kernel):
 
 
 def join_roofline(st, n, d, k, s, prec="fp32"):
-    """Algorithmic bytes of the local-join launches of one merge and the
-    achieved rate over their summed duration."""
-    dp = (d + 3) // 4 * 4
-    db = (d + 31) // 32 * 32
+    """Algorithmic bytes of the local-join launches of one or more merges
+    (summed counters and durations) and the achieved rate:
+      gathers   every neighbourhood member's row once per round,
+                members * (d * b_e + 4) (b_e = 4 for FP32 rows, 2 for bf16;
+                + 4 for its list's worst bound);
+      rescores  BF16 path: the two FP32 rows of every rescored pair,
+                rescored * 2 * d * 4;
+      lists     one read and one write of every list per round,
+                rounds * 2 * n * k * 8.
+    List reads and swaps of the inserts beyond that are implementation
+    traffic, reported apart (insert_scan_bytes: attempts * (8k + 16))."""
+    b_e = 4 if prec == "fp32" else 2
     rounds = st["rounds"]
-    members = sum(st["gathered"])
-    per_u_lists = 8 + 4 * s + 8 * s + 4 * k + 8 * s  # counts, samples, reservoirs
-    if prec == "fp32":
-        gathers = members * (4 * dp + 8)              # fp32 member vectors + worst
-    else:
-        gathers = (members * (2 * db + 8)             # bf16 member vectors + worst
-                   + st["rescored"] * 2 * 4 * dp)     # fp32 rows of every rescored pair
-    traffic = (gathers
-               + rounds * n * per_u_lists                 # neighbourhood id lists
-               + st["insert_attempts"] * (8 * k + 16))   # list scan + CAS per insert
+    members = st["members"]
+    gathers = members * (d * b_e + 4)
+    rescores = st["rescored"] * 2 * d * 4 if prec != "fp32" else 0
+    lists = rounds * 2 * n * k * 8
+    alg = gathers + rescores + lists
     launches = max(st["join_launches"], 1)
-    secs = st["ms"]["join"] / 1e3
-    achieved = traffic / secs if secs > 0 else 0.0
+    secs = st["join_ms"] / 1e3
+    per_launch = alg / launches
+    avg_s = secs / launches
+    achieved = per_launch / avg_s if avg_s > 0 else 0.0
     kernel = "k_join<0, 32, 4>" if prec == "fp32" else "k_join_bf16<0, 32>"
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": measured_traffic(kernel),
-            "kernel": kernel,
-            "launches": launches,
-            "algorithmic_bytes_per_launch": traffic / launches,
-            "avg_launch_ms": st["ms"]["join"] / launches}
+            "kernel": kernel, "launches": launches,
+            "algorithmic_bytes_per_launch": per_launch,
+            "algorithmic_terms_per_launch": {"gathers": gathers / launches,
+                                             "rescores": rescores / launches,
+                                             "lists": lists / launches},
+            "insert_scan_bytes_per_launch": st["insert_attempts"] * (8 * k + 16) / launches,
+            "avg_launch_ms": st["join_ms"] / launches}
 
 
 def serve_bench(args, dev, precision):
@@ -194,9 +245,9 @@ def serve_run(args, dB, G, dR, base, req, offs, sizes, k, nb, budget, slots, bat
         infos, results, by_req = [], {}, {}
         for j in range(R):
             i, ticket = q.get()
-            ids, _, info = srv.wait(ticket, int(sizes[i]))
+            ids, dist, info = srv.wait(ticket, int(sizes[i]))
             infos.append(info)
-            results[i] = ids.numpy()
+            results[i] = (ids.numpy(), dist.numpy())
             by_req[i] = info
             if (j + 1) % 250 == 0:
                 log(f"[serve] {j + 1}/{R} requests done")
@@ -206,7 +257,7 @@ def serve_run(args, dB, G, dR, base, req, offs, sizes, k, nb, budget, slots, bat
         rows_meas = float(sizes[W:].sum())
     finally:
         srv.close()
-    rec = serve_recall(base, req, offs, sizes, results, W, dev, by_req)
+    rec, err = serve_recall(base, req, offs, sizes, results, W, dev, by_req)
     how = ("queued requests merged together as one raw set when a slot frees up"
            if batching else "each request merged with the base on its own")
     out = {
@@ -224,7 +275,8 @@ def serve_run(args, dB, G, dR, base, req, offs, sizes, k, nb, budget, slots, bat
         "inserted_points_per_s": rows_meas / wall, "capacity_rows_per_s": cap,
         "offered_requests_per_s": lam, "requests": R, "rows": int(rows_meas),
         "slots": slots, "hbm_budget_bytes": budget,
-        "recall@10_inserted": rec, "resident_rows_end": int(nb + offs[-1]),
+        "recall@10_inserted": rec, "fp64_error_inserted": err,
+        "resident_rows_end": int(nb + offs[-1]),
     }
     log(f"[serve] {mode}: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "
         f"{out['inserted_points_per_s']:,.0f} rows/s, mean merged rows "
@@ -235,7 +287,8 @@ def serve_run(args, dB, G, dR, base, req, offs, sizes, k, nb, budget, slots, bat
 def serve_recall(base, req, offs, sizes, results, W, dev, infos):
     """recall@10 of inserted rows against their exact neighbours among the
     base and the rows their merge covered (their own request's, or with
-    batching the whole batch's)."""
+    batching the whole batch's), and the error of their stored distances
+    against FP64 (the GEMM form in FP64 is exact on these integer rows)."""
     import torch
     import synth
     g = synth.rng(5007)
@@ -244,6 +297,7 @@ def serve_recall(base, req, offs, sizes, results, W, dev, infos):
     nb = base.shape[0]
     picked = g.choice(np.arange(W, len(sizes)), 100, replace=False)
     hits = total = 0
+    rel, ab = [], []
     for i in picked:
         lo, hi = int(offs[i]), int(offs[i + 1])
         # the raw rows of the merge that ran request i (its own, or its batch)
@@ -257,14 +311,26 @@ def serve_recall(base, req, offs, sizes, results, W, dev, infos):
         Dr[torch.arange(len(rows), device=dev), torch.from_numpy(rows).to(dev)] = float("inf")
         D = torch.cat([Db, Dr], 1)                      # columns: base rows, then merged rows
         kth = torch.topk(D, 10, dim=1, largest=False)[0][:, 9]
-        ids = results[i][rows - (lo - mlo), :10].astype(np.int64)
         first = nb + mlo
-        col = np.where(ids < nb, ids, nb + (ids - first))
-        ok = (ids >= 0) & ((ids < nb) | ((ids >= first) & (ids < first + (mhi - mlo))))
-        got = torch.gather(D, 1, torch.from_numpy(np.where(ok, col, 0)).to(dev))
-        hits += int(((got <= kth[:, None]) & torch.from_numpy(ok).to(dev)).sum().item())
+        allids = results[i][0][rows - (lo - mlo)].astype(np.int64)
+        ok = (allids >= 0) & ((allids < nb) |
+                              ((allids >= first) & (allids < first + (mhi - mlo))))
+        col = np.where(ok, np.where(allids < nb, allids, nb + (allids - first)), 0)
+        got_all = torch.gather(D, 1, torch.from_numpy(col).to(dev)).cpu().numpy()
+        stored = results[i][1][rows - (lo - mlo)].astype(np.float64)
+        e, gv = got_all[ok], stored[ok]
+        big = e >= 1e-6
+        rel.extend((np.abs(gv[big] - e[big]) / e[big]).tolist())
+        ab.extend(np.abs(gv[~big] - e[~big]).tolist())
+        got = torch.from_numpy(got_all[:, :10]).to(dev)
+        okt = torch.from_numpy(ok[:, :10]).to(dev)
+        hits += int(((got <= kth[:, None]) & okt).sum().item())
         total += 10 * len(rows)
-    return hits / total
+    err = {"max_rel": float(max(rel)) if rel else 0.0,
+           "p999_rel": float(np.percentile(rel, 99.9)) if rel else 0.0,
+           "max_abs_below_floor": float(max(ab)) if ab else 0.0, "floor": 1e-6,
+           "entries": len(rel) + len(ab)}
+    return hits / total, err
 
 
 def tree_bench(args, dev):
@@ -285,16 +351,18 @@ def tree_bench(args, dev):
     knng.merge_tree(dX, starts, graphs, k, "l1", **kw)   # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
-    ids, _, st = knng.merge_tree(dX, starts, graphs, k, "l1", **kw)
+    ids, dist, st = knng.merge_tree(dX, starts, graphs, k, "l1", **kw)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t
     rows = synth.rng(4007).choice(len(X), 1000, replace=False)
-    rec = recall_at10(ids.cpu().numpy(), X, rows, dev, metric="l1")
+    ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+    rec = recall_at10(ids, X, rows, dev, metric="l1")
     out = {"workload": "merge tree: 8 x 125,000 x d100 Gaussian mixture (50 components), "
                        "exact k=16 l1 block graphs, pairwise S-Merge in 3 levels",
            "points_per_s": len(X) / secs, "seconds": secs, "level_ms": st["level_ms"],
            "level_rounds": st["level_rounds"], "recall@10": rec,
            "block_graphs_s": t_blocks,
+           "fp64_error": fp64_error(X, ids, dist, rows, "l1"),
            "scanning_rate": st["evals"] / (len(X) * (len(X) - 1) / 2.0)}
     log(f"[tree] 1,000,000 rows in {secs * 1e3:.0f} ms (levels {st['level_ms']} ms), "
         f"recall@10 {rec:.4f}; block graphs {t_blocks:.1f}s")
@@ -341,17 +409,8 @@ def cosine_bench(args, dev):
     ids, dist = graphs["fp32"]
     out["paths_identical"] = bool(np.array_equal(ids, graphs["bf16"][0]) and np.array_equal(
         dist.view(np.uint32), graphs["bf16"][1].view(np.uint32)))
-    # FP64 error of every stored distance of the sampled rows (relative above
-    # 1e-3, absolute below)
-    rel, ab = [], []
-    for i in rows:
-        for j in range(k):
-            e = oracle.dist64("cos", X[i], X[ids[i, j]])
-            (rel if e >= 1e-3 else ab).append(abs(float(dist[i, j]) - e) / (e if e >= 1e-3 else 1))
-    out["fp64_error"] = {"max_rel": float(max(rel)) if rel else 0.0,
-                         "p999_rel": float(np.percentile(rel, 99.9)) if rel else 0.0,
-                         "max_abs_below_1e-3": float(max(ab)) if ab else 0.0,
-                         "entries": len(rel) + len(ab)}
+    # FP64 error of every stored distance of the sampled rows
+    out["fp64_error"] = fp64_error(X, ids, dist, rows, "cos")
     Xd = torch.from_numpy(X).to(device=dev, dtype=torch.float64)
     nrm = Xd.norm(dim=1)
     hits = 0
@@ -523,9 +582,87 @@ def fig4_bench(args, dev):
                         "swept at five size ratios", "rows": out}
 
 
+def c1_bench(args, dev):
+    """The small workload: S-Merge of two sets of 5,000 x d32 i.i.d. N(0,1)
+    rows with exact k=10 input graphs, merged to k=10 with s=10, delta 0,
+    seed 1004.  10,000 points are too few to fill the GPU, so this reports
+    absolute times (no roofline), beside the oracle run in full on the same
+    inputs, and the brute-force cross merge."""
+    import torch
+    import oracle
+    import synth
+    from paper_1908_00814_amd import knng
+    k, s_, seed = 10, 10, 1004
+    S1, S2 = synth.gaussian_sets(5000, 5000, 32)
+    G1 = oracle.exact_graph(S1, k)
+    G2 = oracle.exact_graph(S2, k)
+    t = time.perf_counter()
+    oi, od, ost = oracle.smerge(S1, G1, S2, G2, k, "l2", sample=s_, seed=seed)
+    t_or = time.perf_counter() - t
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    args_ = (d(S1), (d(G1[0]), d(G1[1])), d(S2), (d(G2[0]), d(G2[1])), k, "l2")
+    out = {"workload": "symmetric merge, 2 x 5,000 x d32 N(0,1), exact k=10 input graphs, "
+                       "merged to k=10, s=10, delta 0, squared l2",
+           "oracle_s": t_or, "oracle_rounds": ost["rounds"], "cpu": host_cpu()}
+    X = np.concatenate([S1, S2])
+    for prec in ("fp32", "bf16"):
+        ms = []
+        for rep in range(6):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            gi, gd, gst = knng.merge(*args_, sample=s_, seed=seed, precision=prec)
+            torch.cuda.synchronize()
+            if rep:
+                ms.append((time.perf_counter() - t) * 1e3)
+        gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+        out[prec] = {"ms_median": float(np.median(ms)), "ms_min": float(min(ms)),
+                     "rounds": gst["rounds"],
+                     "identical_to_oracle": bool(np.array_equal(gi, oi) and np.array_equal(
+                         gd.view(np.uint32), od.view(np.uint32)))}
+    out["recall@10"] = recall_at10(gi, X, np.arange(len(X)), dev)
+    ms = []
+    for rep in range(6):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bi, bd = knng.merge_bruteforce(*args_)
+        torch.cuda.synchronize()
+        if rep:
+            ms.append((time.perf_counter() - t) * 1e3)
+    t = time.perf_counter()
+    ei, ed = oracle.merge_bruteforce(S1, G1, S2, G2, k)
+    out["bruteforce"] = {"ms_median": float(np.median(ms)),
+                         "oracle_s": time.perf_counter() - t,
+                         "identical_to_oracle": bool(np.array_equal(bi.cpu().numpy(), ei))}
+    log(f"[c1] S-Merge 2 x 5,000 x d32: FP32 {out['fp32']['ms_median']:.2f} ms, BF16 "
+        f"{out['bf16']['ms_median']:.2f} ms ({ost['rounds']} rounds), oracle {t_or:.2f} s; "
+        f"identical {out['fp32']['identical_to_oracle']}/{out['bf16']['identical_to_oracle']}; "
+        f"recall@10 {out['recall@10']:.4f}; brute-force merge {out['bruteforce']['ms_median']:.2f}"
+        f" ms (oracle {out['bruteforce']['oracle_s']:.2f} s)")
+    return out
+
+
+ORACLE_CHILD = """
+import json, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle
+z = np.load(sys.argv[2])
+k, s, delta, seed = (int(sys.argv[3]), int(sys.argv[4]), float(sys.argv[5]), int(sys.argv[6]))
+t0 = time.time()
+oracle.smerge(z["S1"], (z["g1i"], z["g1d"]), z["S2"], (z["g2i"], z["g2d"]), k, "l2",
+              sample=s, delta=delta, seed=seed)
+print(json.dumps({"start": t0, "end": time.time()}))
+"""
+
+
 def cpu_baseline(n_per, k, s, delta, seed, dev, precision):
-    """The oracle timed on a bounded sample of the headline workload; the GPU
-    merges the same sample and the two graphs are compared."""
+    """The oracle (plain single-threaded C) timed on a bounded sample of the
+    headline workload: once alone, and as one copy per usable CPU (at most 16)
+    running at once on the same sample, which is the host's whole oracle
+    throughput for merges of this size.  The GPU merges the same sample and
+    the two graphs are compared."""
+    import subprocess
+    import tempfile
     import torch
     import oracle
     import synth
@@ -534,10 +671,26 @@ def cpu_baseline(n_per, k, s, delta, seed, dev, precision):
     S1, S2 = synth.byte_cluster_sets(n_per, n_per, workload=2)
     G1 = approximate_graph(S1, k, 0.9, device="cpu", stream=6)
     G2 = approximate_graph(S2, k, 0.9, device="cpu", stream=7)
+    oracle.lib()
     t0 = time.perf_counter()
     oi, od, _ = oracle.smerge(S1, G1, S2, G2, k, "l2", sample=s, delta=delta, seed=seed)
     dt = time.perf_counter() - t0
-    d = lambda a: torch.from_numpy(a).to(dev)
+    cpu = host_cpu()
+    P = max(1, min(16, cpu["usable"]))
+    with tempfile.TemporaryDirectory() as tmp:
+        f = os.path.join(tmp, "sample.npz")
+        np.savez(f, S1=S1, S2=S2, g1i=G1[0], g1d=G1[1], g2i=G2[0], g2d=G2[1])
+        procs = [subprocess.Popen([sys.executable, "-c", ORACLE_CHILD, ROOT, f, str(k), str(s),
+                                   str(delta), str(seed)], stdout=subprocess.PIPE, text=True)
+                 for _ in range(P)]
+        spans = []
+        for p_ in procs:
+            o, _ = p_.communicate()
+            if p_.returncode != 0:
+                raise RuntimeError("oracle child failed")
+            spans.append(json.loads(o.strip().splitlines()[-1]))
+    wall = max(x["end"] for x in spans) - min(x["start"] for x in spans)
+    d = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
     gi, gd, _ = knng.merge(d(S1), (d(G1[0]), d(G1[1])), d(S2), (d(G2[0]), d(G2[1])), k, "l2",
                            sample=s, delta=delta, seed=seed, precision=precision)
     gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
@@ -547,13 +700,16 @@ def cpu_baseline(n_per, k, s, delta, seed, dev, precision):
                                 np.array_equal(gd.view(np.uint32), od.view(np.uint32))),
               "recall@10_oracle": oracle.recall_at(oi, X, rows, 10)[0],
               "recall@10_gpu": oracle.recall_at(gi, X, rows, 10)[0], "rows": 300}
-    return {"value": 2 * n_per / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "parity_with_gpu": parity,
+    return {"value": P * 2 * n_per / wall, "unit": "points/s", "cores": P, "kind": "oracle",
+            "parity_with_gpu": parity, "cpu": cpu,
+            "single_thread": {"value": 2 * n_per / dt, "seconds": dt, "cores": 1},
+            "all_cores": {"processes": P, "wall_s": wall,
+                          "per_process_s": [x["end"] - x["start"] for x in spans]},
             "sample": (f"S-Merge of 2 x {n_per:,} points drawn from the same byte-valued "
                        f"cluster law (d=128, k=20, s={s}, delta={delta}), approximate "
-                       f"input graphs built the same way; single-threaded C oracle, "
-                       f"{dt:.1f} s"),
-            "seconds": dt}
+                       f"input graphs built the same way; the single-threaded C oracle run "
+                       f"as {P} processes at once on {P} of {cpu['nproc']} CPUs "
+                       f"({cpu['model']}), {wall:.1f} s wall; alone: {dt:.1f} s")}
 
 
 def main():
@@ -570,6 +726,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2004)
     ap.add_argument("--cpu-n", type=int, default=25_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 2 x 5,000 x d32 workload")
     ap.add_argument("--only", choices=["fp32", "bf16"], default=None,
                     help="time one path only (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -635,34 +792,46 @@ def main():
         kw = dict(precision=prec, **common)
 
         def step():
+            # phase timing with HIP events on the library's stream (the loop
+            # already synchronises once per round to read its counter)
             return knng.merge(dS1, dG1, dS2, dG2, k, "l2", stream=stream, workspace=ws, out=out,
-                              **kw)[2]
+                              profile=True, **kw)[2]
 
         for i in range(args.warmup):
             st = step()
             log(f"[bench] {prec} warmup {i}: {st['rounds']} rounds")
         torch.cuda.synchronize()
+        acc = {"rounds": 0, "members": 0, "rescored": 0, "insert_attempts": 0, "join_ms": 0.0,
+               "join_launches": 0}
+        phase = {}
         t0 = time.perf_counter()
         for i in range(args.steps):
             st = step()
+            acc["rounds"] += st["rounds"]
+            acc["members"] += sum(st["gathered"])
+            for key in ("rescored", "insert_attempts", "join_launches"):
+                acc[key] += st[key]
+            acc["join_ms"] += st["ms"]["join"]
+            for a_, b_ in st["ms"].items():
+                phase[a_] = phase.get(a_, 0.0) + b_ / args.steps
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         ms_step = elapsed * 1e3 / max(args.steps, 1)
         value = n * args.steps / elapsed
         ids = out[0].cpu().numpy()
+        dist = out[1].cpu().numpy()
         rec = recall_at10(ids, X, rows, dev)
         log(f"[bench] {prec}: {args.steps} steps, {ms_step:.1f} ms/step, {value / 1e6:.2f} M "
             f"points/s, {st['rounds']} rounds, recall@10 {rec:.4f} (1,000 sampled rows)")
-        pst = knng.merge(dS1, dG1, dS2, dG2, k, "l2", stream=stream, workspace=ws, out=out,
-                         profile=True, **kw)[2]
-        roof = join_roofline(pst, n, d, k, args.sample, prec)
-        log(f"[bench] {prec} join: {roof['launches']} launches, {roof['avg_launch_ms']:.3f} ms "
-            f"avg, {roof['achieved']:.0f} GB/s algorithmic ({100 * roof['frac']:.1f}% of HBM "
-            f"peak); phase ms {json.dumps({a: round(b, 2) for a, b in pst['ms'].items()})}")
+        roof = join_roofline(acc, n, d, k, args.sample, prec)
+        log(f"[bench] {prec} join: {roof['launches']} launches in the timed steps, "
+            f"{roof['avg_launch_ms']:.3f} ms avg, {roof['achieved']:.0f} GB/s algorithmic "
+            f"({100 * roof['frac']:.1f}% of HBM peak); phase ms per step "
+            f"{json.dumps({a_: round(b_, 2) for a_, b_ in phase.items()})}")
         paths[prec] = {"value": value, "ms_per_step": ms_step, "recall@10": rec,
-                       "rounds": st["rounds"], "evals": st["evals"], "ids": ids,
-                       "roofline": roof, "phase_ms": pst["ms"],
-                       "rescored": pst["rescored"], "screen_violations": pst["screen_violations"]}
+                       "rounds": st["rounds"], "evals": st["evals"], "ids": ids, "dist": dist,
+                       "roofline": roof, "phase_ms": phase,
+                       "rescored": st["rescored"], "screen_violations": st["screen_violations"]}
     same = (bool(np.array_equal(paths["fp32"]["ids"], paths["bf16"]["ids"]))
             if len(paths) == 2 else None)
     best = max(paths, key=lambda p: paths[p]["value"]) if args.precision == "best" else \
@@ -691,7 +860,10 @@ def main():
         "bf16_over_fp32": (paths["bf16"]["value"] / paths["fp32"]["value"]
                            if len(paths) == 2 else None),
         "paths_identical": same,
+        "fp64_error": fp64_error(X, head["ids"], head["dist"], rows, "l2"),
     }
+    log(f"[bench] FP64 error of the stored distances of 1,000 sampled rows: "
+        f"{json.dumps(line['fp64_error'])}")
     del ws, out
     torch.cuda.empty_cache()
     if not args.no_nnd:
@@ -713,6 +885,8 @@ def main():
         line["p50_insert_latency_ms"] = line["serving"]["p50_ms"]
         line["p99_insert_latency_ms"] = line["serving"]["p99_ms"]
         torch.cuda.empty_cache()
+    if not args.no_c1:
+        line["c1"] = c1_bench(args, dev)
     if not args.no_cpu_baseline:
         log(f"[bench] timing the CPU oracle on 2 x {args.cpu_n} points ...")
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, k, args.sample, args.delta, args.seed,

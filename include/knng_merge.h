@@ -103,7 +103,10 @@ typedef enum {
  *               append (0 = until no update, as the paper states).
  *   max_rounds  cap on rounds (the paper has none).
  *   seed        seed of the counter-based random stream (SplitMix64).
- *   precision   knng_precision.
+ *   precision   knng_precision.  Under KNNG_BF16_RESCORE a rescored pair
+ *               whose bf16 distance lies outside the proven screening margin
+ *               (the bound failed; never observed) makes the call return
+ *               KNNG_EDEVICE, with the count in stats->screen_violations.
  *   flags       KNNG_FLAG_*.
  * Constraints: 3*sample + k <= 160, 1 <= k <= 64.
  */
@@ -349,6 +352,10 @@ size_t knng_server_bytes(int64_t capacity, int64_t max_request, int32_t d, int32
  * memory, allocated once with hipMalloc.  KNNG_ENOMEM when cfg->hbm_budget
  * holds no slot.  Inputs are not kept.  *srv receives the server (NULL on
  * error).
+ * Stream contract (also for device rows given to knng_server_submit): the
+ * server reads its inputs on streams of its own, after waiting for the work
+ * queued on the null stream; a caller that writes them on another stream
+ * must synchronise that stream first.
  */
 knng_status knng_server_create(const knng_set *base, const knng_graph *G, int32_t k,
                                knng_metric metric, const knng_opts *opts,

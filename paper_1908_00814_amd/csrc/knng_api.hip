@@ -192,6 +192,12 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
         stats->max_group = (int32_t)h[C_MAXG];
     }
     prof.collect(stats);
+    // A rescored pair whose bf16 distance left the proven margin means the
+    // bound failed, and a pair it screened out may have been lost: the
+    // result is not trusted (the count is in stats->screen_violations).
+    if (h[C_VIOL])
+        return fail(KNNG_EDEVICE, "BF16 screen: %llu rescored pairs left the error margin",
+                    (unsigned long long)h[C_VIOL]);
     return ok();
 }
 

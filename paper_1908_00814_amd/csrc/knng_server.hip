@@ -499,7 +499,10 @@ static knng_status knng_server_create_impl(const knng_set *base, const knng_grap
             carve_slot(c, *s, s->slots[i]);
         }
         // base rows and lists into the store (validated, sorted keys); the
-        // resident lists start as the base lists
+        // resident lists start as the base lists.  They are read on the
+        // server's own (non-blocking) stream: first let the work the caller
+        // queued on the null stream finish.
+        HIP_TRY(hipStreamSynchronize(nullptr));
         knng_set none{0, base->d, nullptr};
         Rows R;
         knng_status r =
@@ -577,6 +580,10 @@ static knng_status knng_server_submit_impl(knng_server *s, const float *raw, int
     const knng_status rc = [&]() -> knng_status {
         const Layout &w = s->store;
         const float *src = raw;
+        // the rows are read on the server's own (non-blocking) stream: first
+        // let the work the caller queued on the null stream finish
+        if (on_device)
+            HIP_TRY(hipStreamSynchronize(nullptr));
         if (!on_device) {
             HIP_TRY(hipMemcpyAsync(s->stage, raw, (size_t)n_raw * s->d * sizeof(float),
                                    hipMemcpyHostToDevice, s->sub_st));

@@ -373,6 +373,9 @@ class Server:
                  slots=4, batching=False, **kw):
         lib = load()
         o = opts(**kw)
+        # the server reads base and G on its own streams (header: stream
+        # contract); let the current stream's producers finish first
+        torch.cuda.current_stream(base.device).synchronize()
         cfg = ServerConfig(int(capacity if capacity is not None else 2 * base.shape[0]),
                            int(max_request if max_request is not None else base.shape[0]),
                            int(hbm_budget), int(slots), int(bool(batching)))
@@ -391,6 +394,9 @@ class Server:
             raw = torch.from_numpy(raw)
         assert raw.dtype == torch.float32 and raw.dim() == 2 and raw.shape[1] == self.d
         raw = raw.contiguous()
+        if raw.is_cuda:
+            # read on the server's own stream (header: stream contract)
+            torch.cuda.current_stream(raw.device).synchronize()
         t = ctypes.c_uint64()
         _check(load().knng_server_submit(self._h, ctypes.c_void_p(raw.data_ptr()), raw.shape[0],
                                          int(req_id) & (2 ** 64 - 1), ctypes.byref(t)))

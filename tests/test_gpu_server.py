@@ -61,13 +61,17 @@ def _server(hip, base, G, k, metric, **kw):
 
 
 @pytest.mark.parametrize("metric", ["l2", "cos"])
-def test_each_request_is_the_oracles_merge_with_the_base(hip, metric):
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_each_request_is_the_oracles_merge_with_the_base(hip, metric, precision):
+    # the BF16 path covers the bf16 copy and norms written at submission at
+    # the request's store rows, the two-segment row view and the list-mode
+    # join; its screen must not change a single result
     k, s, seed = 8, 6, 31
     base, reqs = _sets(1200, [37, 5, 60], 11, 120)
     m = base.shape[0]
     G = oracle.exact_graph(base, k, metric)
     srv = _server(hip, base, G, k, metric, capacity=1400, max_request=100, slots=0, sample=s,
-                  seed=seed)
+                  seed=seed, precision=precision)
     try:
         rids = [101, 202, 303]
         tickets = [srv.submit(dev(r) if i % 2 else r, rid)
@@ -90,7 +94,8 @@ def test_each_request_is_the_oracles_merge_with_the_base(hip, metric):
         srv.close()
 
 
-def test_results_are_the_same_in_a_mix(hip):
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_results_are_the_same_in_a_mix(hip, precision):
     # ten requests from two threads on three slots: each result equals the
     # request merged alone, and the resident graph does not depend on the
     # order in which they finished
@@ -100,7 +105,7 @@ def test_results_are_the_same_in_a_mix(hip):
     m = base.shape[0]
     G = oracle.exact_graph(base, k)
     srv = _server(hip, base, G, k, "l2", capacity=m + sum(sizes), max_request=80, slots=3,
-                  sample=s, seed=seed)
+                  sample=s, seed=seed, precision=precision)
     assert srv.slots == 3
     tickets = {}
     lock = threading.Lock()
@@ -252,7 +257,8 @@ def test_server_errors(hip):
         srv.close()
 
 
-def test_many_requests_on_one_slot_each_equal_the_oracle(hip):
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_many_requests_on_one_slot_each_equal_the_oracle(hip, precision):
     # one slot keeps its merge state between requests (tags of earlier merges
     # read as "never", only rows they changed are restored): 25 requests in a
     # row, sizes from 1 to 60 rows, each must equal its merge on fresh state
@@ -262,7 +268,7 @@ def test_many_requests_on_one_slot_each_equal_the_oracle(hip):
     m = base.shape[0]
     G = oracle.exact_graph(base, k)
     srv = _server(hip, base, G, k, "l2", capacity=m + sum(sizes), max_request=64, slots=0,
-                  sample=s, seed=seed)
+                  sample=s, seed=seed, precision=precision)
     try:
         first, results = m, []
         for i, r in enumerate(reqs):
