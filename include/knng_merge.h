@@ -257,6 +257,28 @@ size_t knng_hmerge_workspace_size(int64_t n, int32_t d, int32_t k, int64_t n_top
                                   knng_metric metric, const knng_opts *opts);
 
 /*
+ * knng_merge without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, semantics and errors as knng_merge, except:
+ *   - the scratch is a fixed array of KNNG_NOALLOC_SCRATCH_BYTES bytes held
+ *     by the library on every GPU it runs on, until the process ends; a
+ *     merge whose knng_merge_workspace_size exceeds it returns KNNG_ENOMEM;
+ *   - every call on one GPU shares that GPU's array: calls that overlap on
+ *     one GPU (any streams, any threads) race and must not be issued;
+ *   - nothing is allocated on the device; KNNG_FLAG_PROFILE (which creates
+ *     HIP events) is refused with KNNG_EINVAL.
+ */
+#define KNNG_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+knng_status knng_merge_noalloc(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
+                               const knng_graph *G2, int32_t k, knng_metric metric,
+                               const knng_opts *opts, knng_graph *out, void *stream,
+                               knng_stats *stats);
+
+/* KNNG_NOALLOC_SCRATCH_BYTES of the loaded library */
+size_t knng_merge_noalloc_scratch_bytes(void);
+
+/*
  * Brute-force cross merge (Section 1): row i of S1 becomes the top k of
  * G1[i] and every (m(x_i, y_j), n1+j); S2 rows likewise against S1.
  * Deterministic: equal to the exact result in canonical FP32 with ties broken

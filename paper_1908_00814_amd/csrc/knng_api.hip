@@ -248,10 +248,13 @@ size_t knng_expand_workspace_size(int64_t n_base, int64_t n_raw, int32_t d, int3
     return c.off + 256;
 }
 
+// ws_is_device: the workspace is known to be device memory (the library's
+// own static scratch, which hipPointerGetAttributes need not know)
 static knng_status knng_merge_impl(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
                                    const knng_graph *G2, int32_t k, knng_metric metric,
                                    const knng_opts *opts, knng_graph *out, void *workspace,
-                                   size_t workspace_bytes, void *stream, knng_stats *stats)
+                                   size_t workspace_bytes, void *stream, knng_stats *stats,
+                                   bool ws_is_device = false)
 {
     knng_status s;
     if ((s = check_metric(metric)) || (s = check_set(S1, "S1")) || (s = check_set(S2, "S2")) ||
@@ -271,7 +274,7 @@ static knng_status knng_merge_impl(const knng_set *S1, const knng_graph *G1, con
     const size_t need = knng_merge_workspace_size(n1, n2, S1->d, k, G1->k, G2->k, metric, opts);
     if (!workspace || workspace_bytes < need)
         return fail(KNNG_ENOMEM, "workspace %zu bytes, need %zu", workspace_bytes, need);
-    if (!is_device_ptr(workspace))
+    if (!ws_is_device && !is_device_ptr(workspace))
         return fail(KNNG_EINVAL, "workspace is not device memory");
     hipStream_t st = (hipStream_t)stream;
     if (stats)
@@ -303,6 +306,31 @@ knng_status knng_merge(const knng_set *S1, const knng_graph *G1, const knng_set 
         return fail(KNNG_EDEVICE, "unexpected host exception");
     }
 }
+
+} // extern "C"
+
+namespace knng {
+namespace host {
+// knng_merge on device memory the caller vouches for (the no-allocation
+// entry point's static scratch)
+knng_status merge_on_scratch(const knng_set *S1, const knng_graph *G1, const knng_set *S2,
+                             const knng_graph *G2, int32_t k, knng_metric metric,
+                             const knng_opts *opts, knng_graph *out, void *scratch,
+                             size_t scratch_bytes, void *stream, knng_stats *stats)
+{
+    try {
+        return knng_merge_impl(S1, G1, S2, G2, k, metric, opts, out, scratch, scratch_bytes,
+                               stream, stats, true);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
+}
+} // namespace host
+} // namespace knng
+
+extern "C" {
 
 static knng_status knng_expand_impl(const knng_set *S, const knng_graph *G, const knng_set *raw,
                                     int32_t k, knng_metric metric, const knng_opts *opts,

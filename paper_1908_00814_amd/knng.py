@@ -30,7 +30,8 @@ ENTRY_POINTS = ["knng_opts_default", "knng_merge", "knng_merge_workspace_size", 
                 "knng_hmerge_workspace_size", "knng_server_bytes",
                 "knng_server_create", "knng_server_submit", "knng_server_step",
                 "knng_server_wait", "knng_server_snapshot", "knng_server_rebase",
-                "knng_server_status", "knng_server_slots", "knng_server_destroy"]
+                "knng_server_status", "knng_server_slots", "knng_server_destroy",
+                "knng_merge_noalloc", "knng_merge_noalloc_scratch_bytes"]
 
 
 class Opts(ctypes.Structure):
@@ -115,6 +116,10 @@ def load():
     lib.knng_opts_default.argtypes = [pO]
     lib.knng_merge.restype = ctypes.c_int
     lib.knng_merge.argtypes = [pS, pG, pS, pG, I32, ctypes.c_int, pO, pG, P, SZ, P, pSt]
+    lib.knng_merge_noalloc.restype = ctypes.c_int
+    lib.knng_merge_noalloc.argtypes = [pS, pG, pS, pG, I32, ctypes.c_int, pO, pG, P, pSt]
+    lib.knng_merge_noalloc_scratch_bytes.restype = SZ
+    lib.knng_merge_noalloc_scratch_bytes.argtypes = []
     lib.knng_merge_workspace_size.restype = SZ
     lib.knng_merge_workspace_size.argtypes = [I64, I64, I32, I32, I32, I32, ctypes.c_int, pO]
     lib.knng_expand.restype = ctypes.c_int
@@ -244,6 +249,28 @@ def merge(S1, G1, S2, G2, k, metric="l2", stream=None, workspace=None, out=None,
                           _ptr(workspace), workspace.numel(), _stream(stream),
                           ctypes.byref(st)))
     return ids, dist, st.to_dict()
+
+
+def merge_noalloc(S1, G1, S2, G2, k, metric="l2", stream=None, out=None, **kw):
+    """S-Merge on the library's static scratch (knng_merge_noalloc): nothing
+    is allocated on the device except `out` when it is not given.  Returns
+    (ids, dist, stats dict)."""
+    lib = load()
+    o = opts(**kw)
+    s1, s2 = _set(S1), _set(S2)
+    g1, g2 = _graph(*G1), _graph(*G2)
+    n = S1.shape[0] + S2.shape[0]
+    ids, dist = out if out is not None else _out(n, k, S1.device)
+    go = _graph(ids, dist)
+    st = Stats()
+    _check(lib.knng_merge_noalloc(ctypes.byref(s1), ctypes.byref(g1), ctypes.byref(s2),
+                                  ctypes.byref(g2), k, _metric(metric), ctypes.byref(o),
+                                  ctypes.byref(go), _stream(stream), ctypes.byref(st)))
+    return ids, dist, st.to_dict()
+
+
+def noalloc_scratch_bytes():
+    return load().knng_merge_noalloc_scratch_bytes()
 
 
 def expand(S, G, raw, k, metric="l2", stream=None, workspace=None, out=None, **kw):
