@@ -16,7 +16,10 @@
  *   - joint merge, J-Merge (Algorithm 2, Section 3.2);
  *   - the per-round statistics used by the tests: the update count c, the
  *     objective phi(G) of Eq. (1) and the number of distance evaluations C
- *     behind the scanning rate of Section 5.1.
+ *     behind the scanning rate of Section 5.1;
+ *   - graph diversification (Algorithm 3, Section 4) of a k-NN graph, its
+ *     lists and reverse lists merged, and the two-stage top-down NN search
+ *     over a hierarchy of graphs (Section 4).
  *
  * Precision: decisions (which id enters a list) are taken on canonical FP32
  * distances, evaluated in one fixed order written out below, because the GPU
@@ -987,4 +990,262 @@ void orc_hmerge_order(uint64_t seed, int64_t n, int32_t *order)
 uint64_t orc_feistel4(uint64_t seed, uint64_t x, int h)
 {
     return feistel4(seed, x, h);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Graph diversification (Algorithm 3, Section 4)                            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Algorithm 3 on one neighbourhood of sample a: cand[0..m) sorted ascending
+ * by (distance to a, id); cand[0] is kept; every later candidate s is kept
+ * unless some already kept c has m(s, c) < m(s, a) (c occludes s).  The
+ * distance to a is the one the list stores (canonical FP32, symmetric);
+ * m(s, c) is evaluated canonically.  Kept entries go to out (in order);
+ * returns how many.
+ */
+static int gd_select(const float *X, int d, int metric, const pair_t *cand, int m, pair_t *out)
+{
+    int q = 0;
+    for (int i = 0; i < m; i++) {
+        int keep = 1;
+        for (int j = 0; j < q && keep; j++) {
+            float sc = orc_dist32(metric, X + (int64_t)cand[i].id * d,
+                                  X + (int64_t)out[j].id * d, d);
+            if (sc < cand[i].dist)
+                keep = 0;
+        }
+        if (keep)
+            out[q++] = cand[i];
+    }
+    return q;
+}
+
+/*
+ * Diversified graph of G (n rows of k entries over the rows of X, sorted by
+ * (distance, id), id -1 = empty).  For each row a (Section 4):
+ *   Q_f = Algorithm 3 on a's list;
+ *   Q_r = Algorithm 3 on a's reverse list {b : a in G[b]}, each b at the
+ *         distance G[b] stores for a, sorted by (distance, id);
+ *   out[a] = the max_deg first entries, by (distance, id), of Q_f u Q_r
+ *            (an id in both once), padded with (-1, +inf).
+ * Reading: the paper merges the two diversified lists and keeps up to k/2
+ * neighbours in its experiments; max_deg is that bound.
+ */
+int orc_diversify(const float *X, int64_t n, int d, int metric, const int32_t *ids,
+                  const float *dist, int k, int max_deg, int32_t *out_ids, float *out_dist)
+{
+    if (n < 1 || d < 1 || k < 1 || max_deg < 1)
+        return ORC_EINVAL;
+    int64_t *deg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int rc = ORC_OK;
+    pair_t *rev = NULL, *cand = NULL, *qf = NULL, *qr = NULL;
+    int64_t *fill = NULL;
+    if (!deg) {
+        rc = ORC_ENOMEM;
+        goto out;
+    }
+    for (int64_t b = 0; b < n; b++)
+        for (int j = 0; j < k; j++) {
+            int32_t a = ids[b * k + j];
+            if (a < -1 || a >= n || a == b) {
+                rc = ORC_EINVAL;
+                goto out;
+            }
+            if (a >= 0)
+                deg[a + 1]++;
+        }
+    for (int64_t a = 0; a < n; a++)
+        deg[a + 1] += deg[a];
+    rev = (pair_t *)malloc(sizeof(pair_t) * (size_t)(deg[n] > 0 ? deg[n] : 1));
+    fill = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    int64_t maxdeg_in = 0;
+    for (int64_t a = 0; a < n; a++)
+        if (deg[a + 1] - deg[a] > maxdeg_in)
+            maxdeg_in = deg[a + 1] - deg[a];
+    cand = (pair_t *)malloc(sizeof(pair_t) * (size_t)(maxdeg_in + k + 1));
+    qf = (pair_t *)malloc(sizeof(pair_t) * (size_t)(k + 1));
+    qr = (pair_t *)malloc(sizeof(pair_t) * (size_t)(maxdeg_in + 1));
+    if (!rev || !fill || !cand || !qf || !qr) {
+        rc = ORC_ENOMEM;
+        goto out;
+    }
+    for (int64_t b = 0; b < n; b++)
+        for (int j = 0; j < k; j++) {
+            int32_t a = ids[b * k + j];
+            if (a >= 0) {
+                pair_t p = {dist[b * k + j], (int32_t)b};
+                rev[deg[a] + fill[a]++] = p;
+            }
+        }
+    for (int64_t a = 0; a < n; a++) {
+        int m = 0;
+        for (int j = 0; j < k; j++)
+            if (ids[a * k + j] >= 0) {
+                pair_t p = {dist[a * k + j], ids[a * k + j]};
+                cand[m++] = p;
+            }
+        qsort(cand, (size_t)m, sizeof(pair_t), cmp_pair);
+        int nf = gd_select(X, d, metric, cand, m, qf);
+        int64_t r0 = deg[a], nr_in = deg[a + 1] - deg[a];
+        qsort(rev + r0, (size_t)nr_in, sizeof(pair_t), cmp_pair);
+        int nr = gd_select(X, d, metric, rev + r0, (int)nr_in, qr);
+        /* union, (distance, id) order, each id once, first max_deg */
+        int c = 0;
+        for (int j = 0; j < nf; j++)
+            cand[c++] = qf[j];
+        for (int j = 0; j < nr; j++) {
+            int dup = 0;
+            for (int q = 0; q < nf; q++)
+                dup |= qf[q].id == qr[j].id;
+            if (!dup)
+                cand[c++] = qr[j];
+        }
+        qsort(cand, (size_t)c, sizeof(pair_t), cmp_pair);
+        for (int j = 0; j < max_deg; j++) {
+            out_ids[a * max_deg + j] = j < c ? cand[j].id : -1;
+            out_dist[a * max_deg + j] = j < c ? cand[j].dist : INFINITY;
+        }
+    }
+out:
+    free(deg);
+    free(rev);
+    free(fill);
+    free(cand);
+    free(qf);
+    free(qr);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* NN search over the graph hierarchy (Section 4)                            */
+/* ------------------------------------------------------------------------ */
+
+#define TAG_SEARCH 0xD1u
+
+/*
+ * Top-down search of the query q over nl layer graphs.  Layer l holds
+ * rows[l] vertices, the rows 0..rows[l]-1 of X (each layer a prefix of the
+ * next, the last layer all n rows), and lists of deg[l] ids (-1 = empty).
+ *   Stage 1 (layers 0 .. nl-2): start at a random vertex of the top layer,
+ *     draw_below(H(seed, SEARCH, query, 0, 0), rows[0]); on each layer move
+ *     to the closest, by (distance, id), of the current vertex's neighbours
+ *     while it is closer than the current vertex; the vertex reached starts
+ *     the next layer.
+ *   Stage 2 (bottom layer): a ranked list of at most ef entries (distance,
+ *     id), starting with the vertex reached; repeatedly the best entry not
+ *     yet expanded is expanded: its neighbours not visited before are
+ *     evaluated, marked visited, and the list becomes the ef best of itself
+ *     and them; the search ends when every entry of the list is expanded.
+ * The answer is the first topk entries (padded with (-1, +inf)).  Distances
+ * are canonical FP32 m(q, x).  evals (may be NULL) receives the number of
+ * distances evaluated.
+ */
+static int search_one(const float *X, int d, int metric, const int32_t *const *layer_ids,
+                      const int64_t *rows, const int *deg, int nl, const float *q, int64_t qi,
+                      int topk, int ef, uint64_t seed, uint8_t *visited, pair_t *pool,
+                      uint8_t *expanded, int32_t *out_ids, float *out_dist, int64_t *evals)
+{
+    uint64_t h = orc_hash(seed, TAG_SEARCH, (uint64_t)qi, 0, 0);
+    int32_t cur = (int32_t)draw_below(h, (uint32_t)rows[0]);
+    float dcur = orc_dist32(metric, q, X + (int64_t)cur * d, d);
+    int64_t ev = 1;
+    for (int l = 0; l + 1 < nl; l++) {
+        for (;;) {
+            int32_t best = -1;
+            float dbest = INFINITY;
+            for (int j = 0; j < deg[l]; j++) {
+                int32_t v = layer_ids[l][(int64_t)cur * deg[l] + j];
+                if (v < 0)
+                    continue;
+                float dv = orc_dist32(metric, q, X + (int64_t)v * d, d);
+                ev++;
+                if (best < 0 || key_less(dv, v, dbest, best)) {
+                    best = v;
+                    dbest = dv;
+                }
+            }
+            if (best >= 0 && key_less(dbest, best, dcur, cur)) {
+                cur = best;
+                dcur = dbest;
+            } else {
+                break;
+            }
+        }
+    }
+    const int b = nl - 1;
+    memset(visited, 0, (size_t)rows[b]);
+    int cnt = 1;
+    pool[0].dist = dcur;
+    pool[0].id = cur;
+    expanded[0] = 0;
+    visited[cur] = 1;
+    for (;;) {
+        int e = -1;
+        for (int j = 0; j < cnt && e < 0; j++)
+            if (!expanded[j])
+                e = j;
+        if (e < 0)
+            break;
+        expanded[e] = 1;
+        int32_t u = pool[e].id;
+        for (int j = 0; j < deg[b]; j++) {
+            int32_t v = layer_ids[b][(int64_t)u * deg[b] + j];
+            if (v < 0 || visited[v])
+                continue;
+            visited[v] = 1;
+            float dv = orc_dist32(metric, q, X + (int64_t)v * d, d);
+            ev++;
+            /* the pool stays sorted by (distance, id): insert, drop the worst */
+            if (cnt == ef && !key_less(dv, v, pool[ef - 1].dist, pool[ef - 1].id))
+                continue;
+            int pos = cnt < ef ? cnt : ef - 1;
+            while (pos > 0 && key_less(dv, v, pool[pos - 1].dist, pool[pos - 1].id)) {
+                pool[pos] = pool[pos - 1];
+                expanded[pos] = expanded[pos - 1];
+                pos--;
+            }
+            pool[pos].dist = dv;
+            pool[pos].id = v;
+            expanded[pos] = 0;
+            if (cnt < ef)
+                cnt++;
+        }
+    }
+    for (int j = 0; j < topk; j++) {
+        out_ids[j] = j < cnt ? pool[j].id : -1;
+        out_dist[j] = j < cnt ? pool[j].dist : INFINITY;
+    }
+    if (evals)
+        *evals += ev;
+    return ORC_OK;
+}
+
+int orc_search(const float *X, int d, int metric, const int32_t *const *layer_ids,
+               const int64_t *rows, const int *deg, int nl, const float *Q, int64_t nq, int topk,
+               int ef, uint64_t seed, int32_t *out_ids, float *out_dist, int64_t *evals)
+{
+    if (nl < 1 || d < 1 || topk < 1 || ef < topk || nq < 0)
+        return ORC_EINVAL;
+    for (int l = 0; l < nl; l++)
+        if (rows[l] < 1 || deg[l] < 1 || (l > 0 && rows[l] < rows[l - 1]))
+            return ORC_EINVAL;
+    uint8_t *visited = (uint8_t *)malloc((size_t)rows[nl - 1]);
+    pair_t *pool = (pair_t *)malloc(sizeof(pair_t) * (size_t)ef);
+    uint8_t *expanded = (uint8_t *)malloc((size_t)ef);
+    if (!visited || !pool || !expanded) {
+        free(visited);
+        free(pool);
+        free(expanded);
+        return ORC_ENOMEM;
+    }
+    if (evals)
+        *evals = 0;
+    for (int64_t i = 0; i < nq; i++)
+        search_one(X, d, metric, layer_ids, rows, deg, nl, Q + i * d, i, topk, ef, seed, visited,
+                   pool, expanded, out_ids + i * topk, out_dist + i * topk, evals);
+    free(visited);
+    free(pool);
+    free(expanded);
+    return ORC_OK;
 }

@@ -85,6 +85,13 @@ def lib():
         L.orc_hmerge_order.argtypes = [ctypes.c_uint64, I64, P]
         L.orc_feistel4.restype = ctypes.c_uint64
         L.orc_feistel4.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int]
+        L.orc_diversify.restype = ctypes.c_int
+        L.orc_diversify.argtypes = [P, I64, ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
+                                    ctypes.c_int, P, P]
+        L.orc_search.restype = ctypes.c_int
+        L.orc_search.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, I64,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_uint64, P, P,
+                                 ctypes.POINTER(I64)]
         L.orc_dist64_rows.restype = None
         L.orc_dist64_rows.argtypes = [P, I64, ctypes.c_int, ctypes.c_int, P, I64, P]
         _lib = L
@@ -131,6 +138,7 @@ def hash5(seed, tag, a, b, c):
 
 
 TAG_APPEND, TAG_INIT, TAG_FWD, TAG_RNEW, TAG_ROLD = 0xA1, 0xA2, 0xB1, 0xB2, 0xB3
+TAG_SEARCH = 0xD1
 
 
 def draws(seed, tag, row, N, skip, m):
@@ -324,6 +332,68 @@ def hmerge(X, k, n_top, metric="l2", keep_ratio=0.5, sample=10, delta=0.0, max_r
     out_i[order] = np.take_along_axis(rid, srt, axis=1)
     out_d[order] = np.take_along_axis(dist, srt, axis=1)
     return out_i, out_d, stats
+
+
+def hmerge_hierarchy(X, k, n_top, metric="l2", keep_ratio=0.5, sample=10, delta=0.0,
+                     max_rounds=30, seed=0):
+    """H-Merge (Section 3.3) keeping every layer: returns (order, layers),
+    order[i] = the row at position i, layers[l] = (ids, dist) of layer l's
+    graph over positions 0 .. rows_l - 1 (ids are positions), top layer
+    first, exactly as hmerge builds them."""
+    X = _f32(X)
+    n = X.shape[0]
+    order = hmerge_order(seed, n)
+    Xp = X[order]
+    ids = dist = None
+    layers, below = [], 0
+    for l, (rows, kk) in enumerate(hmerge_layers(n, n_top, k)):
+        s_l = splitmix64(seed ^ splitmix64(l))
+        base = Xp[:below] if below else None
+        ids, dist, _ = jmerge(base, (ids, dist), Xp[below:rows], kk, metric,
+                              keep_ratio=keep_ratio, sample=sample, delta=delta,
+                              max_rounds=max_rounds, seed=s_l)
+        layers.append((ids, dist))
+        below = rows
+    return order, layers
+
+
+def diversify(X, G, max_deg, metric="l2"):
+    """Graph diversification (Algorithm 3, Section 4) of G = (ids, dist) over
+    the rows of X: Algorithm 3 on every list and on every reverse list, the
+    two merged, the max_deg closest kept.  Returns (ids, dist)."""
+    X = _f32(X)
+    n, d = X.shape
+    gi, gd = _i32(G[0]), _f32(G[1])
+    k = gi.shape[1]
+    ids = np.empty((n, max_deg), np.int32)
+    dist = np.empty((n, max_deg), np.float32)
+    _check(lib().orc_diversify(_ptr(X), n, d, _metric(metric), _ptr(gi), _ptr(gd), k, max_deg,
+                               _ptr(ids), _ptr(dist)), "diversify")
+    return ids, dist
+
+
+def search(X, layers, Q, topk, ef, seed=0, metric="l2"):
+    """Top-down NN search over a graph hierarchy (Section 4): layers[l] =
+    ids (rows_l, deg_l) over the first rows_l rows of X, top layer first,
+    the last layer holding every row.  Greedy descent on the upper layers
+    from a seeded random top vertex, then a best-first search with a ranked
+    list of ef entries on the bottom layer.  Returns (ids, dist, evals)."""
+    X, Q = _f32(X), _f32(Q)
+    d = X.shape[1]
+    arrs = [_i32(a) for a in layers]
+    nl = len(arrs)
+    ptrs = (ctypes.c_void_p * nl)(*[a.ctypes.data for a in arrs])
+    rows = np.array([a.shape[0] for a in arrs], np.int64)
+    deg = np.array([a.shape[1] for a in arrs], np.int32)
+    nq = Q.shape[0]
+    ids = np.empty((nq, topk), np.int32)
+    dist = np.empty((nq, topk), np.float32)
+    ev = ctypes.c_int64()
+    _check(lib().orc_search(_ptr(X), d, _metric(metric), ctypes.cast(ptrs, ctypes.c_void_p),
+                            _ptr(rows), _ptr(deg), nl, _ptr(Q), nq, topk, ef,
+                            seed & (2 ** 64 - 1), _ptr(ids), _ptr(dist), ctypes.byref(ev)),
+           "search")
+    return ids, dist, int(ev.value)
 
 
 # --------------------------------------------------------------------------
