@@ -257,6 +257,82 @@ size_t knng_hmerge_workspace_size(int64_t n, int32_t d, int32_t k, int64_t n_top
                                   knng_metric metric, const knng_opts *opts);
 
 /*
+ * ------------------------------------------------ hierarchy, diversification, search
+ * Section 4: the layers H-Merge builds form a hierarchy for NN search; each
+ * layer's graph is diversified (Algorithm 3) and the search descends from the
+ * top layer to the bottom one.
+ *
+ * knng_hierarchy_shape: the layers of knng_hmerge for n rows, top block
+ * n_top and list size k: returns the layer count L (0 on bad arguments) and
+ * writes the first min(L, cap) layer sizes to rows (host, may be NULL) and
+ * list sizes to lists (host, may be NULL).  Layer l holds the first rows[l]
+ * positions of the random order; rows[L-1] = n.
+ */
+int32_t knng_hierarchy_shape(int64_t n, int64_t n_top, int32_t k, int64_t *rows, int32_t *lists,
+                             int32_t cap);
+
+/*
+ * knng_hmerge keeping its hierarchy (Section 3.3 builds it, Section 4 searches
+ * it).  Arguments and workspace as knng_hmerge, and instead of `out`:
+ *   perm    (device, n int32, may be NULL): perm[i] = the row of X at position i;
+ *   xp      (device, n x d fp32, may be NULL): xp[i] = X[perm[i]];
+ *   layers  (host array of nlayers graphs with device arrays): layer l is
+ *           rows[l] x lists[l] (knng_hierarchy_shape), ids are positions
+ *           (rows of xp), each row sorted by (distance, id), exactly the graph
+ *           H-Merge built on that layer.
+ * Returns after the outputs are complete.  nlayers must equal the layer count.
+ */
+knng_status knng_hmerge_hierarchy(const knng_set *X, int32_t k, int64_t n_top, knng_metric metric,
+                                  const knng_opts *opts, int32_t *perm, float *xp,
+                                  knng_graph *layers, int32_t nlayers, void *workspace,
+                                  size_t workspace_bytes, void *stream, knng_stats *stats);
+
+/*
+ * Graph diversification (Algorithm 3, Section 4) of G (n = X->n rows of
+ * G->k <= 64 entries; ids over the rows of X, -1 = empty; dist REQUIRED, each
+ * row's stored distances m(a, s), canonical values as the merges write
+ * them).  Per row a, Algorithm 3 keeps the nearest entry of a's list and then
+ * every entry s, in (distance, id) order, that no kept entry c occludes
+ * (m(s, c) < m(s, a), m(s, c) evaluated canonically); the same rule runs over
+ * a's reverse list {b : a in G[b]} (at G[b]'s stored distance); the two kept
+ * sets are merged, an id in both taken once, and the max_degree (1..64)
+ * nearest by (distance, id) are written to out (n x max_degree, padded with
+ * -1 / +inf).  Ids out of range, self ids and negative or non-finite
+ * distances are KNNG_EINVAL.  Synchronises the stream before returning.
+ */
+knng_status knng_diversify(const knng_set *X, const knng_graph *G, int32_t max_degree,
+                           knng_metric metric, knng_graph *out, void *workspace,
+                           size_t workspace_bytes, void *stream);
+
+size_t knng_diversify_workspace_size(int64_t n, int32_t d, int32_t k, knng_metric metric);
+
+/*
+ * NN search over a graph hierarchy (Section 4), one query per row of Q
+ * (nq x d, device).  layers[0..nlayers) (host array, device ids; nlayers <=
+ * 32): layer l is a graph over the rows 0 .. layers[l].n - 1 of X (each
+ * layer a prefix of the next and of X; ids -1 = empty; layers[l].k <= 256),
+ * typically the diversified layers of knng_hmerge_hierarchy over xp.
+ *   Stage 1: from the vertex draw_below(H(seed, 0xD1, query, 0, 0),
+ *     layers[0].n) of the top layer, on each upper layer move to the
+ *     nearest neighbour of the current vertex while it is nearer than the
+ *     current vertex, by (distance, id);
+ *   Stage 2: on the bottom layer, a ranked list of at most ef entries starts
+ *     with the vertex reached; the best entry not yet expanded is expanded
+ *     (its neighbours not evaluated before are evaluated and the list keeps
+ *     the ef best), until every entry is expanded.
+ * out_ids / out_dist (device, nq x topk): the first topk entries (ids are
+ * rows of X, canonical distances; padded with -1 / +inf).  1 <= topk <= ef <=
+ * 256.  evals (host, may be NULL): distances evaluated.  Synchronises the
+ * stream before returning.
+ */
+knng_status knng_search(const knng_set *X, const knng_graph *layers, int32_t nlayers,
+                        const knng_set *Q, int32_t topk, int32_t ef, uint64_t seed,
+                        knng_metric metric, int32_t *out_ids, float *out_dist, void *workspace,
+                        size_t workspace_bytes, void *stream, int64_t *evals);
+
+size_t knng_search_workspace_size(int64_t n, int32_t d, int64_t nq, knng_metric metric);
+
+/*
  * knng_merge without a workspace, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Arguments, semantics and errors as knng_merge, except:

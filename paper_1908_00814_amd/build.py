@@ -14,7 +14,7 @@ BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["knng_api.hip", "knng_prep.hip", "knng_round.hip", "knng_join.hip",
-           "knng_brute.hip", "knng_server.hip", "knng_noalloc.hip"]
+           "knng_brute.hip", "knng_server.hip", "knng_noalloc.hip", "knng_search.hip"]
 
 # -ffp-contract=off keeps the canonical FP32 evaluation order unfused; fp32
 # division and sqrt are correctly rounded (IEEE), as on the host; packed FP32

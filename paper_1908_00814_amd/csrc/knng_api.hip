@@ -766,9 +766,19 @@ extern "C" size_t knng_hmerge_workspace_size(int64_t n, int32_t d, int32_t k, in
     }
 }
 
+// Optional outputs of the hierarchy (knng_hmerge_hierarchy): the random
+// order, the permuted rows and every layer's graph over positions.
+struct HOut {
+    int32_t *perm = nullptr;
+    float *xp = nullptr;
+    knng_graph *layers = nullptr;
+    int32_t nlayers = 0;
+};
+
 static knng_status knng_hmerge_impl(const knng_set *X, int32_t k, int64_t n_top, knng_metric metric,
                                     const knng_opts *opts, knng_graph *out, void *workspace,
-                                    size_t workspace_bytes, void *stream, knng_stats *stats)
+                                    size_t workspace_bytes, void *stream, knng_stats *stats,
+                                    const HOut *ho = nullptr)
 {
     knng_status s;
     if ((s = check_metric(metric)) || (s = check_set(X, "X")) || (s = check_opts(opts, k)))
@@ -787,7 +797,21 @@ static knng_status knng_hmerge_impl(const knng_set *X, int32_t k, int64_t n_top,
             return fail(KNNG_EINVAL, "keep_ratio keeps %d entries of a layer with %d-entry lists",
                         keep_count(opts, p.kk[l]), p.kk[l - 1]);
     }
-    if ((s = check_out(out, n, k)))
+    if (ho) {
+        if ((int)p.rows.size() != ho->nlayers || !ho->layers)
+            return fail(KNNG_EINVAL, "the hierarchy has %zu layers, %d given", p.rows.size(),
+                        ho->nlayers);
+        for (size_t l = 0; l < p.rows.size(); l++) {
+            const knng_graph &g = ho->layers[l];
+            if (g.n != p.rows[l] || g.k != p.kk[l] || !is_device_ptr(g.ids) ||
+                !is_device_ptr(g.dist))
+                return fail(KNNG_EINVAL, "layer %zu must be %lld x %d device arrays", l,
+                            (long long)p.rows[l], p.kk[l]);
+        }
+        if ((ho->perm && !is_device_ptr(ho->perm)) || (ho->xp && !is_device_ptr(ho->xp)))
+            return fail(KNNG_EINVAL, "perm / xp must be device memory");
+    }
+    if ((out || !ho) && (s = check_out(out, n, k)))
         return s;
     const size_t need = knng_hmerge_workspace_size(n, X->d, k, n_top, metric, opts);
     if (!workspace || workspace_bytes < need)
@@ -819,6 +843,13 @@ static knng_status knng_hmerge_impl(const knng_set *X, int32_t k, int64_t n_top,
         s = knng_expand(&base, &g, &raw, p.kk[l], metric, &lo, &o, mws, mws_bytes, stream, &one);
         if (s != KNNG_OK)
             return s;
+        if (ho) {
+            const size_t cells = (size_t)p.rows[l] * p.kk[l];
+            HIP_TRY(hipMemcpyAsync(ho->layers[l].ids, o.ids, cells * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(ho->layers[l].dist, o.dist, cells * sizeof(float),
+                                   hipMemcpyDeviceToDevice, st));
+        }
         cur = nxt;
         total.rounds += one.rounds;
         total.evals += one.evals;
@@ -842,10 +873,61 @@ static knng_status knng_hmerge_impl(const knng_set *X, int32_t k, int64_t n_top,
         }
     }
     // back to the caller's row numbering
-    HIP_TRY(launch_unpermute_graph(h.ids[cur], h.dist[cur], n, k, h.perm, out->ids, out->dist, st));
+    if (out)
+        HIP_TRY(launch_unpermute_graph(h.ids[cur], h.dist[cur], n, k, h.perm, out->ids,
+                                       out->dist, st));
+    if (ho && ho->perm)
+        HIP_TRY(hipMemcpyAsync(ho->perm, h.perm, (size_t)n * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, st));
+    if (ho && ho->xp)
+        HIP_TRY(hipMemcpyAsync(ho->xp, h.xp, (size_t)n * X->d * sizeof(float),
+                               hipMemcpyDeviceToDevice, st));
+    if (ho)
+        HIP_TRY(hipStreamSynchronize(st));
     if (stats)
         *stats = total;
     return ok();
+}
+
+extern "C" int32_t knng_hierarchy_shape(int64_t n, int64_t n_top, int32_t k, int64_t *rows,
+                                        int32_t *lists, int32_t cap)
+{
+    if (n < 2 || n_top < 2 || k < 1)
+        return 0;
+    try {
+        const HPlan p = hmerge_plan(n, n_top, k);
+        for (size_t l = 0; l < p.rows.size() && (int32_t)l < cap; l++) {
+            if (rows)
+                rows[l] = p.rows[l];
+            if (lists)
+                lists[l] = p.kk[l];
+        }
+        return (int32_t)p.rows.size();
+    } catch (...) {
+        return 0;
+    }
+}
+
+extern "C" knng_status knng_hmerge_hierarchy(const knng_set *X, int32_t k, int64_t n_top,
+                                             knng_metric metric, const knng_opts *opts,
+                                             int32_t *perm, float *xp, knng_graph *layers,
+                                             int32_t nlayers, void *workspace,
+                                             size_t workspace_bytes, void *stream,
+                                             knng_stats *stats)
+{
+    try {
+        HOut ho;
+        ho.perm = perm;
+        ho.xp = xp;
+        ho.layers = layers;
+        ho.nlayers = nlayers;
+        return knng_hmerge_impl(X, k, n_top, metric, opts, nullptr, workspace, workspace_bytes,
+                                stream, stats, &ho);
+    } catch (const std::bad_alloc &) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    } catch (...) {
+        return fail(KNNG_EDEVICE, "unexpected host exception");
+    }
 }
 
 extern "C" knng_status knng_hmerge(const knng_set *X, int32_t k, int64_t n_top,

@@ -31,7 +31,9 @@ ENTRY_POINTS = ["knng_opts_default", "knng_merge", "knng_merge_workspace_size", 
                 "knng_server_create", "knng_server_submit", "knng_server_step",
                 "knng_server_wait", "knng_server_snapshot", "knng_server_rebase",
                 "knng_server_status", "knng_server_slots", "knng_server_destroy",
-                "knng_merge_noalloc", "knng_merge_noalloc_scratch_bytes"]
+                "knng_merge_noalloc", "knng_merge_noalloc_scratch_bytes",
+                "knng_hierarchy_shape", "knng_hmerge_hierarchy", "knng_diversify",
+                "knng_diversify_workspace_size", "knng_search", "knng_search_workspace_size"]
 
 
 class Opts(ctypes.Structure):
@@ -116,6 +118,20 @@ def load():
     lib.knng_opts_default.argtypes = [pO]
     lib.knng_merge.restype = ctypes.c_int
     lib.knng_merge.argtypes = [pS, pG, pS, pG, I32, ctypes.c_int, pO, pG, P, SZ, P, pSt]
+    lib.knng_hierarchy_shape.restype = I32
+    lib.knng_hierarchy_shape.argtypes = [I64, I64, I32, P, P, I32]
+    lib.knng_hmerge_hierarchy.restype = ctypes.c_int
+    lib.knng_hmerge_hierarchy.argtypes = [pS, I32, I64, ctypes.c_int, pO, P, P, pG, I32, P, SZ,
+                                          P, pSt]
+    lib.knng_diversify.restype = ctypes.c_int
+    lib.knng_diversify.argtypes = [pS, pG, I32, ctypes.c_int, pG, P, SZ, P]
+    lib.knng_diversify_workspace_size.restype = SZ
+    lib.knng_diversify_workspace_size.argtypes = [I64, I32, I32, ctypes.c_int]
+    lib.knng_search.restype = ctypes.c_int
+    lib.knng_search.argtypes = [pS, pG, I32, pS, I32, I32, ctypes.c_uint64, ctypes.c_int, P, P,
+                                P, SZ, P, ctypes.POINTER(I64)]
+    lib.knng_search_workspace_size.restype = SZ
+    lib.knng_search_workspace_size.argtypes = [I64, I32, I64, ctypes.c_int]
     lib.knng_merge_noalloc.restype = ctypes.c_int
     lib.knng_merge_noalloc.argtypes = [pS, pG, pS, pG, I32, ctypes.c_int, pO, pG, P, pSt]
     lib.knng_merge_noalloc_scratch_bytes.restype = SZ
@@ -384,6 +400,75 @@ def hmerge(X, k, n_top, metric="l2", stream=None, workspace=None, **kw):
     d["layer_rounds"] = [st.pairs[lvl] for lvl in layers]
     d["layer_ms"] = [st.gathered[lvl] / 1e3 for lvl in layers]
     return ids, dist, d
+
+
+def hierarchy_shape(n, n_top, k):
+    """[(rows, list size)] of the H-Merge layers, top first."""
+    lib = load()
+    L = lib.knng_hierarchy_shape(n, n_top, k, None, None, 0)
+    rows = (ctypes.c_int64 * max(L, 1))()
+    lists = (ctypes.c_int32 * max(L, 1))()
+    lib.knng_hierarchy_shape(n, n_top, k, rows, lists, L)
+    return [(rows[i], lists[i]) for i in range(L)]
+
+
+def hmerge_hierarchy(X, k, n_top, metric="l2", stream=None, workspace=None, **kw):
+    """H-Merge keeping its layers (knng_hmerge_hierarchy).  Returns (perm,
+    xp, layers, stats): perm[i] = the row at position i, xp = X[perm], and
+    layers[l] = (ids, dist) over positions, top layer first."""
+    lib = load()
+    o = opts(**kw)
+    n, d = X.shape
+    shape = hierarchy_shape(n, n_top, k)
+    need = lib.knng_hmerge_workspace_size(n, d, k, n_top, _metric(metric), ctypes.byref(o))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    perm = torch.empty(n, dtype=torch.int32, device=X.device)
+    xp = torch.empty((n, d), dtype=torch.float32, device=X.device)
+    layers = [_out(r, kk, X.device) for r, kk in shape]
+    gs = (Graph * len(layers))(*[_graph(i, dd) for i, dd in layers])
+    st = Stats()
+    _check(lib.knng_hmerge_hierarchy(ctypes.byref(_set(X)), k, n_top, _metric(metric),
+                                     ctypes.byref(o), _ptr(perm), _ptr(xp), gs, len(layers),
+                                     _ptr(workspace), workspace.numel(), _stream(stream),
+                                     ctypes.byref(st)))
+    return perm, xp, layers, st.to_dict()
+
+
+def diversify(X, G, max_degree, metric="l2", stream=None):
+    """Graph diversification (knng_diversify) of G = (ids, dist) over the rows
+    of X.  Returns (ids, dist), max_degree columns."""
+    lib = load()
+    n, d = X.shape
+    need = lib.knng_diversify_workspace_size(n, d, G[0].shape[1], _metric(metric))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    ids, dist = _out(n, max_degree, X.device)
+    _check(lib.knng_diversify(ctypes.byref(_set(X)), ctypes.byref(_graph(*G)), max_degree,
+                              _metric(metric), ctypes.byref(_graph(ids, dist)), _ptr(ws),
+                              ws.numel(), _stream(stream)))
+    return ids, dist
+
+
+def search(X, layers, Q, topk, ef, seed=0, metric="l2", stream=None):
+    """Top-down NN search (knng_search) of the rows of Q over layer graphs
+    (ids tensors, or (ids, dist) pairs) over prefixes of X, top first.
+    Returns (ids, dist, evals)."""
+    lib = load()
+    n, d = X.shape
+    nq = Q.shape[0]
+    need = lib.knng_search_workspace_size(n, d, nq, _metric(metric))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    ids_l = [L[0] if isinstance(L, (tuple, list)) else L for L in layers]
+    gs = (Graph * len(ids_l))(*[Graph(t.shape[0], t.shape[1], t.data_ptr(), None)
+                                for t in ids_l])
+    for t in ids_l:
+        assert t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()
+    ids, dist = _out(nq, topk, X.device)
+    ev = ctypes.c_int64()
+    _check(lib.knng_search(ctypes.byref(_set(X)), gs, len(ids_l), ctypes.byref(_set(Q)), topk,
+                           ef, seed & (2 ** 64 - 1), _metric(metric), _ptr(ids), _ptr(dist),
+                           _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(ev)))
+    return ids, dist, ev.value
 
 
 def version():
