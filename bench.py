@@ -582,6 +582,80 @@ def fig4_bench(args, dev):
                         "swept at five size ratios", "rows": out}
 
 
+def search_bench(args, dev, Xclust):
+    """NN search over the H-Merge hierarchy (Section 4): H-Merge (k = 40, as in
+    the paper's search experiments) keeps its layers, each layer is
+    diversified (Algorithm 3, at most k/2 = 20 neighbours), and 10,000 held-out
+    queries descend the hierarchy; recall@1 against the exact nearest
+    neighbour (FP64, tie-tolerant) and queries/s for several ranked-list sizes
+    ef, beside the same search on the bottom layer alone ("flat").  Two sets
+    of 1,000,000 rows: uniform in [0,1)^32 (like the paper's random d=32 set)
+    and the byte-valued clusters of the merge workload (1,000 well separated
+    clusters: the bottom graph has no edges between clusters)."""
+    import torch
+    import synth
+    from paper_1908_00814_amd import knng
+    k, n_top, nq = 40, 15_625, 10_000
+    g = synth.rng(7001)
+    sets = {"uniform_d32": (g.random((1_000_000, 32), dtype=np.float32),
+                            g.random((nq, 32), dtype=np.float32)),
+            "clusters_d128": (Xclust, synth.byte_cluster_points(nq, workload=2, stream=71))}
+    res = {"workload": "H-Merge hierarchy (k=40, top block 15,625) of 1,000,000 rows, layers "
+                       "diversified to at most 20 neighbours, 10,000 held-out queries of the "
+                       "same law, squared l2, top-1; uniform [0,1)^32 and the byte-valued "
+                       "clusters (d=128)"}
+    kw = dict(sample=args.sample, delta=args.delta, seed=args.seed + 9)
+    for name, (X, Q) in sets.items():
+        dX = torch.from_numpy(X).to(dev)
+        dQ = torch.from_numpy(Q).to(dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        perm, xp, layers, hst = knng.hmerge_hierarchy(dX, k, n_top, "l2", **kw)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t
+        del dX
+        t = time.perf_counter()
+        div = [knng.diversify(xp[:L[0].shape[0]].contiguous(), L, k // 2)[0] for L in layers]
+        torch.cuda.synchronize()
+        t_div = time.perf_counter() - t
+        deg = [float((d_ >= 0).sum(1).float().mean().item()) for d_ in div]
+        del layers
+        # FP64 distance of the exact nearest row (positions of xp) of each query
+        Xd = xp.to(torch.float64)
+        sq = (Xd * Xd).sum(1)
+        best = torch.empty(nq, dtype=torch.float64, device=dev)
+        for lo in range(0, nq, 500):
+            qd = dQ[lo:lo + 500].to(torch.float64)
+            D = (qd * qd).sum(1)[:, None] + sq[None, :] - 2.0 * (qd @ Xd.T)
+            best[lo:lo + 500] = D.min(1)[0]
+            del D
+        out = {"build_ms": t_build * 1e3, "diversify_ms": t_div * 1e3,
+               "layers": [[int(L_.shape[0]), int(L_.shape[1])] for L_ in div],
+               "mean_degree": deg, "hierarchy": [], "flat": []}
+        for mode, use in (("hierarchy", div), ("flat", div[-1:])):
+            for ef in (10, 20, 40, 80, 160):
+                knng.search(xp, use, dQ[:256], 1, ef, seed=3)      # warm-up
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                ids, _, ev = knng.search(xp, use, dQ, 1, ef, seed=3)
+                torch.cuda.synchronize()
+                secs = time.perf_counter() - t
+                got = Xd[ids[:, 0].long()]
+                dg = ((got - dQ.to(torch.float64)) ** 2).sum(1)
+                rec = float((dg <= best + 1e-9 * (1.0 + best.abs())).float().mean().item())
+                out[mode].append({"ef": ef, "recall@1": rec, "queries_per_s": nq / secs,
+                                  "evals_per_query": ev / nq})
+                log(f"[search] {name} {mode} ef={ef}: recall@1 {rec:.4f}, {nq / secs:,.0f} "
+                    f"queries/s, {ev / nq:.0f} distances/query")
+        log(f"[search] {name}: hierarchy built in {t_build * 1e3:.0f} ms, diversified in "
+            f"{t_div * 1e3:.0f} ms, layers {out['layers']}, mean degree "
+            f"{[round(v, 1) for v in deg]}")
+        res[name] = out
+        del xp, perm, div, Xd, dQ
+        torch.cuda.empty_cache()
+    return res
+
+
 def c1_bench(args, dev):
     """The small workload: S-Merge of two sets of 5,000 x d32 i.i.d. N(0,1)
     rows with exact k=10 input graphs, merged to k=10 with s=10, delta 0,
@@ -727,6 +801,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=25_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c1", action="store_true", help="skip the 2 x 5,000 x d32 workload")
+    ap.add_argument("--no-search", action="store_true",
+                    help="skip the hierarchy / diversification / search workload")
     ap.add_argument("--only", choices=["fp32", "bf16"], default=None,
                     help="time one path only (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -870,6 +946,9 @@ def main():
         line["complexity"] = complexity_bench(args, dev, dS1, dG1, dS2, X, rows, paths[best])
     del dS1, dS2, dG1, dG2
     torch.cuda.empty_cache()
+    if not args.no_search:
+        line["search"] = search_bench(args, dev, X)
+        torch.cuda.empty_cache()
     if not args.no_table2:
         line["table2"] = table2_bench(args, dev)
         line["fig4"] = fig4_bench(args, dev)
