@@ -423,6 +423,10 @@ typedef struct {
     uint64_t hbm_budget; /* device bytes the server may allocate; 0 = no limit */
     int32_t slots;       /* requests on the device at once; 0 = run in knng_server_step */
     int32_t batching;    /* 1: a slot merges all queued requests that fit as one raw set */
+    int32_t host_rounds; /* 0: each slot runs the rounds of its merges as a launch graph of
+                            one round, captured once and replayed (the device ends the loop;
+                            one read-back per block of rounds); 1: one host round trip per
+                            round (the merges' own loop) */
 } knng_server_config;
 
 typedef struct {
@@ -471,7 +475,8 @@ knng_status knng_server_submit(knng_server *srv, const float *raw, int64_t n_raw
                                uint64_t *ticket);
 
 /* servers without slots: runs the oldest queued request (*ran = 0 when none
- * was queued) */
+ * was queued); the request's own result is collected by knng_server_wait,
+ * and step returns an error only when the server has failed */
 knng_status knng_server_step(knng_server *srv, int32_t *ran);
 
 /*
@@ -500,6 +505,16 @@ knng_status knng_server_status(knng_server *srv, int64_t *base_rows, int64_t *co
 
 /* slots the server runs (after the budget) */
 int32_t knng_server_slots(const knng_server *srv);
+
+/*
+ * Failure isolation, test hook: the next request submitted (or queued) with
+ * this req_id fails with KNNG_EDEVICE after its merge ran and before its
+ * commit, as a request whose merge reported an error would.  A request that
+ * fails before its commit fails alone: the base and the resident graph are
+ * untouched, its rows keep their ids with empty lists (-1 / +inf), and the
+ * server goes on serving.  (A failure during a commit stops the server.)
+ */
+knng_status knng_server_fail_request(knng_server *srv, uint64_t req_id);
 
 /* Lets the requests in slots finish, then frees everything; queued requests
  * are dropped. */

@@ -62,6 +62,88 @@ knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
     return KNNG_OK;
 }
 
+// Graph mode: capture the slot's round once (sampling, the last round's
+// count, the loop control, Reverse(G), the local join, the round advance),
+// then per merge set the device round state and replay the round until the
+// device has ended the loop.
+static knng_status replay_rounds(const Rows &R, const Layout &w, knng_metric metric, bool bf16,
+                                 const knng_opts *o, const RoundArgs &a0, int64_t n, int64_t n1,
+                                 hipStream_t st, int *rounds)
+{
+    RoundGraph &G = *w.graph;
+    if (!G.exec) {
+        // grids of the captured launches are sized for the slot's largest merge
+        RoundArgs ag = a0;
+        ag.dev = w.dev;
+        ag.n = G.rows_cap;
+        ag.n_active = G.rows_cap;
+        ag.rev_m = G.rows_cap;
+        Rows Rg = R;
+        Rg.n = G.rows_cap;
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipError_t e = launch_sample(ag, st);
+        if (e == hipSuccess)
+            e = launch_count_fresh(ag, st);
+        if (e == hipSuccess)
+            e = launch_round_ctl(ag, a0.k, st);
+        if (e == hipSuccess)
+            e = launch_prep_active(ag, st);
+        if (e == hipSuccess)
+            e = launch_reverse_indexed(ag, st);
+        if (e == hipSuccess)
+            e = launch_join(Rg, (int)metric, bf16 ? 1 : 0, ag, st);
+        if (e == hipSuccess)
+            e = launch_round_next(ag, st);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(st, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return fail(KNNG_EDEVICE, "capturing the round graph failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        G.graph = g;
+        HIP_TRY(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+    }
+    DevRound v{};
+    v.round = 0;
+    v.done = 0;
+    v.rounds = 0;
+    v.tag0 = a0.tag0;
+    v.max_rounds = o->max_rounds;
+    v.n = n;
+    v.n1 = n1;
+    v.n_active = 0;
+    v.rev_m = a0.rev_m;
+    v.split = R.split;
+    v.off2 = R.off2;
+    v.seed = o->seed;
+    v.delta = (double)o->delta;
+    HIP_TRY(launch_set_round(w.dev, v, st));
+    // round t ends the loop in replay t + 1; most merges take 6-12 rounds
+    int replays = 0;
+    for (int block = 8;; block = 4) {
+        for (int b = 0; b < block; b++)
+            HIP_TRY(hipGraphLaunch(G.exec, st));
+        replays += block;
+        DevRound hd;
+        HIP_TRY(hipMemcpyAsync(&hd, w.dev, sizeof hd, hipMemcpyDeviceToHost, st));
+        uint64_t h[C_WORDS];
+        knng_status s = read_ctr(w.ctr, h, st);
+        if (s != KNNG_OK)
+            return s;
+        if (h[C_ERR])
+            return fail(KNNG_EDEVICE, "%s", err_text(h[C_ERR]));
+        if (hd.done) {
+            *rounds = hd.rounds;
+            return KNNG_OK;
+        }
+        if (replays > o->max_rounds + 1)
+            return fail(KNNG_EDEVICE, "the round graph did not end the loop in %d replays",
+                        replays);
+    }
+}
+
 // the repeat loop and Merge and Sort, shared by S-Merge and J-Merge
 knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool bf16,
                       const knng_opts *o, int64_t n, int64_t n1, int k, int k1, int joint,
@@ -116,7 +198,14 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     a.seed = o->seed;
     uint64_t h[C_WORDS];
     int rounds = 0;
-    for (int t = 0;; t++) {
+    if (w.graph) {
+        // graph mode: the round is a captured launch graph, replayed in blocks
+        // with one read-back per block; the device ends the loop itself
+        knng_status gs = replay_rounds(R, w, metric, bf16, o, a, n, n1, st, &rounds);
+        if (gs != KNNG_OK)
+            return gs;
+    }
+    for (int t = 0; !w.graph; t++) {
         const bool last = t == o->max_rounds;
         a.round = t;
         prof.begin(PH_SAMPLE);

@@ -61,6 +61,14 @@ struct Carve {
     }
 };
 
+// A slot's repeat loop captured once as a launch graph of one round (graph
+// mode, see DevRound); replayed for every round of every request.
+struct RoundGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t rows_cap = 0;   // most rows a merge of the slot has (grid sizes)
+};
+
 struct Layout {
     uint64_t *ctr;
     float *x, *norm, *sq, *eb;
@@ -77,6 +85,9 @@ struct Layout {
     int32_t tag0 = 0;
     bool incremental = false;
     int32_t *alist = nullptr;  // n words: the round's active rows (list mode)
+    // graph mode (server slots): the device round state and the slot's graph
+    DevRound *dev = nullptr;
+    RoundGraph *graph = nullptr;
 };
 
 // SplitMix64 (one step of the published generator), for seeds derived on the host

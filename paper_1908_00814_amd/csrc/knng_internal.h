@@ -24,6 +24,24 @@ struct Rows {
     __host__ __device__ int64_t phys(int64_t i) const { return i < split ? i : i + off2; }
 };
 
+// Round state of a merge whose repeat loop runs as a replayed launch graph
+// (a server slot): the scalars that change between requests and rounds live
+// here, on the device, and every kernel of the round reads them at entry
+// instead of its by-value arguments; `done` makes the rest of a replay, and
+// every later replay, return at once.
+struct DevRound {
+    int32_t round;      // t, advanced at the end of each round
+    int32_t done;       // the loop has ended
+    int32_t rounds;     // rounds run (valid once done)
+    int32_t tag0;
+    int32_t max_rounds;
+    int32_t pad;
+    int64_t n, n1, n_active, rev_m;
+    int64_t split, off2;  // row view of the merge (Rows::phys)
+    uint64_t seed;
+    double delta;
+};
+
 // Parameters of one iteration of the merge loop.
 struct RoundArgs {
     uint64_t *L;        // n x k list words
@@ -72,7 +90,40 @@ struct RoundArgs {
     int joint;          // 0: S-Merge predicate, 1: J-Merge predicate
     uint64_t seed;
     int round;
+    // graph mode: the round state on the device (nullptr: host-driven loop,
+    // every scalar above is valid as passed)
+    const DevRound *dev = nullptr;
 };
+
+// Graph mode: a kernel's by-value arguments updated from the device round
+// state; false when the loop has ended (the kernel returns at once).
+__device__ inline bool take_round(RoundArgs &a)
+{
+    if (!a.dev)
+        return true;
+    const DevRound *d = a.dev;
+    if (d->done)
+        return false;
+    a.round = d->round;
+    a.tag0 = d->tag0;
+    a.n = d->n;
+    a.n1 = d->n1;
+    a.n_active = d->n_active;
+    a.rev_m = d->rev_m;
+    a.seed = d->seed;
+    return true;
+}
+__device__ inline bool take_round(RoundArgs &a, Rows &R)
+{
+    if (!take_round(a))
+        return false;
+    if (a.dev) {
+        R.n = a.dev->n;
+        R.split = a.dev->split;
+        R.off2 = a.dev->off2;
+    }
+    return true;
+}
 
 // ---- knng_prep.hip
 hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2, int d, int dp,
@@ -150,6 +201,7 @@ hipError_t launch_sort_rows(const uint64_t *src, int src_stride, int64_t n, int 
                             uint64_t *dst, int dst_stride, int32_t *ids, float *dist,
                             hipStream_t st);
 hipError_t launch_zero_counters(uint64_t *ctr, int words, hipStream_t st);
+hipError_t launch_fill_empty(uint64_t *p, int64_t rows, int k, hipStream_t st);
 
 // ---- H-Merge (knng_prep.hip)
 // Random order of n rows (the blocks H-Merge joins in are random subsets):
@@ -179,6 +231,15 @@ hipError_t launch_build_rindex(const uint64_t *gin, int gs, int kk, int64_t m, i
                                int32_t *src, int32_t *deg, int64_t *part, uint64_t *ctr,
                                hipStream_t st);
 hipError_t launch_count_fresh(const RoundArgs &a, hipStream_t st);
+// Graph mode.  set_round: the state at the start of a merge's loop (round 0).
+// round_ctl, after the round's sampling: ends the loop when round t > 0 left
+// c <= delta*n0*k entries, when t = max_rounds, or on an error bit (rounds =
+// t); otherwise copies the round's active-row count and clears the per-round
+// counters.  round_next, after the join: t += 1.  Grids of the graph-mode
+// launches are fixed by `rows_cap` (the most rows a merge of the slot has).
+hipError_t launch_set_round(DevRound *d, const DevRound &v, hipStream_t st);
+hipError_t launch_round_ctl(const RoundArgs &a, int k, hipStream_t st);
+hipError_t launch_round_next(const RoundArgs &a, hipStream_t st);
 
 // ---- knng_join.hip
 hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, hipStream_t st);

@@ -427,6 +427,8 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, MU == 4 ? 4 : 2) void k_join(Row
                                                             int wave_bytes)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
+    if (!take_round(a, R))
+        return;
     const int lane = lane_id();
     const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS, a.s, a.k, false);
     // the insert queue lives across tiles and rows: it is drained in whole
@@ -615,6 +617,8 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
                                                                  int wave_bytes)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
+    if (!take_round(a, R))
+        return;
     const int lane = lane_id();
     const WaveLds L = carve_lds(dyn + (size_t)(threadIdx.x / WAVE) * wave_bytes, GS, a.s, a.k, true);
     // queue word: slot r | slot c << 8 | (p gets q) << 16 | (q gets p) << 17 in
@@ -847,7 +851,8 @@ hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, 
         return hipErrorInvalidValue;  // neighbourhood larger than the staging bound
     const bool small = units <= 4 * WAVE;
     const int64_t rows = a.alist ? a.n_active : a.n;  // list mode: the listed rows
-    const int64_t waves = rows < 32768 ? rows : 32768;
+    // graph mode: a fixed grid whose waves walk however many rows are listed
+    const int64_t waves = a.dev ? 8192 : (rows < 32768 ? rows : 32768);
     int64_t grid = (waves + JOIN_WAVES - 1) / JOIN_WAVES;
     if (grid < 1)
         grid = 1;

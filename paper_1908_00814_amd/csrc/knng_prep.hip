@@ -710,6 +710,22 @@ hipError_t launch_unpermute_graph(const int32_t *ids, const float *dist, int64_t
     return hipGetLastError();
 }
 
+// rows x k list words set to empty slots (~0 - slot)
+__global__ __launch_bounds__(256) void k_fill_empty(uint64_t *p, int64_t rows, int k)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < rows * k;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = empty_key((int)(e % k));
+}
+
+hipError_t launch_fill_empty(uint64_t *p, int64_t rows, int k, hipStream_t st)
+{
+    int64_t g = (rows * k + 255) / 256;
+    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
+    hipLaunchKernelGGL(k_fill_empty, dim3((unsigned)g), dim3(256), 0, st, p, rows, k);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_counters(uint64_t *ctr, int words, hipStream_t st)
 {
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, ctr, words);

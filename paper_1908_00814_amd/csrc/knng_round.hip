@@ -21,6 +21,10 @@ namespace {
 // again in round t+1.  The FRESH count of round t-1 is accumulated per wave.
 __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
 {
+    // graph mode: round max_rounds only counts the last round's entries
+    // (k_count_fresh), as the host-driven loop does
+    if (!take_round(a) || (a.dev && a.round >= a.dev->max_rounds))
+        return;
     const int lane = lane_id();
     const int32_t tr = a.tag0 + a.round;
     int fresh_total = 0;
@@ -107,6 +111,8 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
 // sampled (all its entries OLD) takes its whole list as its OLD sample.
 __global__ __launch_bounds__(256) void k_prep_active(RoundArgs a)
 {
+    if (!take_round(a))
+        return;
     const int lane = lane_id();
     const int32_t tr = a.tag0 + a.round;
     FOR_ACTIVE_ROWS(u, a, tr)
@@ -156,6 +162,8 @@ __device__ inline void offer_reverse(const RoundArgs &a, int64_t v, int64_t u, i
 // joined.
 __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
 {
+    if (!take_round(a))
+        return;
     const int per = a.s + a.k;
     const int64_t total = a.n * per;
     const int32_t tr = a.tag0 + a.round;
@@ -205,6 +213,8 @@ __global__ __launch_bounds__(256) void k_reverse(RoundArgs a)
 // row, edges as in k_reverse.
 __global__ __launch_bounds__(256) void k_reverse_rows(RoundArgs a)
 {
+    if (!take_round(a))
+        return;
     const int lane = lane_id();
     const int32_t *dtag = a.dtag;
     const int32_t tag0 = a.tag0, tr = a.tag0 + a.round;
@@ -249,6 +259,8 @@ __global__ __launch_bounds__(256) void k_reverse_rows(RoundArgs a)
 __global__ __launch_bounds__(256) void k_reverse_base(RoundArgs a)
 {
     __shared__ uint64_t keep_all[256 / WAVE][MAX_S];
+    if (!take_round(a))
+        return;
     const int lane = lane_id();
     uint64_t *keep = keep_all[threadIdx.x / WAVE];
     const int32_t tr = a.tag0 + a.round;
@@ -435,6 +447,9 @@ __global__ __launch_bounds__(256) void k_ri_fill(const uint64_t *gin, int gs, in
 // count the FRESH entries left by the last round (statistics only)
 __global__ __launch_bounds__(256) void k_count_fresh(RoundArgs a)
 {
+    // graph mode: only in round max_rounds (otherwise k_sample counts)
+    if (!take_round(a) || (a.dev && a.round < a.dev->max_rounds))
+        return;
     const int64_t total = a.n * a.k;
     int c = 0;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -445,6 +460,41 @@ __global__ __launch_bounds__(256) void k_count_fresh(RoundArgs a)
     c = wave_sum(c);
     if (lane_id() == 0 && c)
         atomicAdd((unsigned long long *)(a.ctr + C_FRESH), (unsigned long long)c);
+}
+
+// graph mode: the round state at the start of a merge's loop
+__global__ void k_set_round(DevRound *d, DevRound v)
+{
+    if (threadIdx.x == 0)
+        *d = v;
+}
+
+// graph mode, after the round's sampling: stop test of the repeat loop (as
+// in the host-driven loop: c of round t-1 against delta*n0*k for t > 0, the
+// round cap, error bits), else the round's active rows and cleared per-round
+// counters
+__global__ void k_round_ctl(DevRound *d, uint64_t *ctr, int k)
+{
+    if (threadIdx.x != 0 || d->done)
+        return;
+    const int t = d->round;
+    bool stop = ctr[C_ERR] != 0 || t >= d->max_rounds;
+    if (t > 0 && (double)ctr[C_FRESH] <= d->delta * (double)ctr[C_N0] * (double)k)
+        stop = true;
+    if (stop) {
+        d->rounds = t;
+        d->done = 1;
+        return;
+    }
+    d->n_active = (int64_t)ctr[C_ACTIVE];
+    for (int w = 0; w < C_ROUND_WORDS; w++)
+        ctr[w] = 0;
+}
+
+__global__ void k_round_next(DevRound *d)
+{
+    if (threadIdx.x == 0 && !d->done)
+        d->round++;
 }
 
 inline unsigned grid_for(int64_t items, int per_block, unsigned cap)
@@ -466,10 +516,14 @@ hipError_t launch_sample(const RoundArgs &a, hipStream_t st)
 // rows an active-row kernel walks: the list, or all n
 inline int64_t active_span(const RoundArgs &a) { return a.alist ? a.n_active : a.n; }
 
+// graph mode: workgroups of the active-row kernels (their waves walk any
+// number of listed rows)
+constexpr unsigned GRAPH_ACTIVE_BLOCKS = 1024;
+
 hipError_t launch_prep_active(const RoundArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_prep_active, dim3(grid_for(active_span(a), 4, 8192)), dim3(256), 0, st,
-                       a);
+    const unsigned g = a.dev ? GRAPH_ACTIVE_BLOCKS : grid_for(active_span(a), 4, 8192);
+    hipLaunchKernelGGL(k_prep_active, dim3(g), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -483,9 +537,10 @@ hipError_t launch_reverse(const RoundArgs &a, hipStream_t st)
 hipError_t launch_reverse_indexed(const RoundArgs &a, hipStream_t st)
 {
     // base first: it writes the reservoirs of its targets without atomics
-    if (a.rev_m > 0)
-        hipLaunchKernelGGL(k_reverse_base, dim3(grid_for(active_span(a), 4, 8192)), dim3(256), 0,
-                           st, a);
+    if (a.rev_m > 0 || a.dev)
+        hipLaunchKernelGGL(k_reverse_base,
+                           dim3(a.dev ? GRAPH_ACTIVE_BLOCKS : grid_for(active_span(a), 4, 8192)),
+                           dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_reverse_rows, dim3(grid_for(a.n, 4, 8192)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
@@ -507,6 +562,25 @@ hipError_t launch_build_rindex(const uint64_t *gin, int gs, int kk, int64_t m, i
     hipLaunchKernelGGL(k_ri_offsets, dim3((unsigned)parts), dim3(256), 0, st, deg, m, part, off);
     hipLaunchKernelGGL(k_ri_fill, dim3(grid_for(m * kk, 256, 1u << 16)), dim3(256), 0, st, gin,
                        gs, kk, m, off, deg, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_round(DevRound *d, const DevRound &v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_round, dim3(1), dim3(64), 0, st, d, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_ctl(const RoundArgs &a, int k, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_round_ctl, dim3(1), dim3(64), 0, st, const_cast<DevRound *>(a.dev),
+                       a.ctr, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_next(const RoundArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_round_next, dim3(1), dim3(64), 0, st, const_cast<DevRound *>(a.dev));
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <set>
 #include <mutex>
 #include <shared_mutex>
 #include <thread>
@@ -40,7 +41,7 @@ enum ReqState { Q_PENDING = 0, Q_RUNNING = 1, Q_DONE = 2 };
 
 struct Request {
     int64_t first = 0, n = 0;
-    uint64_t seed = 0;
+    uint64_t seed = 0, req_id = 0;
     int state = Q_PENDING;
     knng_status rc = KNNG_OK;
     std::string err;
@@ -67,6 +68,10 @@ struct Slot {
     // initialised in full (first merge, after a rebase or a failed merge).
     int32_t tag0 = 0, prev_tag0 = 0;
     bool fresh = true;
+    // the repeat loop as a launch graph of one round, captured on the first
+    // request, and its device round state
+    RoundGraph graph{};
+    DevRound *dev = nullptr;
 };
 
 } // namespace
@@ -77,6 +82,7 @@ struct knng_server {
     knng_metric metric = KNNG_L2;
     knng_opts opts{};
     bool bf16 = false, manual = false, batching = false;
+    bool host_rounds = false;  // rounds driven by the host instead of the slot graphs
     int64_t capacity = 0, max_request = 0;
     void *mem = nullptr;
     Layout store{};           // x, norm, xb, sq, eb for all rows; gin = base lists
@@ -97,6 +103,8 @@ struct knng_server {
     int64_t m_base = 0;     // rows of the base the requests merge with
     int64_t reserved = 0;   // rows taken by accepted submissions
     int64_t committed = 0;  // request rows folded into the resident graph since the rebase
+    int64_t dropped = 0;    // rows of failed requests since the rebase (empty lists)
+    std::set<uint64_t> fail_ids;  // test hook: request ids made to fail before their commit
     int64_t running = 0;
     uint64_t next_ticket = 1;
     std::deque<uint64_t> pending;
@@ -168,6 +176,7 @@ void carve_slot(Carve &c, const knng_server &s, Slot &sl)
     w.rfill = c.take<int32_t>((size_t)n * 2);
     w.alist = c.take<int32_t>(n);  // active rows of a round: a request touches few rows
     sl.out = c.take<uint64_t>((size_t)n * s.gstride);
+    sl.dev = c.take<DevRound>(1);
 }
 
 size_t store_bytes(knng_server &s)
@@ -214,6 +223,12 @@ knng_status run_request(knng_server *s, Slot &sl, const std::vector<uint64_t> &t
     memset(&st, 0, sizeof st);
     Prof prof{(o.flags & KNNG_FLAG_PROFILE) != 0, sl.st};
     std::vector<uint64_t> keys((size_t)nr * s->gstride);
+    bool inject = false, committing = false;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (uint64_t t : tickets)
+            inject |= s->fail_ids.erase(s->reqs[t].req_id) > 0;
+    }
     const knng_status rc = [&]() -> knng_status {
         Rows R;
         R.x = sl.w.x;
@@ -230,6 +245,11 @@ knng_status run_request(knng_server *s, Slot &sl, const std::vector<uint64_t> &t
         HIP_TRY(launch_zero_counters(sl.w.ctr, C_WORDS, sl.st));
         Layout w = sl.w;
         w.rev_m = m;  // rows 0 .. m-1 start from their base lists unless selected
+        if (!s->host_rounds) {
+            sl.graph.rows_cap = s->capacity;
+            w.dev = sl.dev;
+            w.graph = &sl.graph;
+        }
         if (!sl.fresh)
             HIP_TRY(launch_restore(sl.w.L, sl.w.worst, sl.w.dtag, sl.w.gin, s->gstride, s->k, m,
                                    sl.prev_tag0, sl.st));
@@ -241,6 +261,9 @@ knng_status run_request(knng_server *s, Slot &sl, const std::vector<uint64_t> &t
                                   true);
         if (r != KNNG_OK)
             return r;
+        if (inject)
+            return fail(KNNG_EDEVICE, "request failed on purpose (knng_server_fail_request)");
+        committing = true;
         CommitArgs ca;
         ca.out = sl.out;
         ca.gs = s->gstride;
@@ -299,10 +322,27 @@ knng_status run_request(knng_server *s, Slot &sl, const std::vector<uint64_t> &t
         }
         if (rc == KNNG_OK) {
             s->committed += nr;
-        } else {
+        } else if (committing) {
             // the resident graph may hold part of this commit: stop serving
             s->failed = true;
             s->fail_text = err;
+        } else {
+            // failed before its commit: the resident graph and the base are
+            // untouched; the request's rows keep their ids with empty lists
+            s->dropped += nr;
+        }
+    }
+    if (rc != KNNG_OK && !committing) {
+        sl.fresh = true;  // the slot's kept state is unknown: initialise it in full
+        const knng_status fr = [&]() -> knng_status {
+            HIP_TRY(launch_fill_empty(s->res + first * s->k, nr, s->k, sl.st));
+            HIP_TRY(hipStreamSynchronize(sl.st));
+            return KNNG_OK;
+        }();
+        if (fr != KNNG_OK) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->failed = true;
+            s->fail_text = g_err;
         }
     }
     s->cv_done.notify_all();
@@ -361,6 +401,9 @@ knng_status run_request_guarded(knng_server *s, Slot &sl, const std::vector<uint
             it->second.info.done_us = t_done;
         }
         sl.fresh = true;  // the slot state is unknown: initialise it in full next time
+        // whether its commit ran is unknown: stop serving
+        s->failed = true;
+        s->fail_text = "host memory exhausted while merging a request";
         return fail(KNNG_ENOMEM, "host memory exhausted while merging a request");
     }
 }
@@ -472,6 +515,7 @@ static knng_status knng_server_create_impl(const knng_set *base, const knng_grap
     s->max_request = cfg->max_request;
     s->manual = cfg->slots == 0;
     s->batching = cfg->batching != 0;
+    s->host_rounds = cfg->host_rounds != 0;
     const size_t gbytes = store_bytes(*s), sbytes = slot_bytes(*s);
     int nslots = s->manual ? 1 : cfg->slots;
     if (cfg->hbm_budget) {
@@ -614,6 +658,7 @@ static knng_status knng_server_submit_impl(knng_server *s, const float *raw, int
         r.first = row;
         r.n = n_raw;
         r.seed = sm64_host(s->opts.seed ^ sm64_host(req_id));
+        r.req_id = req_id;
         r.info.first_id = row;
         r.info.rows = n_raw;
         r.info.submit_us = t_submit;
@@ -656,13 +701,15 @@ static knng_status knng_server_step_impl(knng_server *s, int32_t *ran)
         *ran = got ? 1 : 0;
     if (!got)
         return ok();
-    knng_status rc;
     {
         std::shared_lock<std::shared_mutex> state(s->state_mu);
-        rc = run_request_guarded(s, s->slots[0], t);
+        (void)run_request_guarded(s, s->slots[0], t);
     }
     finish_request(s);
-    return rc == KNNG_OK ? ok() : rc;
+    // the request's own result goes to knng_server_wait; step fails only
+    // when the server itself has failed
+    std::lock_guard<std::mutex> lk(s->mu);
+    return s->failed ? fail(KNNG_EDEVICE, "server failed: %s", s->fail_text.c_str()) : ok();
 }
 
 knng_status knng_server_step(knng_server *s, int32_t *ran)
@@ -750,7 +797,7 @@ static knng_status knng_server_snapshot_impl(knng_server *s, knng_graph *out, in
     int64_t n;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (s->m_base + s->committed != s->reserved)
+        if (s->m_base + s->committed + s->dropped != s->reserved)
             return fail(KNNG_EBUSY, "requests were submitted during the snapshot");
         n = s->reserved;
     }
@@ -790,7 +837,7 @@ static knng_status knng_server_rebase_impl(knng_server *s)
     int64_t n;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (s->m_base + s->committed != s->reserved)
+        if (s->m_base + s->committed + s->dropped != s->reserved)
             return fail(KNNG_EBUSY, "requests were submitted during the rebase");
         n = s->reserved;
     }
@@ -806,6 +853,7 @@ static knng_status knng_server_rebase_impl(knng_server *s)
         std::lock_guard<std::mutex> lk(s->mu);
         s->m_base = n;
         s->committed = 0;
+        s->dropped = 0;
     }
     return ok();
 }
@@ -832,11 +880,24 @@ knng_status knng_server_status(knng_server *s, int64_t *base_rows, int64_t *comm
     if (committed_rows)
         *committed_rows = s->committed;
     if (pending_rows)
-        *pending_rows = s->reserved - s->m_base - s->committed;
+        *pending_rows = s->reserved - s->m_base - s->committed - s->dropped;
     return s->failed ? fail(KNNG_EDEVICE, "server failed: %s", s->fail_text.c_str()) : ok();
 }
 
 int32_t knng_server_slots(const knng_server *s) { return s ? (int32_t)s->slots.size() : 0; }
+
+knng_status knng_server_fail_request(knng_server *s, uint64_t req_id)
+{
+    if (!s)
+        return fail(KNNG_EINVAL, "server is NULL");
+    try {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->fail_ids.insert(req_id);
+    } catch (...) {
+        return fail(KNNG_ENOMEM, "host memory exhausted");
+    }
+    return ok();
+}
 
 void knng_server_destroy(knng_server *s)
 {
@@ -852,6 +913,10 @@ void knng_server_destroy(knng_server *s)
             sl.th.join();  // a request in a slot finishes first
     for (Slot &sl : s->slots) {
         (void)hipStreamSynchronize(sl.st);
+        if (sl.graph.exec)
+            (void)hipGraphExecDestroy(sl.graph.exec);
+        if (sl.graph.graph)
+            (void)hipGraphDestroy(sl.graph.graph);
         (void)hipStreamDestroy(sl.st);
     }
     (void)hipStreamSynchronize(s->sub_st);

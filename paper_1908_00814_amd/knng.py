@@ -33,7 +33,8 @@ ENTRY_POINTS = ["knng_opts_default", "knng_merge", "knng_merge_workspace_size", 
                 "knng_server_status", "knng_server_slots", "knng_server_destroy",
                 "knng_merge_noalloc", "knng_merge_noalloc_scratch_bytes",
                 "knng_hierarchy_shape", "knng_hmerge_hierarchy", "knng_diversify",
-                "knng_diversify_workspace_size", "knng_search", "knng_search_workspace_size"]
+                "knng_diversify_workspace_size", "knng_search", "knng_search_workspace_size",
+                "knng_server_fail_request"]
 
 
 class Opts(ctypes.Structure):
@@ -80,7 +81,7 @@ class Stats(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("max_request", ctypes.c_int64),
                 ("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_int32),
-                ("batching", ctypes.c_int32)]
+                ("batching", ctypes.c_int32), ("host_rounds", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -178,6 +179,8 @@ def load():
     lib.knng_server_status.restype = ctypes.c_int
     lib.knng_server_status.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64),
                                        ctypes.POINTER(I64)]
+    lib.knng_server_fail_request.restype = ctypes.c_int
+    lib.knng_server_fail_request.argtypes = [P, ctypes.c_uint64]
     lib.knng_server_destroy.restype = None
     lib.knng_server_destroy.argtypes = [P]
     lib.knng_last_error.restype = ctypes.c_char_p
@@ -482,7 +485,7 @@ class Server:
     slots = 0 runs requests only inside step()."""
 
     def __init__(self, base, G, k, metric="l2", capacity=None, max_request=None, hbm_budget=0,
-                 slots=4, batching=False, **kw):
+                 slots=4, batching=False, host_rounds=False, **kw):
         lib = load()
         o = opts(**kw)
         # the server reads base and G on its own streams (header: stream
@@ -490,7 +493,8 @@ class Server:
         torch.cuda.current_stream(base.device).synchronize()
         cfg = ServerConfig(int(capacity if capacity is not None else 2 * base.shape[0]),
                            int(max_request if max_request is not None else base.shape[0]),
-                           int(hbm_budget), int(slots), int(bool(batching)))
+                           int(hbm_budget), int(slots), int(bool(batching)),
+                           int(bool(host_rounds)))
         h = ctypes.c_void_p()
         _check(lib.knng_server_create(ctypes.byref(_set(base)), ctypes.byref(_graph(*G)), k,
                                       _metric(metric), ctypes.byref(o), ctypes.byref(cfg),
@@ -539,6 +543,10 @@ class Server:
         g = _graph(ids, dist)
         _check(load().knng_server_snapshot(self._h, ctypes.byref(g), ctypes.byref(n)))
         return ids[:n.value], dist[:n.value]
+
+    def fail_request(self, req_id):
+        """Test hook: request req_id fails before its commit."""
+        _check(load().knng_server_fail_request(self._h, int(req_id) & (2 ** 64 - 1)))
 
     def rebase(self):
         _check(load().knng_server_rebase(self._h))

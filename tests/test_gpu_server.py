@@ -285,3 +285,97 @@ def test_many_requests_on_one_slot_each_equal_the_oracle(hip, precision):
         assert_same_graph(host(si), host(sd), ei, ed, "resident graph after 25 requests")
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("slots", [0, 2])
+def test_a_failed_request_fails_alone(hip, slots):
+    # a request made to fail before its commit (the test hook forces, from the
+    # host, the path of a merge that reported an error) fails alone: the
+    # other requests equal the oracle, the resident graph is the base with
+    # only their entries folded in, the failed rows keep their ids with empty
+    # lists, and the server goes on serving
+    from paper_1908_00814_amd.knng import KnngError
+    k, s, seed = 8, 6, 13
+    sizes = [20, 15, 25, 6]
+    base, reqs = _sets(800, sizes, 7, 126)
+    m = base.shape[0]
+    G = oracle.exact_graph(base, k)
+    srv = _server(hip, base, G, k, "l2", capacity=m + sum(sizes), max_request=32, slots=slots,
+                  sample=s, seed=seed)
+    rids = [301, 302, 303, 304]
+    try:
+        srv.fail_request(302)
+        tickets = [srv.submit(r, rid) for r, rid in zip(reqs[:3], rids[:3])]
+        if slots == 0:
+            while srv.step():
+                pass
+        results, first = [], m
+        for t, r, rid in zip(tickets, reqs[:3], rids[:3]):
+            if rid == 302:
+                with pytest.raises(KnngError, match="EDEVICE"):
+                    srv.wait(t, len(r))
+                failed = (first, len(r))
+            else:
+                ids, dist, info = srv.wait(t, len(r))
+                assert info["first_id"] == first
+                oi, od, ost = _alone(base, G, r, k, "l2", first, s, seed, rid)
+                assert_same_graph(ids.numpy(), dist.numpy(), oi[m:], od[m:], f"request {rid}")
+                results.append((oi, od, ost, first, len(r)))
+            first += len(r)
+        # served after the failure
+        t4 = srv.submit(reqs[3], 304)
+        if slots == 0:
+            assert srv.step()
+        ids, dist, info = srv.wait(t4, len(reqs[3]))
+        oi, od, ost = _alone(base, G, reqs[3], k, "l2", first, s, seed, 304)
+        assert_same_graph(ids.numpy(), dist.numpy(), oi[m:], od[m:], "request after the failure")
+        results.append((oi, od, ost, first, len(reqs[3])))
+        st = srv.status()
+        assert st["committed"] == sum(sizes) - sizes[1] and st["pending"] == 0
+        si, sd = (host(a) for a in srv.snapshot())
+        ei, ed = _fold(G, results, m, k)
+        # expected: base rows, then request rows in id order with the failed
+        # request's rows empty
+        rows_i, rows_d = list(ei[:m]), list(ed[:m])
+        done = {r[3]: r for r in results}
+        cur = m
+        for n_ in sizes:
+            if cur == failed[0]:
+                rows_i += [[-1] * k] * n_
+                rows_d += [[np.inf] * k] * n_
+            else:
+                oi_, od_ = done[cur][0], done[cur][1]
+                rows_i += list(oi_[m:m + n_])
+                rows_d += list(od_[m:m + n_])
+            cur += n_
+        assert_same_graph(si, sd, np.array(rows_i, np.int32), np.array(rows_d, np.float32),
+                          "resident graph around a failed request")
+    finally:
+        srv.close()
+
+
+def test_graph_rounds_equal_host_rounds(hip):
+    # the same requests through the slot's captured round graph and through
+    # the host-driven loop: identical results and round counts
+    k, s, seed = 10, 6, 23
+    sizes = [1, 3, 40, 77, 9]
+    base, reqs = _sets(1300, sizes, 12, 127)
+    G = oracle.exact_graph(base, k)
+    out = {}
+    for host_rounds in (False, True):
+        srv = _server(hip, base, G, k, "l2", capacity=1300 + sum(sizes), max_request=80,
+                      slots=0, sample=s, seed=seed, precision="bf16", host_rounds=host_rounds)
+        try:
+            got = []
+            for i, r in enumerate(reqs):
+                t = srv.submit(dev(r), 900 + i)
+                assert srv.step()
+                ids, dist, info = srv.wait(t, len(r))
+                got.append((ids.numpy(), dist.numpy(), info["rounds"], info["evals"]))
+            out[host_rounds] = (got, [host(a) for a in srv.snapshot()])
+        finally:
+            srv.close()
+    for (gi, gd, gr, ge), (hi, hd, hr, he) in zip(out[False][0], out[True][0]):
+        assert_same_graph(gi, gd, hi, hd, "graph vs host rounds")
+        assert gr == hr and ge == he
+    assert_same_graph(*out[False][1], *out[True][1], "resident graph")
