@@ -195,6 +195,7 @@ def serve_bench(args, dev, precision):
     torch.cuda.synchronize()
     log(f"[serve] exact k={k} base graph in {time.perf_counter() - t:.1f}s")
     budget = args.serve_budget_gib << 30
+    service = service_times(args, dB, (gi, gd), dR, offs, sizes, k, nb, precision)
     modes = {}
     for mode, slots, batching in (("independent", args.serve_slots, False),
                                   ("batched", args.serve_batched_slots, True)):
@@ -203,6 +204,48 @@ def serve_bench(args, dev, precision):
     del gi, gd
     out = dict(modes["independent"])
     out["batched"] = modes["batched"]
+    out["service_time_unloaded"] = service
+    return out
+
+
+def service_times(args, dB, G, dR, offs, sizes, k, nb, precision):
+    """Service time of single requests with nothing else running (one slot,
+    requests one after another), by request size, with the rounds run as the
+    slot's captured launch graph and as host round trips."""
+    import torch
+    from paper_1908_00814_amd import knng
+    want = [1, 10, 100, 1000, 10000]
+    # requests of the stream closest in size to each target, 8 of each
+    pick = {w: [int(i) for i in np.argsort(np.abs(sizes - w), kind="stable")[:8]] for w in want}
+    out = {}
+    for host_rounds in (False, True):
+        mode = "host_rounds" if host_rounds else "graph_rounds"
+        srv = knng.Server(dB, G, k, "l2", capacity=nb + int(offs[-1]), max_request=20_000,
+                          slots=0, sample=args.sample, delta=args.delta, seed=args.seed + 5,
+                          precision=precision, host_rounds=host_rounds)
+        try:
+            for i in pick[100][:3]:                       # warm-up (graph capture)
+                t = srv.submit(dR[offs[i]:offs[i + 1]], 10_000 + i)
+                srv.step()
+                srv.wait(t, int(sizes[i]))
+            res = {}
+            for w in want:
+                ms, rounds = [], []
+                for i in pick[w]:
+                    t = srv.submit(dR[offs[i]:offs[i + 1]], 20_000 + i)
+                    srv.step()
+                    info = srv.wait(t, int(sizes[i]))[2]
+                    ms.append((info["done_us"] - info["start_us"]) / 1e3)
+                    rounds.append(info["rounds"])
+                res[str(w)] = {"rows": [int(sizes[i]) for i in pick[w]],
+                               "median_ms": float(np.median(ms)), "mean_rounds":
+                               float(np.mean(rounds))}
+            out[mode] = res
+        finally:
+            srv.close()
+        torch.cuda.synchronize()
+        log(f"[serve] unloaded service time, {mode}: " + ", ".join(
+            f"{w} rows {res[str(w)]['median_ms']:.2f} ms" for w in want))
     return out
 
 
