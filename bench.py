@@ -196,6 +196,7 @@ def serve_bench(args, dev, precision):
     log(f"[serve] exact k={k} base graph in {time.perf_counter() - t:.1f}s")
     budget = args.serve_budget_gib << 30
     service = service_times(args, dB, (gi, gd), dR, offs, sizes, k, nb, precision)
+    jsweep = jmerge_sweep(args, dB, (gi, gd), base, req, k, precision, dev)
     modes = {}
     for mode, slots, batching in (("independent", args.serve_slots, False),
                                   ("batched", args.serve_batched_slots, True)):
@@ -205,6 +206,49 @@ def serve_bench(args, dev, precision):
     out = dict(modes["independent"])
     out["batched"] = modes["batched"]
     out["service_time_unloaded"] = service
+    out["jmerge_recall_sweep"] = jsweep
+    return out
+
+
+def jmerge_sweep(args, dB, G, base, req, k, precision, dev):
+    """recall@10 of the inserted rows of one balanced-append J-Merge (a server
+    request) of raw batches of 2,000 and 20,000 rows of the same mixture into
+    the 2M-row base, against the sample size s: the base's 1,000 clusters are
+    well separated (its exact graph has no edge between clusters), so a raw
+    row meets its cluster only through random Initialize/Append samples."""
+    import torch
+    from paper_1908_00814_amd import knng
+    Xb = torch.from_numpy(base).to(device=dev, dtype=torch.float64)
+    sqb = (Xb * Xb).sum(1)
+    out = []
+    for nr in (2000, 20000):
+        raw = req[:nr]
+        dRaw = torch.from_numpy(raw).to(dev)
+        Xr = torch.from_numpy(raw).to(device=dev, dtype=torch.float64)
+        rows = np.arange(0, nr, max(1, nr // 200))
+        q = Xr[torch.from_numpy(rows).to(dev)]
+        D = torch.cat([(q * q).sum(1)[:, None] + sqb[None, :] - 2.0 * (q @ Xb.T),
+                       (q * q).sum(1)[:, None] + (Xr * Xr).sum(1)[None, :] - 2.0 * (q @ Xr.T)], 1)
+        D[torch.arange(len(rows), device=dev), torch.from_numpy(rows + len(base)).to(dev)] = \
+            float("inf")
+        kth = torch.topk(D, 10, dim=1, largest=False)[0][:, 9]
+        for s_ in (10, 20, 32):
+            kw = dict(sample=s_, delta=args.delta, seed=args.seed + 11, precision=precision,
+                      balanced=True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ids, _, st = knng.expand(dB, G, dRaw, k, "l2", **kw)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t
+            got = ids[torch.from_numpy(rows + len(base)).to(dev), :10].long()
+            dv = torch.gather(D, 1, got.clamp(min=0))
+            rec = float(((dv <= kth[:, None]) & (got >= 0)).float().mean().item())
+            out.append({"raw_rows": nr, "sample": s_, "recall@10_inserted": rec,
+                        "ms": secs * 1e3, "rounds": st["rounds"]})
+            log(f"[serve] J-Merge of {nr:,} raw rows into the base, s={s_}: recall@10 of "
+                f"inserted rows {rec:.4f}, {secs * 1e3:.1f} ms, {st['rounds']} rounds")
+        del D, Xr, q
+    del Xb
     return out
 
 
@@ -400,8 +444,22 @@ def tree_bench(args, dev):
     rows = synth.rng(4007).choice(len(X), 1000, replace=False)
     ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
     rec = recall_at10(ids, X, rows, dev, metric="l1")
+    sweep = []
+    for s_ in (5, 10, 20, 32):
+        for dl in (0.0, 0.001):
+            kw_ = dict(sample=s_, delta=dl, seed=args.seed + 4)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ids_s, _, st_s = knng.merge_tree(dX, starts, graphs, k, "l1", **kw_)
+            torch.cuda.synchronize()
+            secs_s = time.perf_counter() - t
+            rec_s = recall_at10(ids_s.cpu().numpy(), X, rows, dev, metric="l1")
+            sweep.append({"sample": s_, "delta": dl, "recall@10": rec_s, "ms": secs_s * 1e3,
+                          "points_per_s": len(X) / secs_s})
+            log(f"[tree] sweep s={s_} delta={dl}: recall@10 {rec_s:.4f}, {secs_s * 1e3:.0f} ms")
     out = {"workload": "merge tree: 8 x 125,000 x d100 Gaussian mixture (50 components), "
                        "exact k=16 l1 block graphs, pairwise S-Merge in 3 levels",
+           "sweep": sweep,
            "points_per_s": len(X) / secs, "seconds": secs, "level_ms": st["level_ms"],
            "level_rounds": st["level_rounds"], "recall@10": rec,
            "block_graphs_s": t_blocks,
@@ -456,15 +514,39 @@ def cosine_bench(args, dev):
     out["fp64_error"] = fp64_error(X, ids, dist, rows, "cos")
     Xd = torch.from_numpy(X).to(device=dev, dtype=torch.float64)
     nrm = Xd.norm(dim=1)
-    hits = 0
+    Drows = []
     for lo in range(0, len(rows), 100):
         r = torch.from_numpy(rows[lo:lo + 100]).to(dev)
         D = 1.0 - (Xd[r] @ Xd.T) / (nrm[r, None] * nrm[None, :])
         D[torch.arange(len(r), device=dev), r] = float("inf")
-        kth = torch.topk(D, 10, dim=1, largest=False)[0][:, 9]
-        got = torch.from_numpy(ids[rows[lo:lo + 100], :10].astype(np.int64)).to(dev)
-        hits += (torch.gather(D, 1, got) <= kth[:, None] * (1 + 1e-12)).sum().item()
-    out["recall@10"] = hits / (len(rows) * 10)
+        Drows.append(D)
+    del Xd
+    kth = [torch.topk(D, 10, dim=1, largest=False)[0][:, 9] for D in Drows]
+
+    def recall(ids_):
+        hits = 0
+        for b_, (D, kt) in enumerate(zip(Drows, kth)):
+            got = torch.from_numpy(ids_[rows[b_ * 100:(b_ + 1) * 100], :10].astype(np.int64)).to(dev)
+            hits += (torch.gather(D, 1, got) <= kt[:, None] * (1 + 1e-12)).sum().item()
+        return hits / (len(rows) * 10)
+
+    out["recall@10"] = recall(ids)
+    # recall against the sample size s and the stopping threshold delta (BF16)
+    out["sweep"] = []
+    for s_ in (5, 10, 20, 32):
+        for dl in (0.0, 0.001):
+            kw = dict(sample=s_, delta=dl, seed=args.seed + 3, precision="bf16")
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ids_s, _, st = knng.merge(dS1, g1, dS2, g2, k, "cos", **kw)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t
+            rec = recall(ids_s.cpu().numpy())
+            out["sweep"].append({"sample": s_, "delta": dl, "recall@10": rec, "ms": secs * 1e3,
+                                 "points_per_s": n / secs, "rounds": st["rounds"]})
+            log(f"[cosine] sweep s={s_} delta={dl}: recall@10 {rec:.4f}, {secs * 1e3:.0f} ms, "
+                f"{st['rounds']} rounds")
+    del Drows
     log(f"[cosine] identical paths {out['paths_identical']}, recall@10 {out['recall@10']:.4f}, "
         f"FP64 max rel err {out['fp64_error']['max_rel']:.2e}")
     return out
