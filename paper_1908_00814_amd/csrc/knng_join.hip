@@ -76,7 +76,6 @@ struct WaveLds {
     float *gsq;      // GS squared norms of bf16 rows (BF16 path)
     float *gerr;     // GS bf16 rounding-error norms (BF16 path)
     int32_t *tnew;   // 2 s NEW members, first set then second
-    int32_t *told;   // k + s raw OLD candidates
     int32_t *toldA;  // k + s accepted OLD members of the first set
     int32_t *toldB;  // k + s accepted OLD members of the second set
     int32_t *qdst;   // FP32 path: target rows of the QF queued keys
@@ -98,8 +97,8 @@ __host__ __device__ inline int stage_bytes(int GS, bool bf)
 __host__ __device__ inline int wave_lds_bytes(int GS, int s, int k, bool bf)
 {
     const int st = stage_bytes(GS, bf);
-    int b = bf ? st + GS * 8 + QCAP * 8 + 4 * GS * 4 + (2 * s + 3 * (k + s) + QF) * 4
-               : st + GS * 8 + QF * 8 + 2 * GS * 4 + (2 * s + 3 * (k + s) + QF) * 4;
+    int b = bf ? st + GS * 8 + QCAP * 8 + 4 * GS * 4 + (2 * s + 2 * (k + s) + QF) * 4
+               : st + GS * 8 + QF * 8 + 2 * GS * 4 + (2 * s + 2 * (k + s) + QF) * 4;
     return (b + 15) / 16 * 16;
 }
 
@@ -114,42 +113,86 @@ __device__ inline WaveLds carve_lds(unsigned char *base, int GS, int s, int k, b
     L.gsq = bf ? L.gnorm + GS : nullptr;
     L.gerr = bf ? L.gsq + GS : nullptr;
     L.tnew = reinterpret_cast<int32_t *>(bf ? L.gerr + GS : L.gnorm + GS);
-    L.told = L.tnew + 2 * s;
-    L.toldA = L.told + (k + s);
+    L.toldA = L.tnew + 2 * s;
     L.toldB = L.toldA + (k + s);
     L.qdst = L.toldB + (k + s);
     return L;
 }
 
+// The id set of build_group: ID_SET slots (a power of two), linear probing.
+constexpr int ID_SET = 256;
+constexpr uint32_t ID_FREE = 0xFFFFFFFFu;
+
+// claims id in the set; true when this lane's claim put it there (of lanes
+// claiming one id together, exactly one succeeds)
+__device__ __forceinline__ bool claim_id(uint32_t *tab, int32_t id)
+{
+    uint32_t h = ((uint32_t)id * 2654435761u) >> 24;
+    for (int probe = 0; probe < ID_SET; probe++) {
+        const uint32_t old = atomicCAS(tab + h, ID_FREE, (uint32_t)id);
+        if (old == ID_FREE)
+            return true;
+        if (old == (uint32_t)id)
+            return false;
+        h = (h + 1) & (ID_SET - 1);
+    }
+    return false;
+}
+
 // Forms u's neighbourhood in LDS (regions, ids, worst bounds, norms).
-// Returns false when u has no NEW member (no pair to join).
+// Returns false when u has no NEW member (no pair to join).  Two memory round
+// trips: the counts, both samples and both reverse reservoirs together
+// (entries past a count are read and ignored), then the members' bounds and
+// norms.  Repeats are found through a small open-addressing set of ids in LDS
+// (the BF16 path's queue words or the FP32 path's staging area, both free
+// while a neighbourhood is formed): the NEW candidates claim their ids first,
+// then the OLD ones; a candidate is kept when its claim succeeds.
 template <int METRIC, bool BF>
 __device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a, const WaveLds &L,
                                    Regions &g)
 {
+    static_assert(2 * MAX_S <= WAVE && MAX_K + MAX_S <= 2 * WAVE, "candidate lanes");
     const int lane = lane_id();
     const int s = a.s, k = a.k;
+    const int nco = k + s;
     const uint64_t below = (1ull << lane) - 1ull;
-    // NEW candidates: forward NEW sample (lanes < s), reverse NEW (s..2s)
     const int cnt_new = a.cnt_f[2 * u], cnt_old = a.cnt_f[2 * u + 1];
+    uint32_t *tab = BF ? reinterpret_cast<uint32_t *>(L.q64) : reinterpret_cast<uint32_t *>(L.vecT);
+    for (int i = lane; i < ID_SET; i += WAVE)
+        tab[i] = ID_FREE;
+    // NEW candidates: forward NEW sample (lanes < s), reverse NEW (s..2s);
+    // OLD candidates: forward OLD (c < k), reverse OLD (k <= c < k+s), c =
+    // lane + 64 * pass
+    int32_t nf = -1;
+    uint64_t nr = ~0ull;
+    if (lane < s)
+        nf = a.new_f[u * s + lane];
+    else if (lane < 2 * s)
+        nr = a.rnew[u * s + (lane - s)];
+    int32_t of[2] = {-1, -1};
+    uint64_t orv[2] = {~0ull, ~0ull};
+#pragma unroll
+    for (int p = 0; p < 2; p++) {
+        const int c = p * WAVE + lane;
+        if (c < k)
+            of[p] = a.old_f[u * k + c];
+        else if (c < nco)
+            orv[p] = a.rold[u * s + (c - k)];
+    }
     int32_t cid = -1;
     if (lane < s) {
         if (lane < cnt_new)
-            cid = a.new_f[u * s + lane];
+            cid = nf;
     } else if (lane < 2 * s) {
-        uint64_t wv = a.rnew[u * s + (lane - s)];
-        if (!res_empty(wv))
-            cid = (int32_t)(uint32_t)wv;
+        if (!res_empty(nr))
+            cid = (int32_t)(uint32_t)nr;
     }
     if (cid >= a.n) {
         raise_err(a.ctr + C_ERR, ERR_ROW_GROUP);
         cid = -1;
     }
-    bool keep = cid >= 0;
-    for (int j = 0; j < 2 * s; j++) {
-        int32_t o = __shfl(cid, j, WAVE);
-        keep = keep && !(j < lane && o == cid);
-    }
+    // a NEW member is kept once
+    const bool keep = cid >= 0 && claim_id(tab, cid);
     const bool isA = cid < a.n1;
     const uint64_t mA = __ballot(keep && isA), mB = __ballot(keep && !isA);
     const int nA = __popcll(mA), nB = __popcll(mB);
@@ -157,46 +200,45 @@ __device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a,
         return false;
     if (keep)
         L.tnew[isA ? __popcll(mA & below) : nA + __popcll(mB & below)] = cid;
-    __builtin_amdgcn_wave_barrier();
-    // OLD candidates: forward OLD (c < k), reverse OLD (k <= c < k+s), minus
-    // NEW members and repeats
-    const int nco = k + s;
-    int oA = 0, oB = 0;
-    for (int pass = 0; pass * WAVE < nco; pass++) {
-        const int c = pass * WAVE + lane;
-        int32_t oc = -1;
+    // an OLD candidate is kept unless it is a NEW member or repeats an earlier
+    // candidate
+    int32_t oc[2];
+    bool ok[2];
+#pragma unroll
+    for (int p = 0; p < 2; p++) {
+        const int c = p * WAVE + lane;
+        oc[p] = -1;
         if (c < k) {
             if (c < cnt_old)
-                oc = a.old_f[u * k + c];
+                oc[p] = of[p];
         } else if (c < nco) {
-            uint64_t wv = a.rold[u * s + (c - k)];
-            if (!res_empty(wv))
-                oc = (int32_t)(uint32_t)wv;
+            if (!res_empty(orv[p]))
+                oc[p] = (int32_t)(uint32_t)orv[p];
         }
-        if (oc >= a.n) {
+        if (oc[p] >= a.n) {
             raise_err(a.ctr + C_ERR, ERR_ROW_GROUP);
-            oc = -1;
+            oc[p] = -1;
         }
-        if (c < nco)
-            L.told[c] = oc;
-        __builtin_amdgcn_wave_barrier();
-        bool ok = oc >= 0;
-        for (int j = 0; j < nA + nB && ok; j++)
-            ok = L.tnew[j] != oc;
-        for (int j = 0; j < c && ok; j++)
-            ok = L.told[j] != oc;
-        const bool oa = oc < a.n1;
-        const uint64_t moA = __ballot(ok && oa), moB = __ballot(ok && !oa);
-        if (ok) {
+        ok[p] = oc[p] >= 0;
+    }
+#pragma unroll
+    for (int p = 0; p < 2; p++)
+        ok[p] = ok[p] && claim_id(tab, oc[p]);
+    int oA = 0, oB = 0;
+#pragma unroll
+    for (int p = 0; p < 2; p++) {
+        const bool oa = oc[p] < a.n1;
+        const uint64_t moA = __ballot(ok[p] && oa), moB = __ballot(ok[p] && !oa);
+        if (ok[p]) {
             if (oa)
-                L.toldA[oA + __popcll(moA & below)] = oc;
+                L.toldA[oA + __popcll(moA & below)] = oc[p];
             else
-                L.toldB[oB + __popcll(moB & below)] = oc;
+                L.toldB[oB + __popcll(moB & below)] = oc[p];
         }
         oA += __popcll(moA);
         oB += __popcll(moB);
-        __builtin_amdgcn_wave_barrier();
     }
+    __builtin_amdgcn_wave_barrier();
     g.nA = nA;
     g.oA = oA;
     g.nB = nB;
@@ -205,23 +247,45 @@ __device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a,
     g.offNB = g.offOA + r4(oA);
     g.offOB = g.offNB + r4(nB);
     g.GP = g.offOB + r4(oB);
-    for (int slot = lane; slot < g.GP; slot += WAVE) {
-        int32_t id = -1;
+    // slots lane + 64 i: ids, then every bound and norm in one round trip
+    constexpr int NSL = 3;
+    int32_t id[NSL];
+    uint64_t gw[NSL];
+    float gn[NSL], gq[NSL], ge[NSL];
+#pragma unroll
+    for (int i = 0; i < NSL; i++) {
+        const int slot = lane + i * WAVE;
+        int32_t v = -1;
         if (slot < nA)
-            id = L.tnew[slot];
+            v = L.tnew[slot];
         else if (slot >= g.offOA && slot < g.offOA + oA)
-            id = L.toldA[slot - g.offOA];
+            v = L.toldA[slot - g.offOA];
         else if (slot >= g.offNB && slot < g.offNB + nB)
-            id = L.tnew[nA + (slot - g.offNB)];
+            v = L.tnew[nA + (slot - g.offNB)];
         else if (slot >= g.offOB && slot < g.offOB + oB)
-            id = L.toldB[slot - g.offOB];
-        L.grp[slot] = id;
-        L.gw[slot] = id >= 0 ? a.worst[id] : 0ull;
-        if (METRIC == M_COS)
-            L.gnorm[slot] = id >= 0 ? R.norm[R.phys(id)] : 1.0f;
-        if (BF) {
-            L.gsq[slot] = id >= 0 ? R.sq[R.phys(id)] : 0.0f;
-            L.gerr[slot] = id >= 0 ? R.eb[R.phys(id)] : 0.0f;
+            v = L.toldB[slot - g.offOB];
+        id[i] = slot < g.GP ? v : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < NSL; i++) {
+        const bool has = id[i] >= 0;
+        gw[i] = has ? a.worst[id[i]] : 0ull;
+        gn[i] = METRIC == M_COS && has ? R.norm[R.phys(id[i])] : 1.0f;
+        gq[i] = BF && has ? R.sq[R.phys(id[i])] : 0.0f;
+        ge[i] = BF && has ? R.eb[R.phys(id[i])] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < NSL; i++) {
+        const int slot = lane + i * WAVE;
+        if (slot < g.GP) {
+            L.grp[slot] = id[i];
+            L.gw[slot] = gw[i];
+            if (METRIC == M_COS)
+                L.gnorm[slot] = gn[i];
+            if (BF) {
+                L.gsq[slot] = gq[i];
+                L.gerr[slot] = ge[i];
+            }
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -307,13 +371,15 @@ __device__ __forceinline__ void insert_into(const RoundArgs &a, int64_t dst, uin
 }
 
 // UpdateNN of several proposals for one list by one lane: one read of the
-// list, then one compare-and-swap per proposal on the maximum of the lane's
-// local view of the list; a failed swap returns the slot's current word, which
-// replaces the view's, and the proposal is tried again.  Proposal t (bit t of
-// `have`) is key(t).  Every word of the view is one its slot held at some time
-// before the swap (the lane's own swaps included), which is all the argument
-// of bounded_insert needs: each successful swap replaces the true maximum, and
-// duplicates stay out.
+// list into a local view, then one compare-and-swap per proposal on the
+// maximum of the view; a failed swap returns the slot's current word, which
+// replaces the view's, and the proposal is tried again.  Every word of the
+// view is one its slot held at some time before the swap (the lane's own
+// swaps included; a word read through the caches is an older, hence larger,
+// value of its slot), which is all the argument of bounded_insert needs: each
+// successful swap replaces the true maximum, and duplicates stay out.  The
+// view's maximum is kept between proposals, so a proposal that does not beat
+// it costs one comparison; the maximum of the final view bounds the list's.
 template <int KB, class KeyFn>
 __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t have, KeyFn key_of)
 {
@@ -326,31 +392,36 @@ __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t ha
     }
     uint64_t *slots = a.L + dst * cap;
     bool any = false;
-    uint64_t bound = ~0ull;  // an upper bound of the list's maximum after our inserts
     uint64_t v[B];
 #pragma unroll
     for (int j = 0; j < B; j++)
-        v[j] = j < cap ? ld_agent(slots + j) : 0ull;
-    for (int fails = 0; have && fails < SPIN_BUDGET;) {
-        const uint64_t key = key_of(__builtin_ctz(have));
-        const uint64_t kid = key_strip(key);
-        uint64_t mx = 0, second = 0;
-        int mj = 0;
-        bool dup = false;
+        v[j] = j < cap ? slots[j] : 0ull;
+    uint64_t mx = 0;
+    int mj = 0;
+    auto rescan = [&]() {
+        mx = 0;
+        mj = 0;
 #pragma unroll
         for (int j = 0; j < B; j++) {
-            if (j < cap) {
-                dup |= key_strip(v[j]) == kid;
-                if (v[j] > mx) {
-                    second = mx;
-                    mx = v[j];
-                    mj = j;
-                } else if (v[j] > second) {
-                    second = v[j];
-                }
+            if (j < cap && v[j] > mx) {
+                mx = v[j];
+                mj = j;
             }
         }
-        if (dup || key >= mx) {
+    };
+    rescan();
+    for (int fails = 0; have && fails < SPIN_BUDGET;) {
+        const uint64_t key = key_of(__builtin_ctz(have));
+        if (key >= mx) {
+            have &= have - 1;
+            continue;
+        }
+        const uint64_t kid = key_strip(key);
+        bool dup = false;
+#pragma unroll
+        for (int j = 0; j < B; j++)
+            dup |= j < cap && key_strip(v[j]) == kid;
+        if (dup) {
             have &= have - 1;
             continue;
         }
@@ -359,19 +430,19 @@ __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t ha
 #pragma unroll
         for (int j = 0; j < B; j++)
             v[j] = j == mj ? (ok ? key : seen) : v[j];
+        rescan();
         if (!ok) {
             fails++;
             continue;
         }
-        bound = key > second ? key_strip(key) : key_strip(second);
         any = true;
         have &= have - 1;
     }
     if (have)
         atomicOr((unsigned long long *)(a.ctr + C_ERR), (unsigned long long)ERR_SPIN);
     if (any) {
-        // the last success's bound is the tightest: lists only improve
-        atomic_min_u64(a.worst + dst, bound);
+        // every word of the view is at least its slot's current value
+        atomic_min_u64(a.worst + dst, key_strip(mx));
         a.dtag[dst] = a.tag0 + a.round + 1;
     }
 }
@@ -639,26 +710,40 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
     auto grid_at = [&](int gi) { return reinterpret_cast<unsigned char *>(L.vecT) + gi * GRID_BYTES; };
     auto offer_grids = [&](int ng) {
         __builtin_amdgcn_wave_barrier();
-        const int gi = lane >> 5;
-        if (gi < ng) {
-            const unsigned char *gb = grid_at(gi);
-            const float *gl = reinterpret_cast<const float *>(gb);
-            const uint8_t *gflag = gb + 16 * 16 * 4;
-            const int32_t *gid = reinterpret_cast<const int32_t *>(gflag + 16 * 16);
-            const bool rowside = (lane & 31) < 16;
-            const int j = lane & 15;
-            const int32_t me = gid[rowside ? j : 16 + j];
+        auto gids = [&](int gi) {
+            return reinterpret_cast<const int32_t *>(grid_at(gi) + 16 * 16 * 4 + 16 * 16);
+        };
+        const int j = lane & 15;
+        // two tiles of one row band share their row members: one lane then
+        // offers a row member both grids' proposals (lanes 0-15), and the
+        // column members of grid 0 and 1 take lanes 16-31 and 32-47
+        const bool shared = ng == 2 && __ballot(gids(0)[j] != gids(1)[j]) == 0ull;
+        int gi = lane >> 5;
+        bool rowside = (lane & 31) < 16, both = false, act = gi < ng;
+        if (shared) {
+            gi = lane < 32 ? 0 : 1;
+            rowside = lane < 16;
+            both = rowside;
+            act = lane < 48;
+        }
+        if (act) {
+            const int32_t me = gids(gi)[rowside ? j : 16 + j];
             uint32_t have = 0;
             if (me >= 0) {
-                for (int t = 0; t < 16; t++) {
-                    const int cell = rowside ? j * 16 + t : t * 16 + j;
-                    have |= (uint32_t)((gflag[cell] >> (rowside ? 0 : 1)) & 1) << t;
+                for (int g2 = 0; g2 < (both ? 2 : 1); g2++) {
+                    const uint8_t *gflag = grid_at(gi + g2) + 16 * 16 * 4;
+                    for (int t = 0; t < 16; t++) {
+                        const int cell = rowside ? j * 16 + t : t * 16 + j;
+                        have |= (uint32_t)((gflag[cell] >> (rowside ? 0 : 1)) & 1) << (16 * g2 + t);
+                    }
                 }
             }
             if (have)
                 insert_local<KB>(a, me, have, [&](int t) {
-                    const int cell = rowside ? j * 16 + t : t * 16 + j;
-                    return make_key(gl[cell], (uint32_t)gid[rowside ? 16 + t : t],
+                    const int g2 = gi + (t >> 4), tt = t & 15;
+                    const float *gl = reinterpret_cast<const float *>(grid_at(g2));
+                    const int cell = rowside ? j * 16 + tt : tt * 16 + j;
+                    return make_key(gl[cell], (uint32_t)gids(g2)[rowside ? 16 + tt : tt],
                                     F_NEW | F_FRESH);
                 });
         }
@@ -729,33 +814,38 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
                         continue;
                     done = i + 1;
                     const int reg = tl[i] >> 16;
+                    // the column member (lane % 16) is read once for the 4 rows
+                    const int c = ((tl[i] >> 8) & 0xFF) + (lane & 15);
+                    const int32_t qc = L.grp[c];
+                    const float sqc = L.gsq[c], erc = L.gerr[c];
+                    const float nbc = METRIC == M_COS ? L.gnorm[c] : 0.0f;
+                    const uint64_t gwc = L.gw[c];
 #pragma unroll
                     for (int rr = 0; rr < 4; rr++) {
                         const int r = (tl[i] & 0xFF) + kq + rr;
-                        const int c = ((tl[i] >> 8) & 0xFF) + (lane & 15);
                         bool valid = in_rect(reg, r, c, g);
-                        const int32_t p = valid ? L.grp[r] : -1, q = valid ? L.grp[c] : -1;
+                        const int32_t p = valid ? L.grp[r] : -1, q = valid ? qc : -1;
                         valid = valid && p >= 0 && q >= 0;
                         n_pairs += valid;
                         bool vp = false, vq = false;
                         float dbf = 0.0f;
                         if (valid) {
-                            const float sp = L.gsq[r], sq = L.gsq[c];
+                            const float sp = L.gsq[r], sq = sqc;
                             dbf = __builtin_fmaf(-2.0f, acc[i][rr], sp + sq);
                             const float na = METRIC == M_COS ? L.gnorm[r] : 0.0f;
-                            const float nb = METRIC == M_COS ? L.gnorm[c] : 0.0f;
-                            if (signbit(L.gerr[r]) && signbit(L.gerr[c])) {
+                            const float nb = nbc;
+                            if (signbit(L.gerr[r]) && signbit(erc)) {
                                 // certified exact pair: d~ is the canonical value
                                 const float l = METRIC == M_COS ? cos_finish(dbf, na, nb) : dbf;
                                 vp = make_key(l, (uint32_t)q, F_NEW | F_FRESH) < L.gw[r];
-                                vq = make_key(l, (uint32_t)p, F_NEW | F_FRESH) < L.gw[c];
+                                vq = make_key(l, (uint32_t)p, F_NEW | F_FRESH) < gwc;
                             } else {
                                 const float E =
-                                    (fabsf(L.gerr[r]) + fabsf(L.gerr[c])) * (1.0f + 0x1p-22f);
+                                    (fabsf(L.gerr[r]) + fabsf(erc)) * (1.0f + 0x1p-22f);
                                 const float nn = __builtin_sqrtf(sp) + __builtin_sqrtf(sq);
                                 const float N2 = nn * nn * (1.0f + 0x1p-20f);
                                 const float Wp = l2_threshold<METRIC>(L.gw[r], na, nb);
-                                const float Wq = l2_threshold<METRIC>(L.gw[c], na, nb);
+                                const float Wq = l2_threshold<METRIC>(gwc, na, nb);
                                 vp = Wp == inf || dbf <= (Wp + bf16_margin(Wp, E, N2, R.dp)) *
                                                              (1.0f + 0x1p-22f);
                                 vq = Wq == inf || dbf <= (Wq + bf16_margin(Wq, E, N2, R.dp)) *
