@@ -16,90 +16,113 @@ namespace knng {
 namespace {
 
 // Forward sample of round t over the rows holding NEW entries (dtag == t), one
-// wave per row (k <= 64 lanes).  Marks u and every sampled NEW entry as
-// active in round t; a row left with more than s NEW entries is sampled
-// again in round t+1.  The FRESH count of round t-1 is accumulated per wave.
+// group of G lanes per row (k <= G), 64 / G rows per wave.  Marks u and every
+// sampled NEW entry as active in round t; a row left with more than s NEW
+// entries is sampled again in round t+1.  The FRESH count of round t-1 is
+// accumulated per wave.
+template <int G>
 __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
 {
     // graph mode: round max_rounds only counts the last round's entries
     // (k_count_fresh), as the host-driven loop does
     if (!take_round(a) || (a.dev && a.round >= a.dev->max_rounds))
         return;
+    constexpr int RPW = WAVE / G;  // rows per wave step
     const int lane = lane_id();
+    const int grp = lane / G, gl = lane % G, base = grp * G;
+    const uint64_t gbits = G == WAVE ? ~0ull : ((1ull << G) - 1ull) << base;
+    const uint64_t below = (1ull << lane) - 1ull;
     const int32_t tr = a.tag0 + a.round;
     int fresh_total = 0;
-    FOR_TAGGED_ROWS(u, a.n, a.dtag, tr)
-    {
-        const bool act = lane < a.k;
-        uint64_t v = act ? a.L[u * a.k + lane] : ~0ull;
-        const bool empty = !act || key_empty(v);
-        const bool fresh = !empty && (v & F_FRESH);
-        const bool isnew = !empty && (v & F_NEW);
-        const bool isold = !empty && !(v & F_NEW);
-        const uint32_t id = key_id(v);
-        uint64_t pk = ~0ull;
-        if (isnew) {
-            uint64_t h = hash5(a.seed, TAG_FWD, (uint64_t)a.round, (uint64_t)u, (uint64_t)id);
-            pk = ((h >> 32) << 32) | id;
-        }
-        // rank among the NEW entries (ties, which a well-formed list never
-        // has, go by slot so that the sample slots stay a permutation)
-        int rank = 0, nnew = 0;
-        for (int j = 0; j < a.k; j++) {
-            uint64_t o = __shfl(pk, j, WAVE);
-            rank += o < pk || (o == pk && j < lane);
-            nnew += o != ~0ull;
-        }
-        const bool sampled = isnew && rank < a.s;
-        bool mark = false;  // the sampled id becomes active
-        if (sampled) {
-            a.new_f[u * a.s + rank] = (int32_t)id;
-            if (id < a.n)
-                mark = true;
-            else
-                raise_err(a.ctr + C_ERR, ERR_ROW_SAMPLE);
-        }
-        uint64_t nv = v & ~(uint64_t)F_FRESH;
-        if (sampled)
-            nv &= ~(uint64_t)F_NEW;
-        if (act && !empty && nv != v)
-            a.L[u * a.k + lane] = nv;
-        const uint64_t below = (1ull << lane) - 1ull;
-        const uint64_t om = __ballot(isold);
-        if (isold)
-            a.old_f[u * a.k + __popcll(om & below)] = (int32_t)id;
-        uint64_t wv = act ? (empty ? v : key_strip(nv)) : 0ull;
-        wv = wave_max_u64(wv);
-        fresh_total += wave_sum((int)fresh);
-        if (lane == 0) {
-            a.worst[u] = wv;
-            a.cnt_f[2 * u] = nnew < a.s ? nnew : a.s;
-            a.cnt_f[2 * u + 1] = __popcll(om);
-            if (nnew > a.s)
-                a.dtag[u] = tr + 1;
-        }
-        const bool mark_u = lane == 0 && nnew > 0;  // u itself is active
-        if (!a.alist) {
-            if (mark)
-                a.atag[id] = tr;
-            if (mark_u)
-                a.atag[u] = tr;
-        } else {
-            // the first mark of a row in this round appends it to the list
-            const bool fm = mark && atomicExch(a.atag + id, tr) != tr;
-            const bool fu = mark_u && atomicExch(a.atag + u, tr) != tr;
-            const uint64_t m1 = __ballot(fm), m2 = __ballot(fu);
-            const int cnt = __popcll(m1) + __popcll(m2);
-            if (cnt) {
-                unsigned long long base = 0;
-                if (lane == 0)
-                    base = atomicAdd((unsigned long long *)(a.ctr + C_ACTIVE),
-                                     (unsigned long long)cnt);
-                base = __shfl(base, 0, WAVE);
-                if (fm)
-                    a.alist[base + __popcll(m1 & below)] = (int32_t)id;
-                if (fu)
-                    a.alist[base + __popcll(m1)] = (int32_t)u;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const int64_t wave0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    for (int64_t b = wave0; b < a.n; b += nwaves * WAVE) {
+        const int64_t r0 = b + (int64_t)lane * nwaves;
+        uint64_t todo = __ballot(r0 < a.n && a.dtag[r0] == tr);
+        while (todo) {
+            // the next RPW tagged rows, one per group
+            int64_t u = -1;
+#pragma unroll
+            for (int q = 0; q < RPW; q++) {
+                if (todo) {
+                    if (grp == q)
+                        u = b + (int64_t)__builtin_ctzll(todo) * nwaves;
+                    todo &= todo - 1;
+                }
+            }
+            const bool act = u >= 0 && gl < a.k;
+            uint64_t v = act ? a.L[u * a.k + gl] : ~0ull;
+            const bool empty = !act || key_empty(v);
+            const bool fresh = !empty && (v & F_FRESH);
+            const bool isnew = !empty && (v & F_NEW);
+            const bool isold = !empty && !(v & F_NEW);
+            const uint32_t id = key_id(v);
+            uint64_t pk = ~0ull;
+            if (isnew) {
+                uint64_t h = hash5(a.seed, TAG_FWD, (uint64_t)a.round, (uint64_t)u, (uint64_t)id);
+                pk = ((h >> 32) << 32) | id;
+            }
+            // rank among the row's NEW entries (ties, which a well-formed list
+            // never has, go by slot so that the sample slots stay a permutation)
+            int rank = 0, nnew = 0;
+            for (int j = 0; j < a.k; j++) {
+                uint64_t o = __shfl(pk, base + j, WAVE);
+                rank += o < pk || (o == pk && j < gl);
+                nnew += o != ~0ull;
+            }
+            const bool sampled = isnew && rank < a.s;
+            bool mark = false;  // the sampled id becomes active
+            if (sampled) {
+                a.new_f[u * a.s + rank] = (int32_t)id;
+                if (id < a.n)
+                    mark = true;
+                else
+                    raise_err(a.ctr + C_ERR, ERR_ROW_SAMPLE);
+            }
+            uint64_t nv = v & ~(uint64_t)F_FRESH;
+            if (sampled)
+                nv &= ~(uint64_t)F_NEW;
+            if (act && !empty && nv != v)
+                a.L[u * a.k + gl] = nv;
+            const uint64_t om = __ballot(isold) & gbits;
+            if (isold)
+                a.old_f[u * a.k + __popcll(om & below)] = (int32_t)id;
+            uint64_t wv = act ? (empty ? v : key_strip(nv)) : 0ull;
+            for (int o = G / 2; o > 0; o >>= 1) {
+                const uint64_t w = __shfl_xor(wv, o, WAVE);
+                wv = w > wv ? w : wv;
+            }
+            fresh_total += wave_sum((int)fresh);
+            if (u >= 0 && gl == 0) {
+                a.worst[u] = wv;
+                a.cnt_f[2 * u] = nnew < a.s ? nnew : a.s;
+                a.cnt_f[2 * u + 1] = __popcll(om);
+                if (nnew > a.s)
+                    a.dtag[u] = tr + 1;
+            }
+            const bool mark_u = u >= 0 && gl == 0 && nnew > 0;  // u itself is active
+            if (!a.alist) {
+                if (mark)
+                    a.atag[id] = tr;
+                if (mark_u)
+                    a.atag[u] = tr;
+            } else {
+                // the first mark of a row in this round appends it to the list
+                const bool fm = mark && atomicExch(a.atag + id, tr) != tr;
+                const bool fu = mark_u && atomicExch(a.atag + u, tr) != tr;
+                const uint64_t m1 = __ballot(fm), m2 = __ballot(fu);
+                const int cnt = __popcll(m1) + __popcll(m2);
+                if (cnt) {
+                    unsigned long long bs = 0;
+                    if (lane == 0)
+                        bs = atomicAdd((unsigned long long *)(a.ctr + C_ACTIVE),
+                                       (unsigned long long)cnt);
+                    bs = __shfl(bs, 0, WAVE);
+                    if (fm)
+                        a.alist[bs + __popcll(m1 & below)] = (int32_t)id;
+                    if (fu)
+                        a.alist[bs + __popcll(m1) + __popcll(m2 & below)] = (int32_t)u;
+                }
             }
         }
     }
@@ -509,7 +532,12 @@ inline unsigned grid_for(int64_t items, int per_block, unsigned cap)
 
 hipError_t launch_sample(const RoundArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sample, dim3(grid_for(a.n, 4, 8192)), dim3(256), 0, st, a);
+    if (a.k <= 16)
+        hipLaunchKernelGGL(k_sample<16>, dim3(grid_for(a.n, 16, 8192)), dim3(256), 0, st, a);
+    else if (a.k <= 32)
+        hipLaunchKernelGGL(k_sample<32>, dim3(grid_for(a.n, 8, 8192)), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_sample<WAVE>, dim3(grid_for(a.n, 4, 8192)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
