@@ -86,8 +86,8 @@ struct WaveLds {
 // CU's 160 KB of LDS (4 waves per SIMD).
 // first region of a wave's carve: the staged coordinates (FP32 path), or the
 // BF16 path's two insert grids, each a tile's 16 x 16 rescored distances
-// (1 KB), offer flags (256 bytes) and the ids of its 16 row and 16 column
-// members (128 bytes)
+// (1 KB), 32 offer masks of its members (128 of 256 bytes) and the ids of its
+// 16 row and 16 column members (128 bytes)
 constexpr int GRID_BYTES = 16 * 16 * 4 + 16 * 16 + 32 * 4;
 __host__ __device__ inline int stage_bytes(int GS, bool bf)
 {
@@ -713,6 +713,9 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
         auto gids = [&](int gi) {
             return reinterpret_cast<const int32_t *>(grid_at(gi) + 16 * 16 * 4 + 16 * 16);
         };
+        auto gmask = [&](int gi) {
+            return reinterpret_cast<const uint32_t *>(grid_at(gi) + 16 * 16 * 4);
+        };
         const int j = lane & 15;
         // two tiles of one row band share their row members: one lane then
         // offers a row member both grids' proposals (lanes 0-15), and the
@@ -730,13 +733,10 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
             const int32_t me = gids(gi)[rowside ? j : 16 + j];
             uint32_t have = 0;
             if (me >= 0) {
-                for (int g2 = 0; g2 < (both ? 2 : 1); g2++) {
-                    const uint8_t *gflag = grid_at(gi + g2) + 16 * 16 * 4;
-                    for (int t = 0; t < 16; t++) {
-                        const int cell = rowside ? j * 16 + t : t * 16 + j;
-                        have |= (uint32_t)((gflag[cell] >> (rowside ? 0 : 1)) & 1) << (16 * g2 + t);
-                    }
-                }
+                const int mw = (rowside ? 0 : 16) + j;
+                have = gmask(gi)[mw];
+                if (both)
+                    have |= gmask(gi + 1)[mw] << 16;
             }
             if (have)
                 insert_local<KB>(a, me, have, [&](int t) {
@@ -870,12 +870,14 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
                 static_assert(TMAX == 1, "an insert grid holds one tile");
                 unsigned char *gb = grid_at(pending ? 1 : 0);
                 float *gl = reinterpret_cast<float *>(gb);
-                uint8_t *gflag = gb + 16 * 16 * 4;
-                int32_t *gid = reinterpret_cast<int32_t *>(gflag + 16 * 16);
+                // bit t of word j: row member j is offered column member t;
+                // of word 16 + j: column member j is offered row member t
+                uint32_t *gm = reinterpret_cast<uint32_t *>(gb + 16 * 16 * 4);
+                int32_t *gid = reinterpret_cast<int32_t *>(gb + 16 * 16 * 4 + 16 * 16);
                 const int rb = tl[0] & 0xFF, cb = (tl[0] >> 8) & 0xFF;
                 __builtin_amdgcn_wave_barrier();
-                reinterpret_cast<uint32_t *>(gflag)[lane] = 0u;
                 if (lane < 32) {
+                    gm[lane] = 0u;
                     const int slot = (lane < 16 ? rb : cb) + (lane & 15);
                     gid[lane] = slot < g.GP ? L.grp[slot] : -1;
                 }
@@ -907,9 +909,11 @@ __global__ __launch_bounds__(JOIN_WAVES * WAVE, 4) void k_join_bf16(Rows R, Roun
                             l = cos_finish(D, L.gnorm[sr], L.gnorm[sc]);
                         gp = ((w >> 16) & 1) != 0;
                         gq = ((w >> 17) & 1) != 0;
-                        const int cell = (sr - rb) * 16 + (sc - cb);
-                        gl[cell] = l;
-                        gflag[cell] = (uint8_t)((gp ? 1 : 0) | (gq ? 2 : 0));
+                        gl[(sr - rb) * 16 + (sc - cb)] = l;
+                        if (gp)
+                            atomicOr(gm + (sr - rb), 1u << (sc - cb));
+                        if (gq)
+                            atomicOr(gm + 16 + (sc - cb), 1u << (sr - rb));
                     }
                     n_attempt += __popcll(__ballot(gp)) + __popcll(__ballot(gq));
                 }
