@@ -213,6 +213,26 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
             picked[lane] = (int32_t)((skip >= 0 && lane >= skip) ? lane + 1 : lane);
         got = m;
     } else {
+        // the first m draws, when they are distinct, are the answer
+        {
+            const uint64_t h = hash5(a.seed, tag, (uint64_t)i, (uint64_t)lane, 0);
+            uint32_t v;
+            if (skip >= 0) {
+                v = draw_below(h, N - 1);
+                if ((int64_t)v >= skip)
+                    v++;
+            } else {
+                v = draw_below(h, N);
+            }
+            bool dup = false;
+            for (int j = 0; j < m; j++)
+                dup |= j < lane && (uint32_t)__builtin_amdgcn_readlane((int)v, j) == v;
+            if (__ballot(lane < m && dup) == 0ull) {
+                if (lane < m)
+                    picked[lane] = (int32_t)v;
+                got = m;
+            }
+        }
         const int64_t budget = 64 * (int64_t)m + 4096;
         const uint64_t below = (1ull << lane) - 1ull;
         for (int64_t base = 0; got < m && base < budget; base += WAVE) {
@@ -261,6 +281,42 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
         got = __shfl(got, 0, WAVE);
     }
     __builtin_amdgcn_wave_barrier();
+    // l2 between rows certified exact (integer coordinates in [0, 256],
+    // squared norm below 2^23): every partial sum of squared differences is an
+    // integer below 2^24, so any order of summation gives the canonical value;
+    // four lanes then share a distance, each summing a quarter of the bf16 row
+    float dsplit = 0.0f;
+    bool split = false;
+    if (METRIC == M_L2 && R.eb && m > 0 && m <= WAVE / 4 && signbit(R.eb[R.phys(i)])) {
+        const int q = lane >> 2, part = lane & 3;
+        const bool mine = q < m;
+        const int64_t g = mine ? picked[q] + cand_off : i;
+        const bool cert = signbit(R.eb[R.phys(g)]);
+        if (__ballot(mine && !cert) == 0ull) {
+            split = true;
+            const int per = R.db / 4;  // a multiple of 8
+            const uint16_t *xi = R.xb + R.phys(i) * R.db + part * per;
+            const uint16_t *xg = R.xb + R.phys(g) * R.db + part * per;
+            float acc = 0.0f;
+            for (int c = 0; c < per; c += 8) {
+                const uint4 pi = *reinterpret_cast<const uint4 *>(xi + c);
+                const uint4 pg = *reinterpret_cast<const uint4 *>(xg + c);
+                const uint32_t wi[4] = {pi.x, pi.y, pi.z, pi.w}, wg[4] = {pg.x, pg.y, pg.z, pg.w};
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    const float d0 = __uint_as_float(wi[t] << 16) - __uint_as_float(wg[t] << 16);
+                    const float d1 = __uint_as_float(wi[t] & 0xFFFF0000u) -
+                                     __uint_as_float(wg[t] & 0xFFFF0000u);
+                    acc += d0 * d0;
+                    acc += d1 * d1;
+                }
+            }
+            acc += __shfl_xor(acc, 1, WAVE);
+            acc += __shfl_xor(acc, 2, WAVE);
+            // list lane first + q takes group q's sum
+            dsplit = __shfl(acc, 4 * (lane - first), WAVE);
+        }
+    }
     uint64_t key = 0;
     if (lane < a.k) {
         if (lane < first) {
@@ -268,9 +324,15 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
             key = key_empty(key) ? empty_key(lane) : key_strip(key);
         } else if (lane < first + m) {
             int64_t g = picked[lane - first] + cand_off;
-            float na = R.norm ? R.norm[R.phys(i)] : 0.0f, nb = R.norm ? R.norm[R.phys(g)] : 0.0f;
-            float dv = canon_dist<METRIC>(R.x + R.phys(i) * R.dp, R.x + R.phys(g) * R.dp, R.dp,
-                                          na, nb);
+            float dv;
+            if (split) {
+                dv = dsplit;
+            } else {
+                float na = R.norm ? R.norm[R.phys(i)] : 0.0f,
+                      nb = R.norm ? R.norm[R.phys(g)] : 0.0f;
+                dv = canon_dist<METRIC>(R.x + R.phys(i) * R.dp, R.x + R.phys(g) * R.dp, R.dp, na,
+                                        nb);
+            }
             key = make_key(dv, (uint32_t)g, F_NEW);
         } else {
             key = empty_key(lane);
