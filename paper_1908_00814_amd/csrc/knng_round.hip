@@ -16,7 +16,9 @@ namespace knng {
 namespace {
 
 // Forward sample of round t over the rows holding NEW entries (dtag == t), one
-// group of G lanes per row (k <= G), 64 / G rows per wave.  Marks u and every
+// group of G lanes per row (k <= G), 64 / G rows per wave.  The sample is the s
+// NEW entries of smallest hash priority (all of them when there are at most
+// s; where they go in the sample slots does not matter).  Marks u and every
 // sampled NEW entry as active in round t; a row left with more than s NEW
 // entries is sampled again in round t+1.  The FRESH count of round t-1 is
 // accumulated per wave.
@@ -57,18 +59,27 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
             const bool isnew = !empty && (v & F_NEW);
             const bool isold = !empty && !(v & F_NEW);
             const uint32_t id = key_id(v);
-            uint64_t pk = ~0ull;
-            if (isnew) {
-                uint64_t h = hash5(a.seed, TAG_FWD, (uint64_t)a.round, (uint64_t)u, (uint64_t)id);
-                pk = ((h >> 32) << 32) | id;
-            }
-            // rank among the row's NEW entries (ties, which a well-formed list
-            // never has, go by slot so that the sample slots stay a permutation)
-            int rank = 0, nnew = 0;
-            for (int j = 0; j < a.k; j++) {
-                uint64_t o = __shfl(pk, base + j, WAVE);
-                rank += o < pk || (o == pk && j < gl);
-                nnew += o != ~0ull;
+            // a row with at most s NEW entries samples them all, in slot order;
+            // a row with more ranks them by hash priority (ties, which a
+            // well-formed list never has, go by slot so that the sample slots
+            // stay a permutation) and samples the s first
+            const uint64_t nm = __ballot(isnew) & gbits;
+            const int nnew = __popcll(nm);
+            int rank = __popcll(nm & below);
+            if (__ballot(nnew > a.s) != 0ull) {
+                uint64_t pk = ~0ull;
+                if (isnew && nnew > a.s) {
+                    uint64_t h =
+                        hash5(a.seed, TAG_FWD, (uint64_t)a.round, (uint64_t)u, (uint64_t)id);
+                    pk = ((h >> 32) << 32) | id;
+                }
+                int rk = 0;
+                for (int j = 0; j < a.k; j++) {
+                    uint64_t o = __shfl(pk, base + j, WAVE);
+                    rk += o < pk || (o == pk && j < gl);
+                }
+                if (nnew > a.s)
+                    rank = rk;
             }
             const bool sampled = isnew && rank < a.s;
             bool mark = false;  // the sampled id becomes active
