@@ -247,44 +247,63 @@ __device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a,
     g.offNB = g.offOA + r4(oA);
     g.offOB = g.offNB + r4(nB);
     g.GP = g.offOB + r4(oB);
-    // slots lane + 64 i: ids, then every bound and norm in one round trip
-    constexpr int NSL = 3;
-    int32_t id[NSL];
-    uint64_t gw[NSL];
-    float gn[NSL], gq[NSL], ge[NSL];
-#pragma unroll
-    for (int i = 0; i < NSL; i++) {
-        const int slot = lane + i * WAVE;
-        int32_t v = -1;
-        if (slot < nA)
-            v = L.tnew[slot];
-        else if (slot >= g.offOA && slot < g.offOA + oA)
-            v = L.toldA[slot - g.offOA];
-        else if (slot >= g.offNB && slot < g.offNB + nB)
-            v = L.tnew[nA + (slot - g.offNB)];
-        else if (slot >= g.offOB && slot < g.offOB + oB)
-            v = L.toldB[slot - g.offOB];
-        id[i] = slot < g.GP ? v : -1;
-    }
-#pragma unroll
-    for (int i = 0; i < NSL; i++) {
-        const bool has = id[i] >= 0;
-        gw[i] = has ? a.worst[id[i]] : 0ull;
-        gn[i] = METRIC == M_COS && has ? R.norm[R.phys(id[i])] : 1.0f;
-        gq[i] = BF && has ? R.sq[R.phys(id[i])] : 0.0f;
-        ge[i] = BF && has ? R.eb[R.phys(id[i])] : 0.0f;
-    }
-#pragma unroll
-    for (int i = 0; i < NSL; i++) {
-        const int slot = lane + i * WAVE;
-        if (slot < g.GP) {
-            L.grp[slot] = id[i];
-            L.gw[slot] = gw[i];
+    if constexpr (!BF) {
+        // FP32 path: slot by slot (fewer live registers in its larger kernels)
+        for (int slot = lane; slot < g.GP; slot += WAVE) {
+            int32_t id = -1;
+            if (slot < nA)
+                id = L.tnew[slot];
+            else if (slot >= g.offOA && slot < g.offOA + oA)
+                id = L.toldA[slot - g.offOA];
+            else if (slot >= g.offNB && slot < g.offNB + nB)
+                id = L.tnew[nA + (slot - g.offNB)];
+            else if (slot >= g.offOB && slot < g.offOB + oB)
+                id = L.toldB[slot - g.offOB];
+            L.grp[slot] = id;
+            L.gw[slot] = id >= 0 ? a.worst[id] : 0ull;
             if (METRIC == M_COS)
-                L.gnorm[slot] = gn[i];
-            if (BF) {
-                L.gsq[slot] = gq[i];
-                L.gerr[slot] = ge[i];
+                L.gnorm[slot] = id >= 0 ? R.norm[R.phys(id)] : 1.0f;
+        }
+    } else {
+    // slots lane + 64 i: ids, then every bound and norm in one round trip
+        constexpr int NSL = 3;
+        int32_t id[NSL];
+        uint64_t gw[NSL];
+        float gn[NSL], gq[NSL], ge[NSL];
+    #pragma unroll
+        for (int i = 0; i < NSL; i++) {
+            const int slot = lane + i * WAVE;
+            int32_t v = -1;
+            if (slot < nA)
+                v = L.tnew[slot];
+            else if (slot >= g.offOA && slot < g.offOA + oA)
+                v = L.toldA[slot - g.offOA];
+            else if (slot >= g.offNB && slot < g.offNB + nB)
+                v = L.tnew[nA + (slot - g.offNB)];
+            else if (slot >= g.offOB && slot < g.offOB + oB)
+                v = L.toldB[slot - g.offOB];
+            id[i] = slot < g.GP ? v : -1;
+        }
+    #pragma unroll
+        for (int i = 0; i < NSL; i++) {
+            const bool has = id[i] >= 0;
+            gw[i] = has ? a.worst[id[i]] : 0ull;
+            gn[i] = METRIC == M_COS && has ? R.norm[R.phys(id[i])] : 1.0f;
+            gq[i] = BF && has ? R.sq[R.phys(id[i])] : 0.0f;
+            ge[i] = BF && has ? R.eb[R.phys(id[i])] : 0.0f;
+        }
+    #pragma unroll
+        for (int i = 0; i < NSL; i++) {
+            const int slot = lane + i * WAVE;
+            if (slot < g.GP) {
+                L.grp[slot] = id[i];
+                L.gw[slot] = gw[i];
+                if (METRIC == M_COS)
+                    L.gnorm[slot] = gn[i];
+                if (BF) {
+                    L.gsq[slot] = gq[i];
+                    L.gerr[slot] = ge[i];
+                }
             }
         }
     }
