@@ -127,12 +127,49 @@ __global__ __launch_bounds__(256) void k_prep_input(Rows R, int64_t row0, int64_
             if (g == r)
                 err |= ERR_SELF;
         }
+    }
+    // l2 between rows certified exact (integer coordinates in [0, 256],
+    // squared norm below 2^23): every partial sum of squared differences is an
+    // integer below 2^24, so any order gives the canonical value; two lanes
+    // then share a distance, each summing half of the bf16 row
+    float dsplit = 0.0f;
+    bool split = false;
+    if (METRIC == M_L2 && !dist && R.eb && kin <= WAVE / 2 && signbit(R.eb[R.phys(r)])) {
+        const int q = lane >> 1, part = lane & 1;
+        const int64_t gq = __shfl(g, q, WAVE);
+        const bool mine = q < kin && gq >= 0;
+        if (__ballot(mine && !signbit(R.eb[R.phys(gq)])) == 0ull) {
+            split = true;
+            const int half = R.db / 2;  // a multiple of 16
+            const uint16_t *xr = R.xb + R.phys(r) * R.db + part * half;
+            const uint16_t *xg = R.xb + R.phys(mine ? gq : r) * R.db + part * half;
+            float acc = 0.0f;
+            for (int c = 0; c < half; c += 8) {
+                const uint4 pr = *reinterpret_cast<const uint4 *>(xr + c);
+                const uint4 pg = *reinterpret_cast<const uint4 *>(xg + c);
+                const uint32_t wr[4] = {pr.x, pr.y, pr.z, pr.w}, wg[4] = {pg.x, pg.y, pg.z, pg.w};
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    const float d0 = __uint_as_float(wr[t] << 16) - __uint_as_float(wg[t] << 16);
+                    const float d1 = __uint_as_float(wr[t] & 0xFFFF0000u) -
+                                     __uint_as_float(wg[t] & 0xFFFF0000u);
+                    acc += d0 * d0;
+                    acc += d1 * d1;
+                }
+            }
+            acc += __shfl_xor(acc, 1, WAVE);
+            dsplit = __shfl(acc, 2 * lane, WAVE);
+        }
+    }
+    if (act) {
         float dv = 0.0f;
         if (g >= 0) {
             if (dist) {
                 dv = dist[wid * kin + lane];
                 if (!(dv >= 0.0f) || isinf(dv))
                     err |= ERR_BAD_DIST;
+            } else if (split) {
+                dv = dsplit;
             } else {
                 const float *a = R.x + R.phys(r) * R.dp, *b = R.x + R.phys(g) * R.dp;
                 float na = R.norm ? R.norm[R.phys(r)] : 0.0f;
@@ -142,15 +179,21 @@ __global__ __launch_bounds__(256) void k_prep_input(Rows R, int64_t row0, int64_
         }
         key = make_key(dv > 0.0f ? dv : 0.0f, (uint32_t)(g < 0 ? 0 : g), 0);
     }
-    // duplicates and order
+    // duplicates, and the order of recomputed distances (ids are below 2^31)
     int rank = 0;
+    const int32_t g32 = (int32_t)g;
     for (int j = 0; j < kin; j++) {
-        uint64_t o = __shfl(key, j, WAVE);
-        int64_t og = __shfl(g, j, WAVE);
-        if (act && j != lane && og == g && g >= 0)
+        const int32_t og = __builtin_amdgcn_readlane(g32, j);
+        if (act && j != lane && og == g32 && g >= 0)
             err |= ERR_DUP;
-        if (act && o < key)
-            rank++;
+    }
+    if (!dist) {
+        for (int j = 0; j < kin; j++) {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, j);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), j);
+            if (act && (((uint64_t)hi << 32) | lo) < key)
+                rank++;
+        }
     }
     if (dist) {
         uint64_t prev = __shfl_up(key, 1, WAVE);
