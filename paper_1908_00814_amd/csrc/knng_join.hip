@@ -10,10 +10,12 @@
 //   J-Merge: not both from the built set S1 (Algorithm 2).
 // l = m(p, q) is offered to both lists (UpdateNN in both directions) through
 // the lock-free bounded insert; a pair is first screened against an upper
-// bound of each list's worst entry (set at the round start, lowered after
-// every successful insert, read when u's neighbourhood is formed).  The worst
-// entry only decreases during a round, so the screen never drops an edge that
-// could stay.
+// bound of each list's worst entry (set at the round start, lowered after a
+// list takes entries, read when u's neighbourhood is formed).  The worst entry
+// only decreases during a round, so the screen never drops an edge that could
+// stay.  The FP32 path queues its proposals and drains the queue with all
+// lanes; the BF16 path gathers a tile's proposals in an insert grid and offers
+// two grids at a time member by member (insert_local).
 //
 // Layout.  One wave owns one u at a time (4 independent waves per workgroup,
 // no workgroup barriers).  The members are placed in LDS in four regions, each
