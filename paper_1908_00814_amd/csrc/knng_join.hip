@@ -967,7 +967,9 @@ hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, 
     const bool small = units <= 4 * WAVE;
     const int64_t rows = a.alist ? a.n_active : a.n;  // list mode: the listed rows
     // graph mode: a fixed grid whose waves walk however many rows are listed
-    const int64_t waves = a.dev ? 8192 : (rows < 32768 ? rows : 32768);
+    // 8,192 waves, twice what the chip holds at once at 4 waves per SIMD: with
+    // more, the later batches of waves end in a tail of waves with few rows
+    const int64_t waves = a.dev ? 8192 : (rows < 8192 ? rows : 8192);
     int64_t grid = (waves + JOIN_WAVES - 1) / JOIN_WAVES;
     if (grid < 1)
         grid = 1;
