@@ -967,9 +967,11 @@ hipError_t launch_join(const Rows &R, int metric, int bf16, const RoundArgs &a, 
     const bool small = units <= 4 * WAVE;
     const int64_t rows = a.alist ? a.n_active : a.n;  // list mode: the listed rows
     // graph mode: a fixed grid whose waves walk however many rows are listed
-    // 8,192 waves, twice what the chip holds at once at 4 waves per SIMD: with
-    // more, the later batches of waves end in a tail of waves with few rows
-    const int64_t waves = a.dev ? 8192 : (rows < 8192 ? rows : 8192);
+    // BF16: 8,192 waves, twice what the chip holds at once at 4 waves per
+    // SIMD (with more, the later batches of waves end in a tail of waves with
+    // few rows); FP32: 32,768, which measured faster for its kernels
+    const int64_t cap = use_bf ? 8192 : 32768;
+    const int64_t waves = a.dev ? 8192 : (rows < cap ? rows : cap);
     int64_t grid = (waves + JOIN_WAVES - 1) / JOIN_WAVES;
     if (grid < 1)
         grid = 1;
