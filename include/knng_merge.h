@@ -120,7 +120,9 @@ typedef struct {
     uint32_t flags;
 } knng_opts;
 
-/* a point set: n rows of d fp32 values, row-major, on the device */
+/* a point set: n rows of d fp32 values, row-major, on the device; a set and
+ * the union of the sets one call merges hold fewer than 2^30 - 64 rows (a
+ * list entry keeps a row id in 30 bits), 1 <= d <= 65536 */
 typedef struct {
     int64_t n;
     int32_t d;

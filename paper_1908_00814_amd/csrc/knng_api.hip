@@ -352,6 +352,9 @@ static knng_status knng_merge_impl(const knng_set *S1, const knng_graph *G1, con
     if (S1->d != S2->d)
         return fail(KNNG_EINVAL, "S1->d = %d differs from S2->d = %d", S1->d, S2->d);
     const int64_t n1 = S1->n, n2 = S2->n, n = n1 + n2;
+    // a list entry holds a row id in 30 bits
+    if (n >= (1ll << 30) - 64)
+        return fail(KNNG_EINVAL, "n1 + n2 = %lld rows out of range", (long long)n);
     if (k < 1 || k > MAX_K || k > n - 1)
         return fail(KNNG_EINVAL, "k = %d out of range [1, min(64, n1+n2-1)]", k);
     const int k1 = keep_count(opts, k);
@@ -433,6 +436,8 @@ static knng_status knng_expand_impl(const knng_set *S, const knng_graph *G, cons
     if (S->n > 0 && S->d != raw->d)
         return fail(KNNG_EINVAL, "S->d = %d differs from raw->d = %d", S->d, raw->d);
     const int64_t nb = S->n, nr = raw->n, n = nb + nr;
+    if (n >= (1ll << 30) - 64)
+        return fail(KNNG_EINVAL, "S->n + raw->n = %lld rows out of range", (long long)n);
     if (k < 1 || k > MAX_K || k > n - 1)
         return fail(KNNG_EINVAL, "k = %d out of range [1, min(64, n-1)]", k);
     const int k1 = keep_count(opts, k);
@@ -1060,6 +1065,9 @@ static knng_status knng_merge_bruteforce_impl(const knng_set *S1, const knng_gra
     if (S1->d != S2->d)
         return fail(KNNG_EINVAL, "S1->d = %d differs from S2->d = %d", S1->d, S2->d);
     const int64_t n1 = S1->n, n2 = S2->n, n = n1 + n2;
+    // a list entry holds a row id in 30 bits
+    if (n >= (1ll << 30) - 64)
+        return fail(KNNG_EINVAL, "n1 + n2 = %lld rows out of range", (long long)n);
     if (k < 1 || k > MAX_K || k > n - 1)
         return fail(KNNG_EINVAL, "k = %d out of range [1, min(64, n1+n2-1)]", k);
     if ((s = check_graph_in(G1, n1, "G1", 0)) || (s = check_graph_in(G2, n2, "G2", 0)) ||

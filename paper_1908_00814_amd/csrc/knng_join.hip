@@ -401,22 +401,21 @@ __device__ __forceinline__ void insert_into(const RoundArgs &a, int64_t dst, uin
 // successful swap replaces the true maximum, and duplicates stay out.  The
 // view's maximum is kept between proposals, so a proposal that does not beat
 // it costs one comparison; the maximum of the final view bounds the list's.
-template <int KB, class KeyFn>
-__device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t have, KeyFn key_of)
+// FULL: the list is exactly as long as the view, so no slot of the view is
+// unused and no slot index needs a test (without it the compiler keeps one
+// lane mask per slot, which spill and are reloaded in every pass of the loop).
+template <int KB, bool FULL, class KeyFn>
+__device__ __forceinline__ void insert_view(const RoundArgs &a, int64_t dst, uint32_t have,
+                                            KeyFn key_of)
 {
     constexpr int B = KB <= 16 ? KB : (KB == 32 ? 20 : 16);
-    const int cap = a.k;
-    if (cap > B) {
-        for (; have; have &= have - 1)
-            insert_into<KB>(a, dst, key_of(__builtin_ctz(have)));
-        return;
-    }
+    const int cap = FULL ? B : a.k;
     uint64_t *slots = a.L + dst * cap;
     bool any = false;
     uint64_t v[B];
 #pragma unroll
     for (int j = 0; j < B; j++)
-        v[j] = j < cap ? slots[j] : 0ull;
+        v[j] = FULL || j < cap ? slots[j] : 0ull;
     uint64_t mx = 0;
     int mj = 0;
     auto rescan = [&]() {
@@ -424,7 +423,7 @@ __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t ha
         mj = 0;
 #pragma unroll
         for (int j = 0; j < B; j++) {
-            if (j < cap && v[j] > mx) {
+            if ((FULL || j < cap) && v[j] > mx) {
                 mx = v[j];
                 mj = j;
             }
@@ -437,11 +436,13 @@ __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t ha
             have &= have - 1;
             continue;
         }
-        const uint64_t kid = key_strip(key);
+        // equal ids mean equal entries (one pair, one canonical distance), so
+        // the id field decides; empty slots' id fields are above every row id
+        const uint32_t kid = key_id(key);
         bool dup = false;
 #pragma unroll
         for (int j = 0; j < B; j++)
-            dup |= j < cap && key_strip(v[j]) == kid;
+            dup |= (FULL || j < cap) && key_id(v[j]) == kid;
         if (dup) {
             have &= have - 1;
             continue;
@@ -465,6 +466,23 @@ __device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t ha
         // every word of the view is at least its slot's current value
         atomic_min_u64(a.worst + dst, key_strip(mx));
         a.dtag[dst] = a.tag0 + a.round + 1;
+    }
+}
+
+// UpdateNN of the proposals in have (bits of key_of's index) for row dst: a
+// list longer than the view takes them one by one, a shorter or equal one
+// through the view
+template <int KB, class KeyFn>
+__device__ inline void insert_local(const RoundArgs &a, int64_t dst, uint32_t have, KeyFn key_of)
+{
+    constexpr int B = KB <= 16 ? KB : (KB == 32 ? 20 : 16);
+    if (a.k > B) {
+        for (; have; have &= have - 1)
+            insert_into<KB>(a, dst, key_of(__builtin_ctz(have)));
+    } else if (a.k == B) {
+        insert_view<KB, true>(a, dst, have, key_of);
+    } else {
+        insert_view<KB, false>(a, dst, have, key_of);
     }
 }
 

@@ -427,3 +427,25 @@ def test_smerge_limits_identical_to_oracle(hip, case):
                                 precision=prec)
         assert_same_graph(host(gi), host(gd), oi, od, f"{case} {prec}")
         _same_stats(gst, ost)
+
+
+def test_union_above_id_range_rejected(hip):
+    # each set is in range, their union is not: rejected before any row or
+    # list is read (the sets point at a few device bytes)
+    import ctypes
+    import torch
+    lib = hip.load()
+    x = torch.zeros(16, dtype=torch.float32, device="cuda")
+    half = (1 << 29) - 8
+    s1 = hip.Set(half, 1, x.data_ptr())
+    s2 = hip.Set(half, 1, x.data_ptr())
+    g = hip.Graph(0, 0, None, None)
+    o = hip.opts()
+    rc = lib.knng_merge(ctypes.byref(s1), ctypes.byref(g), ctypes.byref(s2), ctypes.byref(g), 6,
+                        0, ctypes.byref(o), ctypes.byref(g), None, 0, None, None)
+    with pytest.raises(hip.KnngError, match="rows out of range"):
+        hip._check(rc)
+    rc = lib.knng_expand(ctypes.byref(s1), ctypes.byref(g), ctypes.byref(s2), 6, 0,
+                         ctypes.byref(o), ctypes.byref(g), None, 0, None, None)
+    with pytest.raises(hip.KnngError, match="rows out of range"):
+        hip._check(rc)
