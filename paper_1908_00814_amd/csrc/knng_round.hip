@@ -171,11 +171,49 @@ __global__ __launch_bounds__(256) void k_prep_active(RoundArgs a)
     }
 }
 
+// An offer past the s-th to a reservoir: every slot has been claimed by an
+// earlier offer, whose store may still be on its way.  The offer reads the
+// slots again until none is empty (a claimed slot is written once, by a wave
+// already past its claim, so the wait ends), then replaces the largest word
+// if it is smaller (compare-and-swap, as in bounded_insert: a failed swap
+// reads the slots again).  A word read through the caches is the slot's
+// current one or an older, larger one.
+__device__ inline void reservoir_overflow(uint64_t *slots, int cap, uint64_t key, uint64_t *err)
+{
+    constexpr int B = MAX_S <= 16 ? MAX_S : (MAX_S == 32 ? 20 : 16);
+    for (int spin = 0; spin < SPIN_BUDGET; spin++) {
+        uint64_t mx = 0;
+        int mj = 0;
+        bool pend = false;
+        for (int j0 = 0; j0 < cap; j0 += B) {
+            uint64_t v[B];
+#pragma unroll
+            for (int j = 0; j < B; j++)
+                v[j] = j0 + j < cap ? (spin == 0 ? slots[j0 + j] : ld_agent(slots + j0 + j))
+                                    : 0ull;
+#pragma unroll
+            for (int j = 0; j < B; j++) {
+                // an empty slot's id field is above every row id
+                pend |= (uint32_t)v[j] >= 0x40000000u;
+                if (v[j] > mx) {
+                    mx = v[j];
+                    mj = j0 + j;
+                }
+            }
+        }
+        if (pend)
+            continue;
+        if (key >= mx || cas64(slots + mj, mx, key))
+            return;
+    }
+    atomicOr((unsigned long long *)err, (unsigned long long)ERR_SPIN);
+}
+
 // u offered to v's reverse reservoir of one kind (0: NEW, 1: OLD), which
-// keeps the s offers of smallest hash priority.  The first s offers take a
-// slot of their own (every slot change is a compare-and-swap to a smaller
-// word, as in bounded_insert, so a slot that a competing insert has taken
-// sends this offer the long way).
+// keeps the s offers of smallest hash priority.  The first s offers claim a
+// slot each and store their word there (an agent-scope store, which the
+// agent-scope reads of other waves see; nothing else writes an empty slot),
+// the others go through reservoir_overflow.
 __device__ inline void offer_reverse(const RoundArgs &a, int64_t v, int64_t u, int kind)
 {
     const uint64_t h = hash5(a.seed, kind ? TAG_ROLD : TAG_RNEW, (uint64_t)a.round, (uint64_t)v,
@@ -183,9 +221,13 @@ __device__ inline void offer_reverse(const RoundArgs &a, int64_t v, int64_t u, i
     const uint64_t key = ((h >> 32) << 32) | (uint64_t)u;
     uint64_t *slots = (kind ? a.rold : a.rnew) + v * a.s;
     const int pos = atomicAdd(a.rfill + 2 * v + kind, 1);
-    if (pos < a.s && cas64(slots + pos, empty_key(pos), key))
-        return;
-    bounded_insert<MAX_S>(slots, a.s, key, DUP_NONE, nullptr, a.ctr + C_ERR);
+    if (pos < a.s)
+        __hip_atomic_store(slots + pos, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // a claimed slot that an overflow offer waits for may be this wave's own:
+    // the ballot (which every active lane reaches) keeps the claims' writes
+    // ahead of the overflow loop in the wave's instruction stream
+    if (__ballot(pos >= a.s) != 0ull && pos >= a.s)
+        reservoir_overflow(slots, a.s, key, a.ctr + C_ERR);
 }
 
 // Reverse(G) of round t, one thread per (row u, slot): a sampled edge u -> v
@@ -289,7 +331,7 @@ __global__ __launch_bounds__(256) void k_reverse_rows(RoundArgs a)
 // has just emptied it), so the wave keeps the s offers of smallest priority
 // itself and stores them, with no atomics; rfill counts every offer made, so
 // that part 1's offers that follow take free slots or go through
-// bounded_insert as before.
+// reservoir_overflow.
 __global__ __launch_bounds__(256) void k_reverse_base(RoundArgs a)
 {
     __shared__ uint64_t keep_all[256 / WAVE][MAX_S];

@@ -449,3 +449,24 @@ def test_union_above_id_range_rejected(hip):
                          ctypes.byref(o), ctypes.byref(g), None, 0, None, None)
     with pytest.raises(hip.KnngError, match="rows out of range"):
         hip._check(rc)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_reverse_hub_reservoirs(hip, precision):
+    # every list holds its set's row 0, so the reverse reservoirs of the two
+    # hubs get thousands of offers each: one wave mixes the first s offers
+    # (slot claims) with later ones, which wait until every claimed slot is
+    # written; identical to the oracle
+    S1, S2 = ragged_sets(3000, 2500, 16, 121)
+    G1 = oracle.exact_graph(S1, 8)[0].copy()
+    G2 = oracle.exact_graph(S2, 8)[0].copy()
+    for G in (G1, G2):
+        rows = np.arange(1, G.shape[0])
+        has = (G[1:] == 0).any(axis=1)
+        G[rows[~has], -1] = 0
+    assert all((G == 0).any(axis=1)[1:].all() for G in (G1, G2))
+    oi, od, ost = oracle.smerge(S1, (G1, None), S2, (G2, None), 8, "l2", sample=5, seed=12)
+    gi, gd, gst = hip.merge(dev(S1), (dev(G1), None), dev(S2), (dev(G2), None), 8, "l2",
+                            sample=5, seed=12, precision=precision)
+    assert_same_graph(host(gi), host(gd), oi, od, f"hub reservoirs {precision}")
+    _same_stats(gst, ost)
