@@ -34,13 +34,12 @@ knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
     R.xb = bf16 ? w.xb : nullptr;
     R.db = w.db;
     R.norm = w.norm;
-    R.sq = w.sq;
-    R.eb = w.eb;
+    R.se = w.se;
     R.n = n;
     R.d = d;
     R.dp = w.dp;
-    if (w.norm || w.sq)
-        HIP_TRY(launch_norms(w.x, n, w.dp, w.norm, w.sq, w.eb, metric == KNNG_COSINE, w.ctr,
+    if (w.norm || w.se)
+        HIP_TRY(launch_norms(w.x, n, w.dp, w.norm, w.se, metric == KNNG_COSINE, w.ctr,
                              st));
     uint64_t h[C_WORDS];
     knng_status s = read_ctr(w.ctr, h, st);

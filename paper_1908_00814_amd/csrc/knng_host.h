@@ -71,7 +71,8 @@ struct RoundGraph {
 
 struct Layout {
     uint64_t *ctr;
-    float *x, *norm, *sq, *eb;
+    float *x, *norm;
+    float2 *se;
     uint16_t *xb;
     uint64_t *gin, *L, *worst, *rnew, *rold;
     int32_t *new_f, *old_f, *cnt_f, *dtag, *atag, *rfill;
@@ -115,8 +116,7 @@ inline void carve_merge(Carve &c, Layout &w, int64_t n, int64_t n_list, int d, i
     w.x = c.take<float>((size_t)n * w.dp);
     w.norm = m == KNNG_COSINE ? c.take<float>(n) : nullptr;
     w.xb = bf16 ? c.take<uint16_t>((size_t)n * w.db) : nullptr;
-    w.sq = bf16 ? c.take<float>(n) : nullptr;
-    w.eb = bf16 ? c.take<float>(n) : nullptr;
+    w.se = bf16 ? c.take<float2>(n) : nullptr;
     w.gin = c.take<uint64_t>((size_t)(n_list > 0 ? n_list : 1) * (gstride > 0 ? gstride : 1));
     w.L = c.take<uint64_t>((size_t)n * k);
     w.worst = c.take<uint64_t>(n);

@@ -16,8 +16,9 @@ struct Rows {
     const float *x;  // rows x dp fp32, zero-padded
     const float *norm;  // canonical norms (cosine) or nullptr
     const uint16_t *xb; // BF16 path: bf16 copy (round to nearest even, stride db), or nullptr
-    const float *sq;    // BF16 path: squared norms of the bf16-rounded rows, or nullptr
-    const float *eb;    // BF16 path: upper bounds of |x - bf16(x)| per row, or nullptr
+    // BF16 path, per row: the squared norm of the bf16-rounded row and an
+    // upper bound of |x - bf16(x)| (read together), or nullptr
+    const float2 *se;
     int64_t n;
     int d, dp, db;  // db: bf16 row stride, d rounded up to 32
     int64_t split = INT64_MAX, off2 = 0;
@@ -128,8 +129,8 @@ __device__ inline bool take_round(RoundArgs &a, Rows &R)
 // ---- knng_prep.hip
 hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2, int d, int dp,
                        float *x, int db, uint16_t *xb, uint64_t *ctr, hipStream_t st);
-hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float *sq_bf16,
-                        float *err_bf16, int check_zero, uint64_t *ctr, hipStream_t st);
+hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float2 *se_bf16,
+                        int check_zero, uint64_t *ctr, hipStream_t st);
 // Input graph rows [row0, row0+nrows) of the concatenated set: local ids +
 // offset -> sorted keys (kin per row) in `gin`.
 hipError_t launch_prep_input(const Rows &R, int metric, int64_t row0, int64_t nrows,

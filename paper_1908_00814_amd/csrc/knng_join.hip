@@ -291,8 +291,9 @@ __device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a,
             const bool has = id[i] >= 0;
             gw[i] = has ? a.worst[id[i]] : 0ull;
             gn[i] = METRIC == M_COS && has ? R.norm[R.phys(id[i])] : 1.0f;
-            gq[i] = BF && has ? R.sq[R.phys(id[i])] : 0.0f;
-            ge[i] = BF && has ? R.eb[R.phys(id[i])] : 0.0f;
+            const float2 se = BF && has ? R.se[R.phys(id[i])] : make_float2(0.0f, 0.0f);
+            gq[i] = se.x;
+            ge[i] = se.y;
         }
     #pragma unroll
         for (int i = 0; i < NSL; i++) {

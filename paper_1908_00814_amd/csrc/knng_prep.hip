@@ -47,7 +47,7 @@ __global__ void k_pack(const float *__restrict__ x1, int64_t n1, const float *__
 // (ascending fused accumulation) and an upper bound of |x - bf16(x)|
 // (accumulated in FP64, rounded up)
 __global__ void k_norms(const float *__restrict__ x, int64_t n, int dp, float *__restrict__ norm,
-                        float *__restrict__ sq, float *__restrict__ eb, int check_zero,
+                        float2 *__restrict__ se, int check_zero,
                         uint64_t *ctr)
 {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -68,7 +68,7 @@ __global__ void k_norms(const float *__restrict__ x, int64_t n, int dp, float *_
         if (check_zero && !(nr > 0.0f))
             atomicOr((unsigned long long *)(ctr + C_ERR), (unsigned long long)ERR_ZERO_NORM);
     }
-    if (sq) {
+    if (se) {
         float acc = 0.0f;
         double e2 = 0.0;
         bool integral = true;  // every coordinate an integer in [0, 256]
@@ -83,7 +83,6 @@ __global__ void k_norms(const float *__restrict__ x, int64_t n, int dp, float *_
                 integral = integral && vs[j] == rintf(vs[j]) && vs[j] >= 0.0f && vs[j] <= 256.0f;
             }
         }
-        sq[r] = acc;
         // the FP64 sum of exact squares is within (dp * 2^-53) relative;
         // inflate it and the sqrt so the fp32 value is an upper bound
         float e = __double2float_ru(__builtin_sqrt(e2 * (1.0 + 0x1p-36)) * (1.0 + 0x1p-50));
@@ -96,7 +95,7 @@ __global__ void k_norms(const float *__restrict__ x, int64_t n, int dp, float *_
         // the canonical FP32 value bit for bit.
         if (integral && acc < 0x1p23f)
             e = -0.0f;
-        eb[r] = e;
+        se[r] = make_float2(acc, e);
     }
 }
 
@@ -134,11 +133,11 @@ __global__ __launch_bounds__(256) void k_prep_input(Rows R, int64_t row0, int64_
     // then share a distance, each summing half of the bf16 row
     float dsplit = 0.0f;
     bool split = false;
-    if (METRIC == M_L2 && !dist && R.eb && kin <= WAVE / 2 && signbit(R.eb[R.phys(r)])) {
+    if (METRIC == M_L2 && !dist && R.se && kin <= WAVE / 2 && signbit(R.se[R.phys(r)].y)) {
         const int q = lane >> 1, part = lane & 1;
         const int64_t gq = __shfl(g, q, WAVE);
         const bool mine = q < kin && gq >= 0;
-        if (__ballot(mine && !signbit(R.eb[R.phys(gq)])) == 0ull) {
+        if (__ballot(mine && !signbit(R.se[R.phys(gq)].y)) == 0ull) {
             split = true;
             const int half = R.db / 2;  // a multiple of 16
             const uint16_t *xr = R.xb + R.phys(r) * R.db + part * half;
@@ -330,11 +329,11 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
     // four lanes then share a distance, each summing a quarter of the bf16 row
     float dsplit = 0.0f;
     bool split = false;
-    if (METRIC == M_L2 && R.eb && m > 0 && m <= WAVE / 4 && signbit(R.eb[R.phys(i)])) {
+    if (METRIC == M_L2 && R.se && m > 0 && m <= WAVE / 4 && signbit(R.se[R.phys(i)].y)) {
         const int q = lane >> 2, part = lane & 3;
         const bool mine = q < m;
         const int64_t g = mine ? picked[q] + cand_off : i;
-        const bool cert = signbit(R.eb[R.phys(g)]);
+        const bool cert = signbit(R.se[R.phys(g)].y);
         if (__ballot(mine && !cert) == 0ull) {
             split = true;
             const int per = R.db / 4;  // a multiple of 8
@@ -705,11 +704,11 @@ hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2,
     return hipGetLastError();
 }
 
-hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float *sq_bf16,
-                        float *err_bf16, int check_zero, uint64_t *ctr, hipStream_t st)
+hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float2 *se_bf16,
+                        int check_zero, uint64_t *ctr, hipStream_t st)
 {
     hipLaunchKernelGGL(k_norms, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, dp, norm,
-                       sq_bf16, err_bf16, check_zero, ctr);
+                       se_bf16, check_zero, ctr);
     return hipGetLastError();
 }
 

@@ -85,7 +85,7 @@ struct knng_server {
     bool host_rounds = false;  // rounds driven by the host instead of the slot graphs
     int64_t capacity = 0, max_request = 0;
     void *mem = nullptr;
-    Layout store{};           // x, norm, xb, sq, eb for all rows; gin = base lists
+    Layout store{};           // x, norm, xb, se for all rows; gin = base lists
     uint64_t *res = nullptr;  // capacity x k resident lists
     float *stage = nullptr;   // max_request x d: host rows on their way in
     uint64_t *sub_ctr = nullptr;
@@ -125,8 +125,7 @@ void carve_store(Carve &c, knng_server &s)
     w.x = c.take<float>((size_t)s.capacity * w.dp);
     w.norm = s.metric == KNNG_COSINE ? c.take<float>(s.capacity) : nullptr;
     w.xb = s.bf16 ? c.take<uint16_t>((size_t)s.capacity * w.db) : nullptr;
-    w.sq = s.bf16 ? c.take<float>(s.capacity) : nullptr;
-    w.eb = s.bf16 ? c.take<float>(s.capacity) : nullptr;
+    w.se = s.bf16 ? c.take<float2>(s.capacity) : nullptr;
     w.gin = c.take<uint64_t>((size_t)s.capacity * s.gstride);
     w.ctr = c.take<uint64_t>(C_WORDS);
     s.res = c.take<uint64_t>((size_t)s.capacity * s.k);
@@ -234,8 +233,7 @@ knng_status run_request(knng_server *s, Slot &sl, const std::vector<uint64_t> &t
         R.x = sl.w.x;
         R.norm = sl.w.norm;
         R.xb = sl.w.xb;
-        R.sq = sl.w.sq;
-        R.eb = sl.w.eb;
+        R.se = sl.w.se;
         R.n = m + nr;
         R.d = s->d;
         R.dp = sl.w.dp;
@@ -637,10 +635,10 @@ static knng_status knng_server_submit_impl(knng_server *s, const float *raw, int
         HIP_TRY(launch_pack(nullptr, 0, src, n_raw, s->d, w.dp, w.x + row * w.dp,
                             s->bf16 ? w.db : 0, s->bf16 ? w.xb + row * w.db : nullptr,
                             s->sub_ctr, s->sub_st));
-        if (w.norm || w.sq)
+        if (w.norm || w.se)
             HIP_TRY(launch_norms(w.x + row * w.dp, n_raw, w.dp, w.norm ? w.norm + row : nullptr,
-                                 w.sq ? w.sq + row : nullptr, w.eb ? w.eb + row : nullptr,
-                                 s->metric == KNNG_COSINE, s->sub_ctr, s->sub_st));
+                                 w.se ? w.se + row : nullptr, s->metric == KNNG_COSINE,
+                                 s->sub_ctr, s->sub_st));
         uint64_t h[C_WORDS];
         knng_status r = read_ctr(s->sub_ctr, h, s->sub_st);
         if (r != KNNG_OK)
