@@ -35,11 +35,12 @@ knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
     R.db = w.db;
     R.norm = w.norm;
     R.se = w.se;
+    R.se_stride = w.ws;
     R.n = n;
     R.d = d;
     R.dp = w.dp;
     if (w.norm || w.se)
-        HIP_TRY(launch_norms(w.x, n, w.dp, w.norm, w.se, metric == KNNG_COSINE, w.ctr,
+        HIP_TRY(launch_norms(w.x, n, w.dp, w.norm, w.se, w.ws, metric == KNNG_COSINE, w.ctr,
                              st));
     uint64_t h[C_WORDS];
     knng_status s = read_ctr(w.ctr, h, st);
@@ -153,6 +154,7 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     InitArgs ia;
     ia.L = w.L;
     ia.worst = w.worst;
+    ia.ws = w.ws;
     ia.dtag = w.dtag;
     ia.atag = w.atag;
     ia.balanced = balanced;
@@ -174,6 +176,7 @@ knng_status run_merge(const Rows &R, const Layout &w, knng_metric metric, bool b
     RoundArgs a;
     a.L = w.L;
     a.worst = w.worst;
+    a.ws = w.ws;
     a.new_f = w.new_f;
     a.old_f = w.old_f;
     a.cnt_f = w.cnt_f;

@@ -77,6 +77,9 @@ struct Layout {
     uint64_t *gin, *L, *worst, *rnew, *rold;
     int32_t *new_f, *old_f, *cnt_f, *dtag, *atag, *rfill;
     int dp, db, gstride;
+    // u64 words from one row's `worst` word to the next: 2 when each is
+    // followed by the row's `se` pair (merges on the BF16 path), else 1
+    int ws = 1;
     // reverse index of the base lists (server only; see RoundArgs)
     const int64_t *rev_off = nullptr;
     const int32_t *rev_src = nullptr;
@@ -116,10 +119,13 @@ inline void carve_merge(Carve &c, Layout &w, int64_t n, int64_t n_list, int d, i
     w.x = c.take<float>((size_t)n * w.dp);
     w.norm = m == KNNG_COSINE ? c.take<float>(n) : nullptr;
     w.xb = bf16 ? c.take<uint16_t>((size_t)n * w.db) : nullptr;
-    w.se = bf16 ? c.take<float2>(n) : nullptr;
     w.gin = c.take<uint64_t>((size_t)(n_list > 0 ? n_list : 1) * (gstride > 0 ? gstride : 1));
     w.L = c.take<uint64_t>((size_t)n * k);
-    w.worst = c.take<uint64_t>(n);
+    // BF16 path: a row's bound and its (norm, error bound) pair share one
+    // 16-byte record, which forming a neighbourhood reads per member
+    w.ws = bf16 ? 2 : 1;
+    w.worst = c.take<uint64_t>((size_t)n * w.ws);
+    w.se = bf16 ? reinterpret_cast<float2 *>(w.worst + 1) : nullptr;
     w.new_f = c.take<int32_t>((size_t)n * s);
     w.old_f = c.take<int32_t>((size_t)n * k);
     w.cnt_f = c.take<int32_t>((size_t)n * 2);

@@ -19,6 +19,7 @@ struct Rows {
     // BF16 path, per row: the squared norm of the bf16-rounded row and an
     // upper bound of |x - bf16(x)| (read together), or nullptr
     const float2 *se;
+    int se_stride = 1;  // float2 units from one row's pair to the next
     int64_t n;
     int d, dp, db;  // db: bf16 row stride, d rounded up to 32
     int64_t split = INT64_MAX, off2 = 0;
@@ -47,7 +48,9 @@ struct DevRound {
 struct RoundArgs {
     uint64_t *L;        // n x k list words
     uint64_t *worst;    // n: upper bound of each list's maximum word (set by the
-                        // sampling step, lowered by the join's inserts)
+                        // sampling step, lowered by the join's inserts), row u at
+                        // worst[u * ws]
+    int ws;
     int32_t *new_f;     // n x s
     int32_t *old_f;     // n x k
     int32_t *cnt_f;     // n x 2: (#new_f, #old_f)
@@ -130,7 +133,7 @@ __device__ inline bool take_round(RoundArgs &a, Rows &R)
 hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2, int d, int dp,
                        float *x, int db, uint16_t *xb, uint64_t *ctr, hipStream_t st);
 hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float2 *se_bf16,
-                        int check_zero, uint64_t *ctr, hipStream_t st);
+                        int se_stride, int check_zero, uint64_t *ctr, hipStream_t st);
 // Input graph rows [row0, row0+nrows) of the concatenated set: local ids +
 // offset -> sorted keys (kin per row) in `gin`.
 hipError_t launch_prep_input(const Rows &R, int metric, int64_t row0, int64_t nrows,
@@ -140,7 +143,8 @@ hipError_t launch_prep_input(const Rows &R, int metric, int64_t row0, int64_t nr
 // Divide + Append (rows with an input list) and Initialize (raw rows).
 struct InitArgs {
     uint64_t *L;
-    uint64_t *worst;    // n: maximum word of each list
+    uint64_t *worst;    // n: maximum word of each list, row u at worst[u * ws]
+    int ws;
     int32_t *dtag, *atag;
     const uint64_t *gin;
     int kin, k, k1;

@@ -262,7 +262,7 @@ __device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a,
             else if (slot >= g.offOB && slot < g.offOB + oB)
                 id = L.toldB[slot - g.offOB];
             L.grp[slot] = id;
-            L.gw[slot] = id >= 0 ? a.worst[id] : 0ull;
+            L.gw[slot] = id >= 0 ? a.worst[id * a.ws] : 0ull;
             if (METRIC == M_COS)
                 L.gnorm[slot] = id >= 0 ? R.norm[R.phys(id)] : 1.0f;
         }
@@ -289,9 +289,10 @@ __device__ inline bool build_group(int64_t u, const Rows &R, const RoundArgs &a,
     #pragma unroll
         for (int i = 0; i < NSL; i++) {
             const bool has = id[i] >= 0;
-            gw[i] = has ? a.worst[id[i]] : 0ull;
+            gw[i] = has ? a.worst[id[i] * a.ws] : 0ull;
             gn[i] = METRIC == M_COS && has ? R.norm[R.phys(id[i])] : 1.0f;
-            const float2 se = BF && has ? R.se[R.phys(id[i])] : make_float2(0.0f, 0.0f);
+            const float2 se =
+                BF && has ? R.se[R.phys(id[i]) * R.se_stride] : make_float2(0.0f, 0.0f);
             gq[i] = se.x;
             ge[i] = se.y;
         }
@@ -388,7 +389,7 @@ __device__ __forceinline__ void insert_into(const RoundArgs &a, int64_t dst, uin
 {
     // dst and the key's id are neighbourhood members, range-checked when the
     // neighbourhood was formed
-    if (bounded_insert<KB>(a.L + dst * a.k, a.k, key, DUP_ID, a.worst + dst, a.ctr + C_ERR))
+    if (bounded_insert<KB>(a.L + dst * a.k, a.k, key, DUP_ID, a.worst + dst * a.ws, a.ctr + C_ERR))
         a.dtag[dst] = a.tag0 + a.round + 1;
 }
 
@@ -465,7 +466,7 @@ __device__ __forceinline__ void insert_view(const RoundArgs &a, int64_t dst, uin
         atomicOr((unsigned long long *)(a.ctr + C_ERR), (unsigned long long)ERR_SPIN);
     if (any) {
         // every word of the view is at least its slot's current value
-        atomic_min_u64(a.worst + dst, key_strip(mx));
+        atomic_min_u64(a.worst + dst * a.ws, key_strip(mx));
         a.dtag[dst] = a.tag0 + a.round + 1;
     }
 }

@@ -47,7 +47,7 @@ __global__ void k_pack(const float *__restrict__ x1, int64_t n1, const float *__
 // (ascending fused accumulation) and an upper bound of |x - bf16(x)|
 // (accumulated in FP64, rounded up)
 __global__ void k_norms(const float *__restrict__ x, int64_t n, int dp, float *__restrict__ norm,
-                        float2 *__restrict__ se, int check_zero,
+                        float2 *__restrict__ se, int se_stride, int check_zero,
                         uint64_t *ctr)
 {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -95,7 +95,7 @@ __global__ void k_norms(const float *__restrict__ x, int64_t n, int dp, float *_
         // the canonical FP32 value bit for bit.
         if (integral && acc < 0x1p23f)
             e = -0.0f;
-        se[r] = make_float2(acc, e);
+        se[r * se_stride] = make_float2(acc, e);
     }
 }
 
@@ -133,11 +133,11 @@ __global__ __launch_bounds__(256) void k_prep_input(Rows R, int64_t row0, int64_
     // then share a distance, each summing half of the bf16 row
     float dsplit = 0.0f;
     bool split = false;
-    if (METRIC == M_L2 && !dist && R.se && kin <= WAVE / 2 && signbit(R.se[R.phys(r)].y)) {
+    if (METRIC == M_L2 && !dist && R.se && kin <= WAVE / 2 && signbit(R.se[R.phys(r) * R.se_stride].y)) {
         const int q = lane >> 1, part = lane & 1;
         const int64_t gq = __shfl(g, q, WAVE);
         const bool mine = q < kin && gq >= 0;
-        if (__ballot(mine && !signbit(R.se[R.phys(gq)].y)) == 0ull) {
+        if (__ballot(mine && !signbit(R.se[R.phys(gq) * R.se_stride].y)) == 0ull) {
             split = true;
             const int half = R.db / 2;  // a multiple of 16
             const uint16_t *xr = R.xb + R.phys(r) * R.db + part * half;
@@ -329,11 +329,11 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
     // four lanes then share a distance, each summing a quarter of the bf16 row
     float dsplit = 0.0f;
     bool split = false;
-    if (METRIC == M_L2 && R.se && m > 0 && m <= WAVE / 4 && signbit(R.se[R.phys(i)].y)) {
+    if (METRIC == M_L2 && R.se && m > 0 && m <= WAVE / 4 && signbit(R.se[R.phys(i) * R.se_stride].y)) {
         const int q = lane >> 2, part = lane & 3;
         const bool mine = q < m;
         const int64_t g = mine ? picked[q] + cand_off : i;
-        const bool cert = signbit(R.se[R.phys(g)].y);
+        const bool cert = signbit(R.se[R.phys(g) * R.se_stride].y);
         if (__ballot(mine && !cert) == 0ull) {
             split = true;
             const int per = R.db / 4;  // a multiple of 8
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
     // row is sampled in round 0 iff it holds a NEW entry
     const uint64_t wv = wave_max_u64(key_empty(key) ? key : key_strip(key));
     if (lane == 0) {
-        a.worst[i] = wv;
+        a.worst[i * a.ws] = wv;
         a.dtag[i] = m > 0 ? a.tag0 : a.tag0 - 1;
         a.atag[i] = a.tag0 - 1;
     }
@@ -705,10 +705,10 @@ hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2,
 }
 
 hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float2 *se_bf16,
-                        int check_zero, uint64_t *ctr, hipStream_t st)
+                        int se_stride, int check_zero, uint64_t *ctr, hipStream_t st)
 {
     hipLaunchKernelGGL(k_norms, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, dp, norm,
-                       se_bf16, check_zero, ctr);
+                       se_bf16, se_stride, check_zero, ctr);
     return hipGetLastError();
 }
 

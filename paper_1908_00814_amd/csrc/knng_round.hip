@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_sample(RoundArgs a)
             }
             fresh_total += wave_sum((int)fresh);
             if (u >= 0 && gl == 0) {
-                a.worst[u] = wv;
+                a.worst[u * a.ws] = wv;
                 a.cnt_f[2 * u] = nnew < a.s ? nnew : a.s;
                 a.cnt_f[2 * u + 1] = __popcll(om);
                 if (nnew > a.s)

@@ -637,7 +637,7 @@ static knng_status knng_server_submit_impl(knng_server *s, const float *raw, int
                             s->sub_ctr, s->sub_st));
         if (w.norm || w.se)
             HIP_TRY(launch_norms(w.x + row * w.dp, n_raw, w.dp, w.norm ? w.norm + row : nullptr,
-                                 w.se ? w.se + row : nullptr, s->metric == KNNG_COSINE,
+                                 w.se ? w.se + row : nullptr, 1, s->metric == KNNG_COSINE,
                                  s->sub_ctr, s->sub_st));
         uint64_t h[C_WORDS];
         knng_status r = read_ctr(s->sub_ctr, h, s->sub_st);
