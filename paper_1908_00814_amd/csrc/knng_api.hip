@@ -29,7 +29,8 @@ knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
     const int d = B->d;
     HIP_TRY(launch_zero_counters(w.ctr, C_WORDS, st));
     HIP_TRY(launch_pack(A->n ? A->x : nullptr, n1, B->x, n - n1, d, w.dp, w.x,
-                        bf16 ? w.db : 0, bf16 ? w.xb : nullptr, w.ctr, st));
+                        bf16 ? w.db : 0, bf16 ? w.xb : nullptr, bf16 ? w.se : nullptr, w.ws,
+                        w.ctr, st));
     R.x = w.x;
     R.xb = bf16 ? w.xb : nullptr;
     R.db = w.db;
@@ -39,9 +40,8 @@ knng_status prepare(const knng_set *A, const knng_graph *GA, const knng_set *B,
     R.n = n;
     R.d = d;
     R.dp = w.dp;
-    if (w.norm || w.se)
-        HIP_TRY(launch_norms(w.x, n, w.dp, w.norm, w.se, w.ws, metric == KNNG_COSINE, w.ctr,
-                             st));
+    if (w.norm)
+        HIP_TRY(launch_norms(w.x, n, w.dp, w.norm, metric == KNNG_COSINE, w.ctr, st));
     uint64_t h[C_WORDS];
     knng_status s = read_ctr(w.ctr, h, st);
     if (s != KNNG_OK)

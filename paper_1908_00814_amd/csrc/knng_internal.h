@@ -130,10 +130,13 @@ __device__ inline bool take_round(RoundArgs &a, Rows &R)
 }
 
 // ---- knng_prep.hip
+// se (BF16 path, or nullptr): per row the squared norm of the bf16-rounded row
+// and the bound of |x - bf16(x)|, at se[r * se_stride]
 hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2, int d, int dp,
-                       float *x, int db, uint16_t *xb, uint64_t *ctr, hipStream_t st);
-hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float2 *se_bf16,
-                        int se_stride, int check_zero, uint64_t *ctr, hipStream_t st);
+                       float *x, int db, uint16_t *xb, float2 *se, int se_stride, uint64_t *ctr,
+                       hipStream_t st);
+hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, int check_zero,
+                        uint64_t *ctr, hipStream_t st);
 // Input graph rows [row0, row0+nrows) of the concatenated set: local ids +
 // offset -> sorted keys (kin per row) in `gin`.
 hipError_t launch_prep_input(const Rows &R, int metric, int64_t row0, int64_t nrows,

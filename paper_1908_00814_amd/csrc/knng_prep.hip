@@ -11,92 +11,97 @@ namespace knng {
 
 namespace {
 
-// concatenate the two sets into one zero-padded fp32 array (and, for the
-// BF16 path, a zero-padded bf16 copy with rows of db elements)
-__global__ void k_pack(const float *__restrict__ x1, int64_t n1, const float *__restrict__ x2,
-                       int64_t n2, int d, int dp, float *__restrict__ x, int db,
-                       uint16_t *__restrict__ xb, uint64_t *ctr)
+// Concatenate the two sets into one zero-padded fp32 array and, for the BF16
+// path, a zero-padded bf16 copy with rows of db elements plus, per row
+// (se[r * se_stride]), the squared norm of the bf16-rounded row and an upper
+// bound of |x - bf16(x)|.  One wave per row at a time (rows wave-strided),
+// lane l taking coordinates l, l + 64, ...; the two per-row values are wave
+// sums.  A row whose coordinates are integers in [0, 256] and whose squared
+// norm is below 2^23 gets the exactness certificate (the bound -0.0): its
+// partial sums are integers below 2^24, so its squared norm is exact in any
+// order of summation.  For two certified rows p, q every partial dot product
+// is at most |p||q| < 2^23 and every canonical partial sum of (p_t - q_t)^2 at
+// most |p|^2 + |q|^2 < 2^24; all are integers, so the bf16 evaluation and the
+// canonical FP32 one are exact and equal bit for bit.  Other rows use the
+// norm only under the screen's margin, which bounds the rounding of any
+// order of summation (a sum of dp terms).
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ x1, int64_t n1,
+                                              const float *__restrict__ x2, int64_t n2, int d,
+                                              int dp, float *__restrict__ x, int db,
+                                              uint16_t *__restrict__ xb, float2 *__restrict__ se,
+                                              int se_stride, uint64_t *ctr)
 {
+    const int lane = lane_id();
     const int64_t n = n1 + n2;
     const int w = xb && db > dp ? db : dp;
-    const int64_t total = n * (int64_t)w;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     uint32_t bad = 0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / w;
-        const int c = (int)(e - r * w);
-        float v = 0.0f;
-        if (c < d) {
-            v = r < n1 ? x1[r * d + c] : x2[(r - n1) * d + c];
-            if (!isfinite(v)) {
-                bad = 1;
-                v = 0.0f;
+    for (int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE; r < n;
+         r += nwaves) {
+        const float *src = r < n1 ? x1 + r * d : x2 + (r - n1) * d;
+        float acc = 0.0f;
+        double e2 = 0.0;
+        bool integral = true;  // every coordinate an integer in [0, 256]
+        for (int c = lane; c < w; c += WAVE) {
+            float v = 0.0f;
+            if (c < d) {
+                v = src[c];
+                if (!isfinite(v)) {
+                    bad = 1;
+                    v = 0.0f;
+                }
+            }
+            if (c < dp)
+                x[r * dp + c] = v;
+            if (xb && c < db) {
+                const uint16_t h = f32_to_bf16(v);
+                xb[r * db + c] = h;
+                const float b = bf16_to_f32(h);
+                acc = __builtin_fmaf(b, b, acc);
+                const double dd = (double)v - (double)b;
+                e2 += dd * dd;
+                integral = integral && v == rintf(v) && v >= 0.0f && v <= 256.0f;
             }
         }
-        if (c < dp)
-            x[r * dp + c] = v;
-        if (xb && c < db)
-            xb[r * db + c] = f32_to_bf16(v);
+        if (se) {
+            for (int o = WAVE / 2; o > 0; o >>= 1) {
+                acc += __shfl_xor(acc, o, WAVE);
+                e2 += __shfl_xor(e2, o, WAVE);
+            }
+            const bool cert = __ballot(!integral) == 0ull && acc < 0x1p23f;
+            if (lane == 0) {
+                // the FP64 sum of exact squares is within (dp * 2^-53)
+                // relative; inflate it and the sqrt so the fp32 value is an
+                // upper bound
+                float e = __double2float_ru(__builtin_sqrt(e2 * (1.0 + 0x1p-36)) * (1.0 + 0x1p-50));
+                se[r * se_stride] = make_float2(acc, cert ? -0.0f : e);
+            }
+        }
     }
     if (bad)
         atomicOr((unsigned long long *)(ctr + C_ERR), (unsigned long long)ERR_NONFINITE);
 }
 
-// canonical norms (ascending fused accumulation, correctly rounded sqrt) and,
-// for the BF16 path, per row: the squared norm of the bf16-rounded row
-// (ascending fused accumulation) and an upper bound of |x - bf16(x)|
-// (accumulated in FP64, rounded up)
+// canonical norms (ascending fused accumulation, correctly rounded sqrt)
 __global__ void k_norms(const float *__restrict__ x, int64_t n, int dp, float *__restrict__ norm,
-                        float2 *__restrict__ se, int se_stride, int check_zero,
-                        uint64_t *ctr)
+                        int check_zero, uint64_t *ctr)
 {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= n)
         return;
     const float4 *p = reinterpret_cast<const float4 *>(x + r * dp);
-    if (norm) {
-        float acc = 0.0f;
-        for (int t = 0; t < dp / 4; t++) {
-            float4 v = p[t];
-            acc = __builtin_fmaf(v.x, v.x, acc);
-            acc = __builtin_fmaf(v.y, v.y, acc);
-            acc = __builtin_fmaf(v.z, v.z, acc);
-            acc = __builtin_fmaf(v.w, v.w, acc);
-        }
-        float nr = __builtin_sqrtf(acc);  // correctly rounded (see build flags)
-        norm[r] = nr;
-        if (check_zero && !(nr > 0.0f))
-            atomicOr((unsigned long long *)(ctr + C_ERR), (unsigned long long)ERR_ZERO_NORM);
+    float acc = 0.0f;
+    for (int t = 0; t < dp / 4; t++) {
+        float4 v = p[t];
+        acc = __builtin_fmaf(v.x, v.x, acc);
+        acc = __builtin_fmaf(v.y, v.y, acc);
+        acc = __builtin_fmaf(v.z, v.z, acc);
+        acc = __builtin_fmaf(v.w, v.w, acc);
     }
-    if (se) {
-        float acc = 0.0f;
-        double e2 = 0.0;
-        bool integral = true;  // every coordinate an integer in [0, 256]
-        for (int t = 0; t < dp / 4; t++) {
-            float4 v = p[t];
-            float vs[4] = {v.x, v.y, v.z, v.w};
-            for (int j = 0; j < 4; j++) {
-                float b = bf16_to_f32(f32_to_bf16(vs[j]));
-                acc = __builtin_fmaf(b, b, acc);
-                double dd = (double)vs[j] - (double)b;
-                e2 += dd * dd;
-                integral = integral && vs[j] == rintf(vs[j]) && vs[j] >= 0.0f && vs[j] <= 256.0f;
-            }
-        }
-        // the FP64 sum of exact squares is within (dp * 2^-53) relative;
-        // inflate it and the sqrt so the fp32 value is an upper bound
-        float e = __double2float_ru(__builtin_sqrt(e2 * (1.0 + 0x1p-36)) * (1.0 + 0x1p-50));
-        // Exactness certificate, stored as the sign of the bound: coordinates
-        // are integers in [0, 256] (bf16-exact) and |x|^2 < 2^23.  For two
-        // certified rows p, q: every partial dot product is at most
-        // |p||q| < 2^23, |p|^2 + |q|^2 < 2^24, and (p_t - q_t)^2 <= p_t^2 + q_t^2
-        // bounds every canonical partial sum by |p|^2 + |q|^2 < 2^24; all are
-        // integers, so both evaluations are exact and the bf16 distance equals
-        // the canonical FP32 value bit for bit.
-        if (integral && acc < 0x1p23f)
-            e = -0.0f;
-        se[r * se_stride] = make_float2(acc, e);
-    }
+    float nr = __builtin_sqrtf(acc);  // correctly rounded (see build flags)
+    norm[r] = nr;
+    if (check_zero && !(nr > 0.0f))
+        atomicOr((unsigned long long *)(ctr + C_ERR), (unsigned long long)ERR_ZERO_NORM);
 }
 
 // one wave per input row: local ids -> global keys, validated, sorted
@@ -412,10 +417,13 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
         atomicAdd((unsigned long long *)(a.ctr + C_N0), (unsigned long long)n0);
 }
 
-// top k of row i's list and its rear part, deduplicated (one wave; cand and
-// kept are the wave's 2 x 64 words of LDS)
-__device__ inline void final_row(const FinalArgs &a, const int64_t i, uint64_t *cand,
-                                 uint64_t *kept)
+// top k of row i's list and its rear part, deduplicated, by a group of G
+// lanes (G = 64: one row per wave, G = 32: two); cand and kept are the
+// group's 2 x G words of LDS; live: the row exists (a group past the last row
+// takes part in the group sum only)
+template <int G>
+__device__ inline void final_row(const FinalArgs &a, const int64_t i, const bool live,
+                                 uint64_t *cand, uint64_t *kept)
 {
     const uint64_t *__restrict__ L = a.L;
     const uint64_t *gin = a.gin;
@@ -423,24 +431,24 @@ __device__ inline void final_row(const FinalArgs &a, const int64_t i, uint64_t *
     int32_t *out_ids = a.out_ids;
     float *out_dist = a.out_dist;
     uint64_t *out_keys = a.out_keys;  // may alias gin: row i is read before it is written
-    const int lane = lane_id();
+    const int lane = lane_id() % G;
     __builtin_amdgcn_wave_barrier();  // the previous row's reads of cand / kept are done
     int rear0 = a.k1;
     if (!selected_base_row(a.seed, a.balanced, i, a.rows_with_rear, a.n_raw))
         rear0 = kin < k ? kin : k;
-    const int nrear = i < a.rows_with_rear ? kin - rear0 : 0;
-    uint64_t c0 = lane < k ? key_strip(L[i * k + lane]) : ~0ull;
+    const int nrear = live && i < a.rows_with_rear ? kin - rear0 : 0;
+    uint64_t c0 = live && lane < k ? key_strip(L[i * k + lane]) : ~0ull;
     uint64_t c1 = lane < nrear ? key_strip(gin[i * kin + rear0 + lane]) : ~0ull;
     if (key_empty(c0))
         c0 = ~0ull;
     if (key_empty(c1))
         c1 = ~0ull;  // padding of rows shorter than the row stride
     cand[lane] = c0;
-    cand[WAVE + lane] = c1;
+    cand[G + lane] = c1;
     __builtin_amdgcn_wave_barrier();
     // keep the first occurrence of each entry (only slots [0, k) and
-    // [WAVE, WAVE + nrear) hold candidates; the rest hold ~0, which matches
-    // and outranks nothing)
+    // [G, G + nrear) hold candidates; the rest hold ~0, which matches and
+    // outranks nothing)
     bool v0 = c0 != ~0ull, v1 = c1 != ~0ull;
     for (int j = 0; j < k; j++) {
         const uint64_t o = cand[j];
@@ -449,13 +457,13 @@ __device__ inline void final_row(const FinalArgs &a, const int64_t i, uint64_t *
         if (o == c1)
             v1 = false;
     }
-    for (int j = WAVE; j < WAVE + nrear; j++) {
+    for (int j = G; j < G + nrear; j++) {
         const uint64_t o = cand[j];
-        if (o == c1 && j < WAVE + lane)
+        if (o == c1 && j < G + lane)
             v1 = false;
     }
     kept[lane] = v0 ? c0 : ~0ull;
-    kept[WAVE + lane] = v1 ? c1 : ~0ull;
+    kept[G + lane] = v1 ? c1 : ~0ull;
     __builtin_amdgcn_wave_barrier();
     int r0 = 0, r1 = 0;
     for (int j = 0; j < k; j++) {
@@ -463,12 +471,16 @@ __device__ inline void final_row(const FinalArgs &a, const int64_t i, uint64_t *
         r0 += o < c0;
         r1 += o < c1;
     }
-    for (int j = WAVE; j < WAVE + nrear; j++) {
+    for (int j = G; j < G + nrear; j++) {
         const uint64_t o = kept[j];
         r0 += o < c0;
         r1 += o < c1;
     }
-    int nvalid = wave_sum((int)v0 + (int)v1);
+    int nvalid = (int)v0 + (int)v1;
+    for (int o = G / 2; o > 0; o >>= 1)
+        nvalid += __shfl_xor(nvalid, o, WAVE);
+    if (!live)
+        return;
     if (out_ids) {
         if (v0 && r0 < k) {
             out_ids[i * k + r0] = (int32_t)key_id(c0);
@@ -494,26 +506,30 @@ __device__ inline void final_row(const FinalArgs &a, const int64_t i, uint64_t *
     }
 }
 
-// one wave per row; with a.touched, a wave-strided walk over the rows that
-// held a NEW entry and the rows without a rear part
+// G = 64: one wave per row, or with a.touched a wave-strided walk over the
+// rows that held a NEW entry and the rows without a rear part; G = 32: two
+// rows per wave, for lists and kept input entries of at most 32 each
+template <int G>
 __global__ __launch_bounds__(256) void k_final(FinalArgs a)
 {
     __shared__ uint64_t cand_all[4][2 * WAVE];
     __shared__ uint64_t kept_all[4][2 * WAVE];
     const int w = threadIdx.x / WAVE;
-    uint64_t *cand = cand_all[w];
-    uint64_t *kept = kept_all[w];
-    if (a.touched) {
-        const int32_t *touched = a.touched;
-        FOR_ROWS_IF(i, a.n, [&](int64_t r) {
-            return r >= a.rows_with_rear || touched[r] >= a.tag0;
-        })
-        final_row(a, i, cand, kept);
-        return;
+    const int g = (threadIdx.x % WAVE) / G;
+    uint64_t *cand = cand_all[w] + g * 2 * G;
+    uint64_t *kept = kept_all[w] + g * 2 * G;
+    if constexpr (G == WAVE) {
+        if (a.touched) {
+            const int32_t *touched = a.touched;
+            FOR_ROWS_IF(i, a.n, [&](int64_t r) {
+                return r >= a.rows_with_rear || touched[r] >= a.tag0;
+            })
+            final_row<WAVE>(a, i, true, cand, kept);
+            return;
+        }
     }
-    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
-    if (i < a.n)
-        final_row(a, i, cand, kept);
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE * (WAVE / G) + g;
+    final_row<G>(a, i, i < a.n, cand, kept);
 }
 
 // commit of row i of one request into the resident lists (one wave)
@@ -693,22 +709,23 @@ inline unsigned grid_for(int64_t items, int per_block)
 } // namespace
 
 hipError_t launch_pack(const float *x1, int64_t n1, const float *x2, int64_t n2, int d, int dp,
-                       float *x, int db, uint16_t *xb, uint64_t *ctr, hipStream_t st)
+                       float *x, int db, uint16_t *xb, float2 *se, int se_stride, uint64_t *ctr,
+                       hipStream_t st)
 {
-    const int64_t total = (n1 + n2) * (int64_t)(xb && db > dp ? db : dp);
-    unsigned grid = grid_for(total, 256);
-    if (grid > 65536u)
-        grid = 65536u;
-    hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, x1, n1, x2, n2, d, dp, x, db, xb,
-                       ctr);
+    // at most 2,048 blocks of 4 waves, each wave walking rows
+    unsigned g = grid_for(n1 + n2, 4);
+    if (g > 2048u)
+        g = 2048u;
+    hipLaunchKernelGGL(k_pack, dim3(g), dim3(256), 0, st, x1, n1, x2, n2, d, dp, x, db, xb, se,
+                       se_stride, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, float2 *se_bf16,
-                        int se_stride, int check_zero, uint64_t *ctr, hipStream_t st)
+hipError_t launch_norms(const float *x, int64_t n, int dp, float *norm, int check_zero,
+                        uint64_t *ctr, hipStream_t st)
 {
     hipLaunchKernelGGL(k_norms, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, dp, norm,
-                       se_bf16, se_stride, check_zero, ctr);
+                       check_zero, ctr);
     return hipGetLastError();
 }
 
@@ -747,10 +764,14 @@ hipError_t launch_init(const Rows &R, int metric, const InitArgs &a, hipStream_t
 
 hipError_t launch_final(const FinalArgs &a, hipStream_t st)
 {
+    if (!a.touched && a.k <= 32 && a.kin <= 32) {
+        hipLaunchKernelGGL(k_final<32>, dim3(grid_for(a.n, 8)), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
     unsigned g = grid_for(a.n, 4);
     if (a.touched && g > 8192u)
         g = 8192u;
-    hipLaunchKernelGGL(k_final, dim3(g), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_final<WAVE>, dim3(g), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -714,9 +714,10 @@ static knng_status knng_search_impl(const knng_set *X, const knng_graph *layers,
     if (s != KNNG_OK)
         return s;
     if (nq > 0) {
-        HIP_TRY(launch_pack(nullptr, 0, Q->x, nq, Q->d, w.dp, qx, 0, nullptr, w.ctr, st));
+        HIP_TRY(launch_pack(nullptr, 0, Q->x, nq, Q->d, w.dp, qx, 0, nullptr, nullptr, 1, w.ctr,
+                            st));
         if (qn)
-            HIP_TRY(launch_norms(qx, nq, w.dp, qn, nullptr, 1, 1, w.ctr, st));
+            HIP_TRY(launch_norms(qx, nq, w.dp, qn, 1, w.ctr, st));
         const size_t lds = search_lds_per_wave(w.dp) * SW;
         const unsigned grid = grid_of(nq, SW, 8192);
         auto go = [&](auto kern) -> hipError_t {

@@ -634,11 +634,10 @@ static knng_status knng_server_submit_impl(knng_server *s, const float *raw, int
         HIP_TRY(launch_zero_counters(s->sub_ctr, C_WORDS, s->sub_st));
         HIP_TRY(launch_pack(nullptr, 0, src, n_raw, s->d, w.dp, w.x + row * w.dp,
                             s->bf16 ? w.db : 0, s->bf16 ? w.xb + row * w.db : nullptr,
-                            s->sub_ctr, s->sub_st));
-        if (w.norm || w.se)
-            HIP_TRY(launch_norms(w.x + row * w.dp, n_raw, w.dp, w.norm ? w.norm + row : nullptr,
-                                 w.se ? w.se + row : nullptr, 1, s->metric == KNNG_COSINE,
-                                 s->sub_ctr, s->sub_st));
+                            s->bf16 ? w.se + row : nullptr, 1, s->sub_ctr, s->sub_st));
+        if (w.norm)
+            HIP_TRY(launch_norms(w.x + row * w.dp, n_raw, w.dp, w.norm + row,
+                                 s->metric == KNNG_COSINE, s->sub_ctr, s->sub_st));
         uint64_t h[C_WORDS];
         knng_status r = read_ctr(s->sub_ctr, h, s->sub_st);
         if (r != KNNG_OK)
