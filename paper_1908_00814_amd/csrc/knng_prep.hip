@@ -138,7 +138,8 @@ __global__ __launch_bounds__(256) void k_prep_input(Rows R, int64_t row0, int64_
     // then share a distance, each summing half of the bf16 row
     float dsplit = 0.0f;
     bool split = false;
-    if (METRIC == M_L2 && !dist && R.se && kin <= WAVE / 2 && signbit(R.se[R.phys(r) * R.se_stride].y)) {
+    if (METRIC == M_L2 && !dist && R.se && kin <= WAVE / 2 &&
+        signbit(R.se[R.phys(r) * R.se_stride].y)) {
         const int q = lane >> 1, part = lane & 1;
         const int64_t gq = __shfl(g, q, WAVE);
         const bool mine = q < kin && gq >= 0;
@@ -334,7 +335,8 @@ __global__ __launch_bounds__(256) void k_init(Rows R, InitArgs a)
     // four lanes then share a distance, each summing a quarter of the bf16 row
     float dsplit = 0.0f;
     bool split = false;
-    if (METRIC == M_L2 && R.se && m > 0 && m <= WAVE / 4 && signbit(R.se[R.phys(i) * R.se_stride].y)) {
+    if (METRIC == M_L2 && R.se && m > 0 && m <= WAVE / 4 &&
+        signbit(R.se[R.phys(i) * R.se_stride].y)) {
         const int q = lane >> 2, part = lane & 3;
         const bool mine = q < m;
         const int64_t g = mine ? picked[q] + cand_off : i;
