@@ -496,7 +496,7 @@ static knng_status knng_server_create_impl(const knng_set *base, const knng_grap
         return rc;
     if (cfg->capacity < m || cfg->capacity >= (1ll << 30) - 64)
         return fail(KNNG_EINVAL,
-                    "capacity %lld must hold the base (%lld rows) and stay below 2^30",
+                    "capacity %lld must hold the base (%lld rows) and stay below 2^30 - 64",
                     (long long)cfg->capacity, (long long)m);
     if (cfg->max_request < 1)
         return fail(KNNG_EINVAL, "max_request must be >= 1");
